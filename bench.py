@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Benchmark: multi-rhs Wilson-Dirac apply on one MI355X.
+
+Timed step: one application of the full Wilson-Dirac operator D_W to a block
+of nrhs = 16 FP64 spinor fields on a 32^3 x 64 lattice (near-identity SU(3)
+links U = exp(i 0.3 H), m0 = -0.05, rhs-innermost layout), inputs resident in
+HBM.  Reported value: nominal GFLOP/s (1392 flop per site and rhs).  The JSON
+line also carries the roofline of the kernel (algorithmic HBM bytes
+(36 + 24 nrhs) x 16 per site over the measured launch time), an nrhs sweep in
+FP64/FP32/FP16 for the full and the Schur (odd-even) apply, and the oracle's
+CPU throughput on one rhs.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-sweep] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+DIMS = (64, 32, 32, 32)
+NRHS = 16
+M0 = -0.05
+EPS = 0.3
+CONFIG = 3
+FLOP_SITE_RHS = 1392          # 1320 projected hopping + 72 diagonal/combine
+SCHUR_FLOP_SITE_RHS = 2712    # per even site: two hopping passes + axpy
+HBM_PEAK_GBS = 8000.0
+
+
+def bytes_full(v, nrhs, esz):
+    """Algorithmic bytes of one full apply: every link, input and output element once."""
+    return (36 + 24 * nrhs) * esz * v
+
+
+def bytes_schur_two_pass(v, nrhs, esz):
+    """Two hopping passes over half lattices: links twice, in/tmp/out spinors."""
+    return (2 * 36 + 60 * nrhs) * esz * (v // 2)
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def timed(fn, steps, warmup):
+    import torch
+
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        fn()
+    stop.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / steps  # ms per call
+
+
+def tile_rhs(base, nrhs):
+    """Block of nrhs rhs (LAYOUT2) built by repeating the generated rhs."""
+    import torch
+
+    reps = (nrhs + base.shape[-1] - 1) // base.shape[-1]
+    return base.repeat(*([1] * (base.dim() - 1)), reps)[..., :nrhs].contiguous()
+
+
+def to_f16(t):
+    import torch
+
+    return torch.view_as_real(t.to(torch.complex64)).to(torch.float16).contiguous()
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--fast-inputs", action="store_true",
+                    help="draw the inputs on the GPU (seeded torch generator) instead of the seeded host "
+                         "recipe; for profiling runs, where values do not matter")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 2 GiB device copy (for scaling HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the multi-rhs apply and GMRES are single-device here "
+              "(rhs or lattice sharding across GPUs is not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import lqcd_synth as syn
+    import paper_2601_05816_amd as lq
+
+    lq.load()
+    dev = torch.device("cuda:0")
+    v = int(np.prod(DIMS))
+    t0 = time.time()
+    if args.fast_inputs:
+        gen = torch.Generator(device=dev).manual_seed(CONFIG)
+        U64 = torch.randn((4,) + DIMS + (3, 3), dtype=torch.complex128, device=dev, generator=gen)
+        psi64 = torch.randn(DIMS + (4, 3, NRHS), dtype=torch.complex128, device=dev, generator=gen)
+        U = psi_np = None
+        args.no_cpu = True
+    else:
+        U = syn.gauge_field(DIMS, "near_identity", config=CONFIG, eps=EPS)
+        log(f"gauge field generated ({time.time() - t0:.1f}s)")
+        psi_np = syn.spinor_block(DIMS, NRHS, config=CONFIG)
+        log(f"spinors generated ({time.time() - t0:.1f}s)")
+        U64 = torch.from_numpy(U).to(dev)
+        psi64 = torch.from_numpy(np.ascontiguousarray(np.moveaxis(psi_np, 0, -1))).to(dev)
+    eta64 = torch.empty_like(psi64)
+    torch.cuda.synchronize()
+    log("inputs resident on the GPU")
+
+    # ---------------------------------------------------------------- headline
+    def step():
+        lq.dirac_apply(U64, psi64, M0, layout=lq.LAYOUT2, out=eta64)
+
+    ms = timed(step, args.steps, args.warmup)
+    gflops = FLOP_SITE_RHS * v * NRHS / (ms * 1e-3) / 1e9
+    alg_bytes = bytes_full(v, NRHS, 16)
+    achieved = alg_bytes / (ms * 1e-3) / 1e9
+    log(f"D_W FP64 nrhs={NRHS}: {ms:.3f} ms, {gflops:.0f} GFLOP/s, {achieved:.0f} GB/s algorithmic")
+
+    result = {
+        "metric": "D_W mrhs apply GFLOP/s & HBM GB/s vs nrhs; mixed vs FP64 GMRES time-to-1e-10",
+        "value": round(gflops, 1),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic: seeded near-identity SU(3) links exp(i 0.3 H), Gaussian spinors",
+        "config": {"workload": "wilson_dirac_apply_32x32x32x64_nrhs16_f64", "lattice": list(DIMS),
+                   "nrhs": NRHS, "m0": M0, "layout": "rhs-innermost [site][12][nrhs]",
+                   "flop_per_site_rhs": FLOP_SITE_RHS},
+        "hbm_gbs_algorithmic": round(achieved, 1),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+    }
+
+    if args.copy_calibration:
+        n = (2 << 30) // 16
+        src = torch.ones(n, dtype=torch.complex128, device=dev)
+        dst = torch.empty_like(src)
+        t_copy = timed(lambda: dst.copy_(src), 3, 1)
+        result["copy_calibration"] = {"bytes_read": n * 16, "bytes_written": n * 16, "ms": round(t_copy, 4),
+                                      "gbs_read_plus_write": round(2 * n * 16 / t_copy / 1e6, 1)}
+        log(f"copy calibration: {t_copy:.3f} ms for 2 GiB")
+        del src, dst
+
+    # ------------------------------------------------------------------ sweep
+    if not args.no_sweep:
+        sweep = []
+        half = v // 2
+        for prec_name, prec in (("f64", lq.F64), ("f32", lq.F32), ("f16", lq.F16)):
+            Up = U64 if prec == lq.F64 else (U64.to(torch.complex64) if prec == lq.F32 else to_f16(U64))
+            esz = {lq.F64: 16, lq.F32: 8, lq.F16: 4}[prec]
+            for n in (1, 4, 8, 16, 32, 64):
+                base = tile_rhs(psi64, n)
+                x = base if prec == lq.F64 else (base.to(torch.complex64) if prec == lq.F32 else to_f16(base))
+                y = torch.empty_like(x)
+                steps = max(5, args.steps // 5)
+                t_full = timed(lambda: lq.dirac_apply(Up, x, M0, layout=lq.LAYOUT2, out=y), steps, 2)
+                # a half-lattice block of the same rhs count (values do not affect timing)
+                xe = x.reshape((v,) + tuple(x.shape[4:]))[:half].contiguous()
+                ye = torch.empty_like(xe)
+                t_eo = timed(lambda: lq.dirac_apply_eo(Up, xe, M0, layout=lq.LAYOUT2, out=ye), steps, 2)
+                rec = {"prec": prec_name, "nrhs": n,
+                       "full_ms": round(t_full, 4),
+                       "full_gflops": round(FLOP_SITE_RHS * v * n / t_full / 1e6, 1),
+                       "full_gbs": round(bytes_full(v, n, esz) / t_full / 1e6, 1),
+                       "schur_ms": round(t_eo, 4),
+                       "schur_gflops": round(SCHUR_FLOP_SITE_RHS * half * n / t_eo / 1e6, 1),
+                       "schur_gbs_two_pass": round(bytes_schur_two_pass(v, n, esz) / t_eo / 1e6, 1)}
+                rec["full_frac_hbm"] = round(rec["full_gbs"] / HBM_PEAK_GBS, 3)
+                log(json.dumps(rec))
+                sweep.append(rec)
+                del x, y, xe, ye, base
+            del Up
+            torch.cuda.empty_cache()
+        result["sweep"] = sweep
+
+    # ------------------------------------------------------- oracle baseline
+    if not args.no_cpu:
+        from oracle import dirac
+
+        t = time.time()
+        dirac.apply_dw(U, psi_np[:1], M0)
+        dt = time.time() - t
+        result["cpu_baseline"] = {
+            "value": round(FLOP_SITE_RHS * v / dt / 1e9, 3), "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+            "sample": f"one rhs of the same 32^3x64 apply (complex128 NumPy, single-threaded einsum), {dt:.1f} s",
+            "host_cpus": os.cpu_count()}
+        log(f"oracle: {dt:.1f} s for one rhs")
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -85,3 +85,26 @@ def dense(U: np.ndarray, m0: float) -> np.ndarray:
     eye = np.eye(n, dtype=np.complex128).reshape((n,) + tuple(dims) + (4, 3))
     cols = apply_dw(U, eye, m0).reshape(n, n)
     return cols.T.copy()
+
+
+def apply_dw_sites(U: np.ndarray, psi: np.ndarray, m0: float, sites) -> np.ndarray:
+    """(D_W psi) at the listed site numbers only, evaluated one site at a time
+    from the definition (for checking a full-size result on a sample).
+    Returns (nrhs, len(sites), 4, 3)."""
+    dims = U.shape[1:5]
+    g = gammas()
+    one = np.eye(4, dtype=np.complex128)
+    out = np.empty((psi.shape[0], len(sites), 4, 3), dtype=np.complex128)
+    for k, s in enumerate(sites):
+        x = np.array(np.unravel_index(int(s), dims))
+        acc = (4.0 + m0) * psi[(slice(None),) + tuple(x)].astype(np.complex128)
+        for mu in range(4):
+            xp = x.copy(); xp[mu] = (xp[mu] + 1) % dims[mu]
+            xm = x.copy(); xm[mu] = (xm[mu] - 1) % dims[mu]
+            uf = U[(mu,) + tuple(x)]
+            ub = U[(mu,) + tuple(xm)]
+            fwd = np.einsum("ab,nsb->nsa", uf, psi[(slice(None),) + tuple(xp)])
+            bwd = np.einsum("ba,nsb->nsa", np.conj(ub), psi[(slice(None),) + tuple(xm)])
+            acc = acc - 0.5 * (np.einsum("st,nta->nsa", one - g[mu], fwd) + np.einsum("st,nta->nsa", one + g[mu], bwd))
+        out[:, k] = acc
+    return out

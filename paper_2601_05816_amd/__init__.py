@@ -1,0 +1,244 @@
+"""Multi-rhs Wilson-Dirac operator and batched GMRES on AMD MI355X.
+
+Thin Python binding over the C-ABI of liblqcd.so (declared in include/lqcd.h).
+Torch tensors provide device memory and the current HIP stream; every
+computation happens in the library's HIP kernels.  The binding only checks
+shapes, marshals pointers and forwards status codes as exceptions.
+
+Tensor shapes (lattice dims (N0, N1, N2, N3), N0 = time):
+  U                      complex[4, N0, N1, N2, N3, 3, 3]
+  block, RHS_OUTER       complex[nrhs, N0, N1, N2, N3, 4, 3]
+  block, LAYOUT1         complex[N0, N1, N2, N3, nrhs, 4, 3]
+  block, LAYOUT2         complex[N0, N1, N2, N3, 4, 3, nrhs]
+  half-lattice blocks    the four lattice axes replaced by one axis of V/2 sites
+complex128 selects FP64, complex64 FP32; FP16 storage uses float16 tensors
+with a trailing axis of 2 (re, im).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+F64, F32, F16 = 0, 1, 2
+RHS_OUTER, LAYOUT1, LAYOUT2 = 0, 1, 2
+DAGGER = 1
+OK, NOT_CONVERGED = 0, 1
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblqcd.so")
+_lib = None
+
+
+class LqcdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"lqcd error {code}: {msg}")
+        self.code = code
+
+
+class Lattice(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int32 * 4)]
+
+
+class SolverParams(ctypes.Structure):
+    _fields_ = [("restart", ctypes.c_int32), ("max_restarts", ctypes.c_int32), ("eo", ctypes.c_int32),
+                ("mode", ctypes.c_int32), ("x_is_guess", ctypes.c_int32), ("fixed_iters", ctypes.c_int32),
+                ("tol", ctypes.c_double), ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class RhsStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("restarts", ctypes.c_int32), ("outer_iters", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("true_relres", ctypes.c_double), ("est_relres", ctypes.c_double)]
+
+
+def load():
+    """Load liblqcd.so.  Raises if it has not been built: there is no fallback."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing; build it with `python -m paper_2601_05816_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    lp = ctypes.POINTER(Lattice)
+    lib.lqcd_last_error.restype = ctypes.c_char_p
+    lib.lqcd_lattice_tables.argtypes = [lp, vp, vp]
+    lib.dirac_apply.argtypes = [lp, vp, vp, vp, i32, dbl, i32, i32, i32, vp]
+    lib.dirac_apply_eo.argtypes = [lp, vp, vp, vp, i32, dbl, i32, i32, i32, vp]
+    lib.lqcd_set_kernel_variant.argtypes = [i32, vp]
+    for name in ("lqcd_lattice_tables", "dirac_apply", "dirac_apply_eo", "lqcd_set_kernel_variant"):
+        getattr(lib, name).restype = i32
+    if hasattr(lib, "gmres_solve"):
+        lib.lqcd_solver_defaults.argtypes = [ctypes.POINTER(SolverParams)]
+        lib.lqcd_solver_defaults.restype = None
+        lib.gmres_workspace_bytes.argtypes = [lp, i32, ctypes.POINTER(SolverParams)]
+        lib.gmres_workspace_bytes.restype = ctypes.c_size_t
+        lib.gmres_solve.argtypes = [lp, vp, vp, vp, i32, dbl, i32, ctypes.POINTER(SolverParams), vp,
+                                    ctypes.c_size_t, ctypes.POINTER(RhsStats), vp]
+        lib.gmres_solve.restype = i32
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc < 0:
+        raise LqcdError(rc, load().lqcd_last_error().decode())
+    return rc
+
+
+def _lattice(dims):
+    lat = Lattice()
+    for i in range(4):
+        lat.dims[i] = int(dims[i])
+    return lat
+
+
+def lattice_tables(dims):
+    """(nbr[V, 8], eo_site[2, V/2]) as int32 numpy arrays, computed by the library."""
+    v = int(np.prod(dims))
+    nbr = np.empty((v, 8), dtype=np.int32)
+    eo = np.empty((2, v // 2), dtype=np.int32)
+    _check(load().lqcd_lattice_tables(ctypes.byref(_lattice(dims)), nbr.ctypes.data, eo.ctypes.data))
+    return nbr, eo
+
+
+def set_kernel_variant(variant=0, pencil=None):
+    """Wilson kernel choice: 0 automatic, 1 one site per work item, 2 pencils;
+    pencil = (tile Y, tile Z, t segments) with 0 = automatic."""
+    arr = None
+    if pencil is not None:
+        arr = (ctypes.c_int32 * 3)(*[int(v) for v in pencil])
+    _check(load().lqcd_set_kernel_variant(int(variant), arr))
+
+
+# ------------------------------------------------------------- tensors
+def _prec_of(t):
+    import torch
+
+    if t.dtype == torch.complex128:
+        return F64
+    if t.dtype == torch.complex64:
+        return F32
+    if t.dtype == torch.float16 and t.shape[-1] == 2:
+        return F16
+    raise TypeError(f"unsupported dtype {t.dtype} (complex128, complex64, or float16[..., 2])")
+
+
+def _core_shape(t, prec):
+    return tuple(t.shape[:-1]) if prec == F16 else tuple(t.shape)
+
+
+def _dims_of_links(U, prec):
+    s = _core_shape(U, prec)
+    if len(s) != 7 or s[0] != 4 or s[5:] != (3, 3):
+        raise ValueError(f"gauge field must be [4, N0, N1, N2, N3, 3, 3], got {s}")
+    return s[1:5]
+
+
+def _nrhs_of(t, prec, layout, nsite_axes):
+    s = _core_shape(t, prec)
+    if layout == RHS_OUTER:
+        return s[0], s[1:1 + nsite_axes]
+    if layout == LAYOUT1:
+        return s[nsite_axes], s[:nsite_axes]
+    if layout == LAYOUT2:
+        return s[-1], s[:nsite_axes]
+    raise ValueError(f"unknown layout {layout}")
+
+
+def _check_device(*ts):
+    for t in ts:
+        if not t.is_cuda:
+            raise ValueError("all tensors must live on the GPU")
+        if not t.is_contiguous():
+            raise ValueError("tensors must be contiguous")
+
+
+def _stream():
+    import torch
+
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def dirac_apply(U, psi, m0, layout=LAYOUT2, dagger=False, out=None):
+    """eta = D psi (or D^dagger psi) for every rhs of a full-lattice block."""
+    import torch
+
+    prec = _prec_of(psi)
+    if _prec_of(U) != prec:
+        raise TypeError("U and psi must have the same precision")
+    dims = _dims_of_links(U, prec)
+    nrhs, sdims = _nrhs_of(psi, prec, layout, 4)
+    if tuple(sdims) != tuple(dims):
+        raise ValueError(f"spinor lattice {sdims} does not match gauge lattice {dims}")
+    out = torch.empty_like(psi) if out is None else out
+    _check_device(U, psi, out)
+    _check(load().dirac_apply(ctypes.byref(_lattice(dims)), U.data_ptr(), psi.data_ptr(), out.data_ptr(), nrhs,
+                              float(m0), layout, prec, DAGGER if dagger else 0, _stream()))
+    return out
+
+
+def dirac_apply_eo(U, psi_e, m0, layout=LAYOUT2, dagger=False, out=None):
+    """eta_e = S psi_e, S = D_ee - D_eo D_oo^-1 D_oe, for an even half-lattice block."""
+    import torch
+
+    prec = _prec_of(psi_e)
+    if _prec_of(U) != prec:
+        raise TypeError("U and psi_e must have the same precision")
+    dims = _dims_of_links(U, prec)
+    nrhs, sdims = _nrhs_of(psi_e, prec, layout, 1)
+    if int(sdims[0]) * 2 != int(np.prod(dims)):
+        raise ValueError(f"half-lattice block has {sdims[0]} sites, lattice {dims} needs {int(np.prod(dims)) // 2}")
+    out = torch.empty_like(psi_e) if out is None else out
+    _check_device(U, psi_e, out)
+    _check(load().dirac_apply_eo(ctypes.byref(_lattice(dims)), U.data_ptr(), psi_e.data_ptr(), out.data_ptr(),
+                                 nrhs, float(m0), layout, prec, DAGGER if dagger else 0, _stream()))
+    return out
+
+
+# ---------------------------------------------------------------- solver
+MODES = {"f64": 0, "ir-f32": 1, "ir-f16": 2}
+
+
+def solver_params(restart=30, max_restarts=200, eo=True, mode=0, tol=1e-10, inner_tol=0.0, max_outer=50,
+                  x_is_guess=False, fixed_iters=False):
+    p = SolverParams()
+    load().lqcd_solver_defaults(ctypes.byref(p))
+    p.restart, p.max_restarts, p.eo = int(restart), int(max_restarts), int(bool(eo))
+    p.mode = MODES[mode] if isinstance(mode, str) else int(mode)
+    p.tol, p.inner_tol, p.max_outer = float(tol), float(inner_tol), int(max_outer)
+    p.x_is_guess, p.fixed_iters = int(bool(x_is_guess)), int(bool(fixed_iters))
+    return p
+
+
+def gmres_workspace_bytes(dims, nrhs, params):
+    return int(load().gmres_workspace_bytes(ctypes.byref(_lattice(dims)), int(nrhs), ctypes.byref(params)))
+
+
+def gmres_solve(U, b, m0, layout=LAYOUT2, x0=None, work=None, **kw):
+    """x = D^-1 b per rhs with batched GMRES (FP64 U and b, full lattice).
+
+    Keyword arguments are those of solver_params; x0 (same shape as b) is the
+    initial guess.  Returns (x, stats, status) with stats a dict of per-rhs
+    numpy arrays and status OK or NOT_CONVERGED."""
+    import torch
+
+    if U.dtype != torch.complex128 or b.dtype != torch.complex128:
+        raise TypeError("gmres_solve takes complex128 U and b")
+    dims = _dims_of_links(U, F64)
+    nrhs, sdims = _nrhs_of(b, F64, layout, 4)
+    if tuple(sdims) != tuple(dims):
+        raise ValueError(f"source lattice {sdims} does not match gauge lattice {dims}")
+    p = solver_params(x_is_guess=x0 is not None, **kw)
+    x = x0.clone() if x0 is not None else torch.empty_like(b)
+    need = gmres_workspace_bytes(dims, nrhs, p)
+    if work is None or work.numel() < need:
+        work = torch.empty(need, dtype=torch.uint8, device=b.device)
+    _check_device(U, b, x, work)
+    st = (RhsStats * nrhs)()
+    rc = _check(load().gmres_solve(ctypes.byref(_lattice(dims)), U.data_ptr(), b.data_ptr(), x.data_ptr(), nrhs,
+                                   float(m0), layout, ctypes.byref(p), work.data_ptr(), work.numel(), st, _stream()))
+    stats = {k: np.array([getattr(s, k) for s in st]) for k, _ in RhsStats._fields_}
+    return x, stats, rc

@@ -1,0 +1,35 @@
+// Internal launchers of the batched BLAS-1 kernels (blas.hip).  Vectors are
+// rhs-innermost [nrow][nrhs] complex in precision `prec`; nelem = nrow*nrhs.
+// Reduction outputs are complex double.  `part` buffers hold nblk*K*nrhs
+// complex doubles; nblk must be reduce_grid(nelem).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+
+namespace lq {
+
+constexpr int DOT_KB = 16;  // dot products computed per pass over w
+
+unsigned reduce_grid(size_t nelem);
+hipError_t dot_parts(int prec, const void* V, size_t vstride, int k0, int K, const void* w, size_t nelem, int nrhs,
+                     const int* live, void* part, unsigned nblk, hipStream_t s);
+hipError_t norm_parts(int prec, const void* x, size_t nelem, int nrhs, const int* live, void* part, unsigned nblk,
+                      hipStream_t s);
+hipError_t cgs_update(int prec, const void* V, size_t vstride, int K, const void* h, void* w, size_t nelem, int nrhs,
+                      const int* live, void* part, unsigned nblk, hipStream_t s);
+hipError_t b_minus_y(int prec, const void* b, void* y, size_t nelem, int nrhs, const int* live, void* part,
+                     unsigned nblk, hipStream_t s);
+hipError_t reduce_parts(const void* part, int nblk, int K, int nrhs, double scale, void* out, hipStream_t s);
+hipError_t scale_rhs(int prec, void* x, size_t nelem, int nrhs, const double* f, const int* live, hipStream_t s);
+hipError_t lincomb(int prec, const void* V, size_t vstride, int kmax, const void* y, const int* cnt, int precx,
+                   void* x, size_t nelem, int nrhs, double scale, hipStream_t s);
+// out = f[rhs] * in (f may be null); add = true: out += f[rhs] * in
+hipError_t convert(int pin, const void* in, int pout, void* out, size_t nelem, int nrhs, const double* f,
+                   hipStream_t s);
+hipError_t add_scaled(int pin, const void* in, void* out64, size_t nelem, int nrhs, const double* f, hipStream_t s);
+hipError_t convert_links(const void* in, int pout, void* out, size_t n, hipStream_t s);
+hipError_t pack(int layout, bool to_internal, void* abi, void* ie, void* io, const int* dims, int nrhs, int eo,
+                hipStream_t s);
+
+}  // namespace lq

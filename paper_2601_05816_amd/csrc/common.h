@@ -1,0 +1,126 @@
+// Shared device/host helpers: complex storage types, precision traits, spinor
+// block addressing for the three layouts, XCD-aware block mapping.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/lqcd.h"
+
+namespace lq {
+
+// ---------------------------------------------------------------- complex ---
+template <typename R>
+struct cx {
+  R re, im;
+};
+
+template <typename R>
+__device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename R>
+__device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename R>
+__device__ __forceinline__ cx<R> operator-(cx<R> a) { return {-a.re, -a.im}; }
+// multiply by +i
+template <typename R>
+__device__ __forceinline__ cx<R> mul_i(cx<R> a) { return {-a.im, a.re}; }
+template <typename R>
+__device__ __forceinline__ cx<R> scale(R s, cx<R> a) { return {s * a.re, s * a.im}; }
+// acc += a * b
+template <typename R>
+__device__ __forceinline__ cx<R> cmadd(cx<R> acc, cx<R> a, cx<R> b) {
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(-a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(a.im, b.re, acc.im);
+  return acc;
+}
+// acc += conj(a) * b
+template <typename R>
+__device__ __forceinline__ cx<R> cjmadd(cx<R> acc, cx<R> a, cx<R> b) {
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(-a.im, b.re, acc.im);
+  return acc;
+}
+
+// ------------------------------------------------------ precision traits ---
+typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
+
+template <int PREC>
+struct prec_traits;
+template <>
+struct prec_traits<LQCD_F64> {
+  typedef double2 store;   // one complex number in memory
+  typedef double real;     // arithmetic type
+};
+template <>
+struct prec_traits<LQCD_F32> {
+  typedef float2 store;
+  typedef float real;
+};
+template <>
+struct prec_traits<LQCD_F16> {
+  typedef h2_t store;
+  typedef float real;
+};
+
+__device__ __forceinline__ cx<double> ld(const double2* p) {
+  double2 v = *p;
+  return {v.x, v.y};
+}
+__device__ __forceinline__ cx<float> ld(const float2* p) {
+  float2 v = *p;
+  return {v.x, v.y};
+}
+__device__ __forceinline__ cx<float> ld(const h2_t* p) {
+  h2_t v = *p;
+  return {(float)v.x, (float)v.y};
+}
+__device__ __forceinline__ void st(double2* p, cx<double> a) { *p = make_double2(a.re, a.im); }
+__device__ __forceinline__ void st(float2* p, cx<float> a) { *p = make_float2(a.re, a.im); }
+__device__ __forceinline__ void st(h2_t* p, cx<float> a) {
+  h2_t v;
+  v.x = (_Float16)a.re;
+  v.y = (_Float16)a.im;
+  *p = v;
+}
+
+// ---------------------------------------------------------- block layout ---
+// Element (site, comp, rhs) of a spinor block with `nsites` sites, 12
+// components per site and nrhs right-hand sides.
+template <int LAYOUT>
+struct blk {
+  // offset of component 0 of (site, rhs)
+  __device__ __forceinline__ static size_t base(size_t site, int rhs, size_t nsites, int nrhs) {
+    if (LAYOUT == LQCD_LAYOUT2) return site * 12u * (size_t)nrhs + (size_t)rhs;
+    if (LAYOUT == LQCD_LAYOUT1) return (site * (size_t)nrhs + (size_t)rhs) * 12u;
+    return ((size_t)rhs * nsites + site) * 12u;  // LQCD_RHS_OUTER
+  }
+  __device__ __forceinline__ static int cstride(int nrhs) { return LAYOUT == LQCD_LAYOUT2 ? nrhs : 1; }
+  // work item t -> (site, rhs): the rhs index runs fastest where it is the
+  // innermost memory index, the site index otherwise.
+  __device__ __forceinline__ static void item(size_t t, size_t nsites, int nrhs, size_t& site, int& rhs) {
+    if (LAYOUT == LQCD_RHS_OUTER) {
+      rhs = (int)(t / nsites);
+      site = t - (size_t)rhs * nsites;
+    } else {
+      site = t / (size_t)nrhs;
+      rhs = (int)(t - site * (size_t)nrhs);
+    }
+  }
+};
+
+// Consecutive workgroups are dispatched round-robin over the 8 XCDs, each
+// with a private L2.  Renumber so that XCD k processes a contiguous range of
+// the logical block space (a bijection for any grid size).
+__device__ __forceinline__ unsigned xcd_block(unsigned bid, unsigned nblk) {
+  const unsigned nx = 8;
+  unsigned q = nblk / nx, r = nblk % nx;
+  unsigned k = bid % nx, i = bid / nx;
+  return k * q + (k < r ? k : r) + i;
+}
+
+}  // namespace lq

@@ -1,0 +1,390 @@
+// Wilson-Dirac kernels that stream along the time direction ("pencils").
+//
+// A work item owns one spatial column (z, y, x) and one rhs and walks a
+// segment of t values.  The +t neighbour loaded for site t is the centre of
+// site t+1 and the -t neighbour of site t+2, so each spinor along t is read
+// once and its three uses (Algorithm 1: the diagonal term of line 1 and the
+// two time-direction hops of lines 7 and 9) are served from registers; only
+// the six spatial neighbours go through the caches.  The time link U_0(x) is
+// shared between the +t hop of site t and the -t hop of site t+1.
+//
+// Columns are grouped into tiles (TX x TY x TZ).  Workgroup b runs on XCD
+// b mod 8 (the dispatcher's round-robin); the eight workgroups of a "tile
+// group" at the same position of the dispatch order therefore work on eight
+// adjacent tiles at the same time, so that a tile's spatial halo is the
+// interior of a tile that another XCD reads in the same time step.  Within
+// an XCD the tile's workgroups cover the tile's columns and rhs.  The
+// mapping is a bijection for any tile shape; the tile shape and the number
+// of t segments only change locality.
+#include "kernels.h"
+#include "wilson.h"
+
+namespace lq {
+
+struct pencil_geo {
+  int n[4];          // N0 = T, N1 = Z, N2 = Y, N3 = X
+  size_t V;
+  int TX, TY, TZ;    // column tile (in columns; TX counts compact columns for eo)
+  int NTX, NTY, NTZ; // tiles per direction
+  int nseg, Lt;      // t segments and their length
+  int bpt;           // workgroups per tile and segment
+  int ntiles;
+};
+
+// (column coordinates, rhs, t0) of this work item, or false if idle.
+template <int LAYOUT>
+__device__ __forceinline__ bool pencil_item(const pencil_geo& pg, int nrhs, int& x, int& y, int& z, int& rhs,
+                                            int& t0) {
+  const unsigned b = blockIdx.x;
+  const unsigned k = b & 7u, i = b >> 3;
+  const unsigned u = i / pg.bpt, q = i % pg.bpt;
+  const unsigned grp = u / pg.nseg, seg = u % pg.nseg;
+  const unsigned tile = grp * 8u + k;
+  if (tile >= (unsigned)pg.ntiles) return false;
+  const unsigned CT = (unsigned)pg.TX * pg.TY * pg.TZ;
+  const unsigned tin = q * blockDim.x + threadIdx.x;
+  if (tin >= CT * (unsigned)nrhs) return false;
+  unsigned col;
+  if (LAYOUT == LQCD_RHS_OUTER) {
+    rhs = (int)(tin / CT);
+    col = tin % CT;
+  } else {
+    col = tin / nrhs;
+    rhs = (int)(tin % nrhs);
+  }
+  const int tx = tile % pg.NTX, ty = (tile / pg.NTX) % pg.NTY, tz = tile / (pg.NTX * pg.NTY);
+  x = tx * pg.TX + (int)(col % pg.TX);
+  y = ty * pg.TY + (int)((col / pg.TX) % pg.TY);
+  z = tz * pg.TZ + (int)(col / (pg.TX * pg.TY));
+  t0 = (int)seg * pg.Lt;
+  return true;
+}
+
+template <typename R>
+__device__ __forceinline__ half_spinor<R> hscale(R s, half_spinor<R> h) {
+#pragma unroll
+  for (int i = 0; i < 6; ++i) h.c[i / 3][i % 3] = scale(s, h.c[i / 3][i % 3]);
+  return h;
+}
+
+// acc += c * (hop term of direction MU with projector sign T) for a loaded
+// neighbour p and link u (ADJ: use u^dagger)
+template <int MU, int T, bool ADJ, typename S, typename R>
+__device__ __forceinline__ void add_hop(spinor<R>& acc, const spinor<R>& p, const S* __restrict__ u, R c) {
+  half_spinor<R> h = project<MU, T>(p);
+  reconstruct<MU, T>(acc, hscale(c, colour_mul<ADJ>(u, h)));
+}
+
+// ---------------------------------------------------------- full lattice
+template <int PREC, int LAYOUT, int SG>
+__global__ __launch_bounds__(256) void k_wilson_full_p(const typename prec_traits<PREC>::store* __restrict__ U,
+                                                       const typename prec_traits<PREC>::store* __restrict__ psi,
+                                                       typename prec_traits<PREC>::store* __restrict__ eta,
+                                                       pencil_geo pg, int nrhs,
+                                                       typename prec_traits<PREC>::real diag,
+                                                       typename prec_traits<PREC>::real hopc) {
+  typedef typename prec_traits<PREC>::store S;
+  typedef typename prec_traits<PREC>::real R;
+  int x, y, z, rhs, t0;
+  if (!pencil_item<LAYOUT>(pg, nrhs, x, y, z, rhs, t0)) return;
+  const int T = pg.n[0], NZ = pg.n[1], NY = pg.n[2], NX = pg.n[3];
+  const size_t V = pg.V, S0 = (size_t)NZ * NY * NX;
+  const int cs = blk<LAYOUT>::cstride(nrhs);
+  // column bases (site number at t = 0) of this column and its spatial neighbours
+  const size_t c0 = ((size_t)z * NY + y) * NX + x;
+  const size_t cxf = c0 - x + (x + 1 < NX ? x + 1 : 0), cxb = c0 - x + (x > 0 ? x - 1 : NX - 1);
+  const size_t cyf = c0 + (size_t)((y + 1 < NY ? y + 1 : 0) - y) * NX;
+  const size_t cyb = c0 + (size_t)((y > 0 ? y - 1 : NY - 1) - y) * NX;
+  const size_t czf = c0 + (size_t)((z + 1 < NZ ? z + 1 : 0) - z) * NY * NX;
+  const size_t czb = c0 + (size_t)((z > 0 ? z - 1 : NZ - 1) - z) * NY * NX;
+  const S* U0 = U;
+  const S* U1 = U + 1 * V * 9;
+  const S* U2 = U + 2 * V * 9;
+  const S* U3 = U + 3 * V * 9;
+
+  // prologue: the -t hop of site t0 and the projected centre of t0
+  spinor<R> acc;
+  half_spinor<R> hplus;
+  {
+    const int tm = t0 > 0 ? t0 - 1 : T - 1;
+    const size_t sm = (size_t)tm * S0 + c0;
+    spinor<R> pm = load_spinor<S, R>(psi, blk<LAYOUT>::base(sm, rhs, V, nrhs), cs);
+#pragma unroll
+    for (int i = 0; i < 12; ++i) acc.c[i / 3][i % 3] = {R(0), R(0)};
+    add_hop<0, SG, true, S, R>(acc, pm, U0 + sm * 9, hopc);
+    const size_t s0 = (size_t)t0 * S0 + c0;
+    spinor<R> p0 = load_spinor<S, R>(psi, blk<LAYOUT>::base(s0, rhs, V, nrhs), cs);
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+      cx<R> a = acc.c[i / 3][i % 3], b = p0.c[i / 3][i % 3];
+      acc.c[i / 3][i % 3] = {fma(diag, b.re, a.re), fma(diag, b.im, a.im)};
+    }
+    hplus = project<0, SG>(p0);
+  }
+  for (int it = 0; it < pg.Lt; ++it) {
+    const int t = t0 + it;
+    const size_t toff = (size_t)t * S0;
+    const size_t site = toff + c0;
+    // spatial hops (directions 3 = x, 2 = y, 1 = z)
+    {
+      spinor<R> p = load_spinor<S, R>(psi, blk<LAYOUT>::base(toff + cxf, rhs, V, nrhs), cs);
+      add_hop<3, -SG, false, S, R>(acc, p, U3 + site * 9, hopc);
+    }
+    {
+      spinor<R> p = load_spinor<S, R>(psi, blk<LAYOUT>::base(toff + cxb, rhs, V, nrhs), cs);
+      add_hop<3, SG, true, S, R>(acc, p, U3 + (toff + cxb) * 9, hopc);
+    }
+    {
+      spinor<R> p = load_spinor<S, R>(psi, blk<LAYOUT>::base(toff + cyf, rhs, V, nrhs), cs);
+      add_hop<2, -SG, false, S, R>(acc, p, U2 + site * 9, hopc);
+    }
+    {
+      spinor<R> p = load_spinor<S, R>(psi, blk<LAYOUT>::base(toff + cyb, rhs, V, nrhs), cs);
+      add_hop<2, SG, true, S, R>(acc, p, U2 + (toff + cyb) * 9, hopc);
+    }
+    {
+      spinor<R> p = load_spinor<S, R>(psi, blk<LAYOUT>::base(toff + czf, rhs, V, nrhs), cs);
+      add_hop<1, -SG, false, S, R>(acc, p, U1 + site * 9, hopc);
+    }
+    {
+      spinor<R> p = load_spinor<S, R>(psi, blk<LAYOUT>::base(toff + czb, rhs, V, nrhs), cs);
+      add_hop<1, SG, true, S, R>(acc, p, U1 + (toff + czb) * 9, hopc);
+    }
+    // time direction: psi(t+1) gives the +t hop of t, and the centre and the
+    // -t hop (through U_0(t)^dagger and the carried projection of psi(t)) of t+1
+    const int t1 = t + 1 < T ? t + 1 : 0;
+    const size_t s1 = (size_t)t1 * S0 + c0;
+    spinor<R> p1 = load_spinor<S, R>(psi, blk<LAYOUT>::base(s1, rhs, V, nrhs), cs);
+    add_hop<0, -SG, false, S, R>(acc, p1, U0 + site * 9, hopc);
+    store_spinor<S, R>(eta, blk<LAYOUT>::base(site, rhs, V, nrhs), cs, acc);
+    if (it + 1 < pg.Lt) {
+#pragma unroll
+      for (int i = 0; i < 12; ++i) acc.c[i / 3][i % 3] = scale(diag, p1.c[i / 3][i % 3]);
+      reconstruct<0, SG>(acc, hscale(hopc, colour_mul<true>(U0 + site * 9, hplus)));
+      hplus = project<0, SG>(p1);
+    }
+  }
+}
+
+// --------------------------------------------------------- odd-even hop
+// out(h) = alpha xin(h) + beta hop(in)(h) on parity p; columns are the
+// compact (z, y, j) columns, j = x >> 1.  Along t the output site of a
+// compact column alternates between x = 2j and 2j + 1; its +-t neighbours
+// (parity 1-p) lie in the same compact column at t +- 1 with the same x.
+// The neighbour at t+1 is the +t hop of t and the -t hop of t+2: its
+// projection is carried two steps in a small FIFO.
+template <int PREC, int LAYOUT, int SG>
+__global__ __launch_bounds__(256) void k_wilson_eo_p(const typename prec_traits<PREC>::store* __restrict__ U,
+                                                     const typename prec_traits<PREC>::store* __restrict__ in,
+                                                     const typename prec_traits<PREC>::store* __restrict__ xin,
+                                                     typename prec_traits<PREC>::store* __restrict__ out,
+                                                     pencil_geo pg, int p, int nrhs,
+                                                     typename prec_traits<PREC>::real alpha,
+                                                     typename prec_traits<PREC>::real beta,
+                                                     const int* __restrict__ live) {
+  typedef typename prec_traits<PREC>::store S;
+  typedef typename prec_traits<PREC>::real R;
+  int j, y, z, rhs, t0;
+  if (!pencil_item<LAYOUT>(pg, nrhs, j, y, z, rhs, t0)) return;
+  if (live && !live[rhs]) return;
+  const int T = pg.n[0], NZ = pg.n[1], NY = pg.n[2], NX = pg.n[3];
+  const int NXh = NX >> 1;
+  const size_t V = pg.V, Vh = V / 2;
+  const size_t S0 = (size_t)NZ * NY * NX, H0 = S0 / 2;  // site / compact strides of one time slice
+  const int cs = blk<LAYOUT>::cstride(nrhs);
+  const size_t row = (size_t)z * NY + y;                   // (z, y) row
+  const size_t hc = row * NXh + j;                         // compact column base at t = 0
+  const size_t hyf = ((size_t)z * NY + (y + 1 < NY ? y + 1 : 0)) * NXh + j;
+  const size_t hyb = ((size_t)z * NY + (y > 0 ? y - 1 : NY - 1)) * NXh + j;
+  const size_t hzf = ((size_t)(z + 1 < NZ ? z + 1 : 0) * NY + y) * NXh + j;
+  const size_t hzb = ((size_t)(z > 0 ? z - 1 : NZ - 1) * NY + y) * NXh + j;
+  const size_t lyb = ((size_t)z * NY + (y > 0 ? y - 1 : NY - 1)) * NX;  // site bases (x added later)
+  const size_t lzb = ((size_t)(z > 0 ? z - 1 : NZ - 1) * NY + y) * NX;
+  const size_t lrow = row * NX;
+  const S* U0 = U;
+  const S* U1 = U + 1 * V * 9;
+  const S* U2 = U + 2 * V * 9;
+  const S* U3 = U + 3 * V * 9;
+  const int par0 = (p + z + y) & 1;  // x parity offset at t = 0
+
+  // FIFO of projected (1 + SG gamma_0) in(t') for t' = t-1 (q0) and t (q1)
+  half_spinor<R> q0, q1;
+  {
+    const int tm = t0 > 0 ? t0 - 1 : T - 1;
+    spinor<R> pm = load_spinor<S, R>(in, blk<LAYOUT>::base((size_t)tm * H0 + hc, rhs, Vh, nrhs), cs);
+    q0 = project<0, SG>(pm);
+    spinor<R> pz = load_spinor<S, R>(in, blk<LAYOUT>::base((size_t)t0 * H0 + hc, rhs, Vh, nrhs), cs);
+    q1 = project<0, SG>(pz);
+  }
+  for (int it = 0; it < pg.Lt; ++it) {
+    const int t = t0 + it;
+    const int x = 2 * j + ((par0 + t) & 1);
+    const size_t site = (size_t)t * S0 + lrow + x;
+    const size_t hh = (size_t)t * H0 + hc;
+    const size_t toffh = (size_t)t * H0;
+    spinor<R> acc;
+#pragma unroll
+    for (int i = 0; i < 12; ++i) acc.c[i / 3][i % 3] = {R(0), R(0)};
+    // -t hop from the carried projection of in(t-1) through U_0(t-1, x)^dagger
+    {
+      const int tm = t > 0 ? t - 1 : T - 1;
+      reconstruct<0, SG>(acc, colour_mul<true>(U0 + ((size_t)tm * S0 + lrow + x) * 9, q0));
+    }
+    // spatial hops
+    {
+      const int xf = x + 1 < NX ? x + 1 : 0, xb = x > 0 ? x - 1 : NX - 1;
+      spinor<R> pf = load_spinor<S, R>(in, blk<LAYOUT>::base(toffh + row * NXh + (xf >> 1), rhs, Vh, nrhs), cs);
+      add_hop<3, -SG, false, S, R>(acc, pf, U3 + site * 9, R(1));
+      spinor<R> pb = load_spinor<S, R>(in, blk<LAYOUT>::base(toffh + row * NXh + (xb >> 1), rhs, Vh, nrhs), cs);
+      add_hop<3, SG, true, S, R>(acc, pb, U3 + ((size_t)t * S0 + lrow + xb) * 9, R(1));
+    }
+    {
+      spinor<R> pf = load_spinor<S, R>(in, blk<LAYOUT>::base(toffh + hyf, rhs, Vh, nrhs), cs);
+      add_hop<2, -SG, false, S, R>(acc, pf, U2 + site * 9, R(1));
+      spinor<R> pb = load_spinor<S, R>(in, blk<LAYOUT>::base(toffh + hyb, rhs, Vh, nrhs), cs);
+      add_hop<2, SG, true, S, R>(acc, pb, U2 + ((size_t)t * S0 + lyb + x) * 9, R(1));
+    }
+    {
+      spinor<R> pf = load_spinor<S, R>(in, blk<LAYOUT>::base(toffh + hzf, rhs, Vh, nrhs), cs);
+      add_hop<1, -SG, false, S, R>(acc, pf, U1 + site * 9, R(1));
+      spinor<R> pb = load_spinor<S, R>(in, blk<LAYOUT>::base(toffh + hzb, rhs, Vh, nrhs), cs);
+      add_hop<1, SG, true, S, R>(acc, pb, U1 + ((size_t)t * S0 + lzb + x) * 9, R(1));
+    }
+    // +t hop: in(t+1) in the same compact column (same x)
+    {
+      const int t1 = t + 1 < T ? t + 1 : 0;
+      spinor<R> p1 = load_spinor<S, R>(in, blk<LAYOUT>::base((size_t)t1 * H0 + hc, rhs, Vh, nrhs), cs);
+      add_hop<0, -SG, false, S, R>(acc, p1, U0 + site * 9, R(1));
+      q0 = q1;
+      q1 = project<0, SG>(p1);
+    }
+    const size_t me = blk<LAYOUT>::base(hh, rhs, Vh, nrhs);
+    if (xin) {
+      spinor<R> xv = load_spinor<S, R>(xin, me, cs);
+#pragma unroll
+      for (int i = 0; i < 12; ++i) {
+        cx<R> a = acc.c[i / 3][i % 3], b = xv.c[i / 3][i % 3];
+        acc.c[i / 3][i % 3] = {fma(beta, a.re, alpha * b.re), fma(beta, a.im, alpha * b.im)};
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 12; ++i) acc.c[i / 3][i % 3] = scale(beta, acc.c[i / 3][i % 3]);
+    }
+    store_spinor<S, R>(out, me, cs, acc);
+  }
+}
+
+// ------------------------------------------------------------ configuration
+static int g_variant = 0;                 // 0 auto, 1 site kernel, 2 pencil kernel
+static int g_pencil[3] = {0, 0, 0};       // TY, TZ, nseg overrides (0 = automatic)
+
+void set_variant(int v, const int* pencil) {
+  g_variant = v;
+  for (int i = 0; i < 3; ++i) g_pencil[i] = pencil ? pencil[i] : 0;
+}
+int get_variant() { return g_variant; }
+
+static int largest_divisor_at_most(int n, int cap) {
+  if (cap < 1) cap = 1;
+  for (int d = cap < n ? cap : n; d >= 1; --d)
+    if (n % d == 0) return d;
+  return 1;
+}
+
+// Tile: all of X, then as much of Y and Z as one XCD keeps resident (about
+// 16384 work items); segments: enough work items for several waves of
+// residency on the whole chip.
+static pencil_geo make_pencil(const lqcd_lattice* lat, int nrhs, bool eo) {
+  pencil_geo pg;
+  for (int i = 0; i < 4; ++i) pg.n[i] = lat->dims[i];
+  pg.V = (size_t)pg.n[0] * pg.n[1] * pg.n[2] * pg.n[3];
+  const int T = pg.n[0], NZ = pg.n[1], NY = pg.n[2], NX = pg.n[3];
+  pg.TX = eo ? NX / 2 : NX;
+  const int target_cols = (16384 / nrhs) > 0 ? 16384 / nrhs : 1;
+  int rest = target_cols / pg.TX;
+  if (rest < 1) rest = 1;
+  int TY = g_pencil[0] > 0 ? g_pencil[0] : largest_divisor_at_most(NY, rest);
+  int TZ = g_pencil[1] > 0 ? g_pencil[1] : largest_divisor_at_most(NZ, rest / TY);
+  if (NY % TY) TY = 1;
+  if (NZ % TZ) TZ = 1;
+  pg.TY = TY;
+  pg.TZ = TZ;
+  pg.NTX = 1;
+  pg.NTY = NY / TY;
+  pg.NTZ = NZ / TZ;
+  pg.ntiles = pg.NTY * pg.NTZ;
+  const size_t cols = (size_t)pg.TX * NY * NZ;
+  int nseg = 1;
+  if (g_pencil[2] > 0 && T % g_pencil[2] == 0) {
+    nseg = g_pencil[2];
+  } else {
+    const size_t want = 524288;
+    while (nseg < T && cols * (size_t)nrhs * nseg < want) {
+      int next = nseg + 1;
+      while (next < T && T % next) ++next;
+      nseg = next;
+    }
+  }
+  pg.nseg = nseg;
+  pg.Lt = T / nseg;
+  const size_t items = (size_t)pg.TX * TY * TZ * nrhs;
+  pg.bpt = (int)((items + 255) / 256);
+  return pg;
+}
+
+static unsigned pencil_blocks(const pencil_geo& pg) {
+  const unsigned ngroups = (unsigned)((pg.ntiles + 7) / 8);
+  return ngroups * 8u * (unsigned)pg.nseg * (unsigned)pg.bpt;
+}
+
+template <int PREC, int LAYOUT, int SG>
+static void launch_full_p(const lqcd_lattice* lat, const void* U, const void* psi, void* eta, int nrhs, double diag,
+                          double hopc, hipStream_t s) {
+  typedef typename prec_traits<PREC>::store S;
+  typedef typename prec_traits<PREC>::real R;
+  pencil_geo pg = make_pencil(lat, nrhs, false);
+  hipLaunchKernelGGL((k_wilson_full_p<PREC, LAYOUT, SG>), dim3(pencil_blocks(pg)), dim3(256), 0, s, (const S*)U,
+                     (const S*)psi, (S*)eta, pg, nrhs, (R)diag, (R)hopc);
+}
+
+template <int PREC, int LAYOUT, int SG>
+static void launch_eo_p(const lqcd_lattice* lat, const void* U, const void* in, const void* xin, void* out, int p,
+                        int nrhs, double alpha, double beta, const int* live, hipStream_t s) {
+  typedef typename prec_traits<PREC>::store S;
+  typedef typename prec_traits<PREC>::real R;
+  pencil_geo pg = make_pencil(lat, nrhs, true);
+  hipLaunchKernelGGL((k_wilson_eo_p<PREC, LAYOUT, SG>), dim3(pencil_blocks(pg)), dim3(256), 0, s, (const S*)U,
+                     (const S*)in, (const S*)xin, (S*)out, pg, p, nrhs, (R)alpha, (R)beta, live);
+}
+
+#define LQ_KEY(p, l, d) ((p) * 100 + (l) * 10 + (d))
+#define LQ_CASE(P, L, D, FN, ...) \
+  case LQ_KEY(P, L, D): FN<P, L, (D) ? -1 : 1>(__VA_ARGS__); break;
+#define LQ_CASES_L(P, D, FN, ...)                   \
+  LQ_CASE(P, LQCD_RHS_OUTER, D, FN, __VA_ARGS__)    \
+  LQ_CASE(P, LQCD_LAYOUT1, D, FN, __VA_ARGS__)      \
+  LQ_CASE(P, LQCD_LAYOUT2, D, FN, __VA_ARGS__)
+#define LQ_DISPATCH(PREC_, LAYOUT_, DAG_, FN, ...)                                         \
+  do {                                                                                     \
+    switch (LQ_KEY(PREC_, LAYOUT_, DAG_)) {                                                \
+      LQ_CASES_L(LQCD_F64, 0, FN, __VA_ARGS__) LQ_CASES_L(LQCD_F64, 1, FN, __VA_ARGS__)    \
+      LQ_CASES_L(LQCD_F32, 0, FN, __VA_ARGS__) LQ_CASES_L(LQCD_F32, 1, FN, __VA_ARGS__)    \
+      LQ_CASES_L(LQCD_F16, 0, FN, __VA_ARGS__) LQ_CASES_L(LQCD_F16, 1, FN, __VA_ARGS__)    \
+      default: return hipErrorInvalidValue;                                                \
+    }                                                                                      \
+  } while (0)
+
+hipError_t wilson_full_pencil(const lqcd_lattice* lat, const void* U, const void* psi, void* eta, int nrhs,
+                              double diag, double hopc, int layout, int prec, bool dagger, hipStream_t s) {
+  LQ_DISPATCH(prec, layout, (dagger ? 1 : 0), launch_full_p, lat, U, psi, eta, nrhs, diag, hopc, s);
+  return hipGetLastError();
+}
+
+hipError_t wilson_eo_pencil(const lqcd_lattice* lat, const void* U, const void* in, const void* xin, void* out,
+                            int p, int nrhs, double alpha, double beta, int layout, int prec, bool dagger,
+                            const int* live, hipStream_t s) {
+  LQ_DISPATCH(prec, layout, (dagger ? 1 : 0), launch_eo_p, lat, U, in, xin, out, p, nrhs, alpha, beta, live, s);
+  return hipGetLastError();
+}
+
+}  // namespace lq

@@ -1,0 +1,120 @@
+// Per-site Wilson hopping term on a block of right-hand sides.
+//
+// For one output site x and one rhs the kernels accumulate
+//   hop(x) = sum_mu [ (1 - s gamma_mu) U_mu(x) psi(x+mu) + (1 + s gamma_mu) U_mu(x-mu)^dag psi(x-mu) ]
+// with s = +1 for D and s = -1 for D^dagger (the adjoint of each hopping term
+// flips the sign of gamma_mu), the quantity summed in Algorithm 1, lines 7 and 9.
+// Each term is evaluated on a half spinor, as Sec. III-A.1 describes for the
+// projected vectors lambda_mu and chi_mu: with psi = (u; d) in upper/lower
+// spin pairs and gamma_mu = [[0, B], [B^dag, 0]],
+//   (1 + t gamma_mu) psi = (h; t B^dag h),  h = u + t B d,
+// so the colour matrix multiplies the 2x3 block h only (two 3x3-by-3 products
+// instead of four) and the lower spins are rebuilt from the product.  Every
+// B_mu has entries in {0, +-1, +-i}, so the projection is additions only.
+#pragma once
+
+#include "common.h"
+
+namespace lq {
+
+template <typename R>
+struct spinor {
+  cx<R> c[4][3];  // [spin][colour]
+};
+template <typename R>
+struct half_spinor {
+  cx<R> c[2][3];
+};
+
+// h = u + t B_mu d  (T = t = +-1)
+template <int MU, int T, typename R>
+__device__ __forceinline__ half_spinor<R> project(const spinor<R>& p) {
+  half_spinor<R> h;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    cx<R> u0 = p.c[0][a], u1 = p.c[1][a], d0 = p.c[2][a], d1 = p.c[3][a];
+    cx<R> b0, b1;  // (B d)_0, (B d)_1
+    if (MU == 0) { b0 = d0; b1 = d1; }                               // B_0 = 1
+    if (MU == 1) { b0 = -mul_i(d1); b1 = -mul_i(d0); }               // B_1 = [[0,-i],[-i,0]]
+    if (MU == 2) { b0 = -d1; b1 = d0; }                              // B_2 = [[0,-1],[1,0]]
+    if (MU == 3) { b0 = -mul_i(d0); b1 = mul_i(d1); }                // B_3 = [[-i,0],[0,i]]
+    if (T > 0) { h.c[0][a] = u0 + b0; h.c[1][a] = u1 + b1; }
+    else       { h.c[0][a] = u0 - b0; h.c[1][a] = u1 - b1; }
+  }
+  return h;
+}
+
+// acc += (r; t B_mu^dag r)
+template <int MU, int T, typename R>
+__device__ __forceinline__ void reconstruct(spinor<R>& acc, const half_spinor<R>& r) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    cx<R> r0 = r.c[0][a], r1 = r.c[1][a];
+    cx<R> l0, l1;  // (B^dag r)_0, (B^dag r)_1
+    if (MU == 0) { l0 = r0; l1 = r1; }
+    if (MU == 1) { l0 = mul_i(r1); l1 = mul_i(r0); }
+    if (MU == 2) { l0 = r1; l1 = -r0; }
+    if (MU == 3) { l0 = mul_i(r0); l1 = -mul_i(r1); }
+    acc.c[0][a] = acc.c[0][a] + r0;
+    acc.c[1][a] = acc.c[1][a] + r1;
+    if (T > 0) { acc.c[2][a] = acc.c[2][a] + l0; acc.c[3][a] = acc.c[3][a] + l1; }
+    else       { acc.c[2][a] = acc.c[2][a] - l0; acc.c[3][a] = acc.c[3][a] - l1; }
+  }
+}
+
+// r = U h (ADJ = false) or U^dag h (ADJ = true); U row-major 3x3 in memory.
+template <bool ADJ, typename S, typename R>
+__device__ __forceinline__ half_spinor<R> colour_mul(const S* __restrict__ u, const half_spinor<R>& h) {
+  cx<R> m[3][3];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) m[i / 3][i % 3] = ld(u + i);
+  half_spinor<R> r;
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      cx<R> acc = {R(0), R(0)};
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        if (ADJ) acc = cjmadd(acc, m[b][a], h.c[s][b]);
+        else     acc = cmadd(acc, m[a][b], h.c[s][b]);
+      }
+      r.c[s][a] = acc;
+    }
+  }
+  return r;
+}
+
+template <typename S, typename R>
+__device__ __forceinline__ spinor<R> load_spinor(const S* __restrict__ p, size_t base, int cs) {
+  spinor<R> v;
+#pragma unroll
+  for (int i = 0; i < 12; ++i) v.c[i / 3][i % 3] = ld(p + base + (size_t)i * cs);
+  return v;
+}
+
+template <typename S, typename R>
+__device__ __forceinline__ void store_spinor(S* __restrict__ p, size_t base, int cs, const spinor<R>& v) {
+#pragma unroll
+  for (int i = 0; i < 12; ++i) st(p + base + (size_t)i * cs, v.c[i / 3][i % 3]);
+}
+
+// One direction mu: forward neighbour (block offset fb, link U_mu(x) at uf)
+// and backward neighbour (block offset bb, link U_mu(x-mu) at ub).
+// SG = +1 for D, -1 for D^dagger.
+template <int MU, int SG, typename S, typename R>
+__device__ __forceinline__ void hop_dir(spinor<R>& acc, const S* __restrict__ psi, int cs, size_t fb,
+                                        size_t bb, const S* __restrict__ uf, const S* __restrict__ ub) {
+  {
+    spinor<R> p = load_spinor<S, R>(psi, fb, cs);
+    half_spinor<R> h = project<MU, -SG>(p);
+    reconstruct<MU, -SG>(acc, colour_mul<false>(uf, h));
+  }
+  {
+    spinor<R> p = load_spinor<S, R>(psi, bb, cs);
+    half_spinor<R> h = project<MU, SG>(p);
+    reconstruct<MU, SG>(acc, colour_mul<true>(ub, h));
+  }
+}
+
+}  // namespace lq

@@ -1,0 +1,60 @@
+"""Test-side conversions between the oracle's array shapes and the tensors
+the binding takes (layout permutations and precision casts only)."""
+import numpy as np
+
+import paper_2601_05816_amd as lq
+
+
+def to_layout_np(block, layout):
+    """oracle block (nrhs, *sites, 4, 3) -> numpy array in `layout`."""
+    ns = block.ndim - 3  # number of site axes
+    if layout == lq.RHS_OUTER:
+        return np.ascontiguousarray(block)
+    if layout == lq.LAYOUT1:
+        return np.ascontiguousarray(np.moveaxis(block, 0, ns))
+    return np.ascontiguousarray(np.moveaxis(block, 0, -1))
+
+
+def from_layout_np(arr, layout, ns):
+    if layout == lq.RHS_OUTER:
+        return arr
+    if layout == lq.LAYOUT1:
+        return np.moveaxis(arr, ns, 0)
+    return np.moveaxis(arr, -1, 0)
+
+
+def to_dev(arr, prec, device="cuda"):
+    import torch
+
+    if prec == lq.F64:
+        return torch.from_numpy(np.ascontiguousarray(arr.astype(np.complex128))).to(device)
+    if prec == lq.F32:
+        return torch.from_numpy(np.ascontiguousarray(arr.astype(np.complex64))).to(device)
+    h = np.stack([arr.real, arr.imag], axis=-1).astype(np.float16)
+    return torch.from_numpy(np.ascontiguousarray(h)).to(device)
+
+
+def from_dev(t, prec):
+    a = t.cpu().numpy()
+    if prec == lq.F16:
+        a = a.astype(np.float64)
+        return a[..., 0] + 1j * a[..., 1]
+    return a.astype(np.complex128)
+
+
+def rounded(arr, prec):
+    """The values a precision actually stores (what the GPU reads)."""
+    if prec == lq.F64:
+        return arr.astype(np.complex128)
+    if prec == lq.F32:
+        return arr.astype(np.complex64).astype(np.complex128)
+    re = arr.real.astype(np.float16).astype(np.float64)
+    im = arr.imag.astype(np.float16).astype(np.float64)
+    return re + 1j * im
+
+
+def rel_err_per_rhs(got, want):
+    n = got.shape[0]
+    g = got.reshape(n, -1)
+    w = want.reshape(n, -1)
+    return np.linalg.norm(g - w, axis=1) / np.linalg.norm(w, axis=1)

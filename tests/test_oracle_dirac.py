@@ -154,3 +154,12 @@ def test_linearity_and_blocks_independent():
     block = dirac.apply_dw(U, psi, 0.3)
     for i in range(3):
         assert np.allclose(dirac.apply_dw(U, psi[i:i + 1], 0.3)[0], block[i], atol=1e-14)
+
+
+def test_site_sampled_apply_matches_block():
+    dims = (4, 4, 2, 6)
+    U = syn.gauge_field(dims, "near_identity", config=10)
+    psi = syn.spinor_block(dims, 3, config=10)
+    full = dirac.apply_dw(U, psi, -0.05).reshape(3, -1, 4, 3)
+    sites = [0, 5, 17, 95, 191]
+    assert np.max(np.abs(dirac.apply_dw_sites(U, psi, -0.05, sites) - full[:, sites])) < 1e-13
