@@ -83,12 +83,39 @@ int lqcd_lattice_tables(const lqcd_lattice* lat, int32_t* nbr, int32_t* eo_site)
 
 /* Kernel selection for the Wilson kernels (process-wide; for tuning and
  * tests).  variant 0 = automatic, 1 = one (site, rhs) per work item,
- * 2 = time-streaming pencils.  pencil (may be NULL) = {tile Y, tile Z, number
- * of t segments} for variant 2; 0 entries are chosen automatically, values
+ * 2 = time-streaming pencils with the links of each step staged in LDS,
+ * 3 = pencils without LDS staging.  pencil (may be NULL) = {tile Y, tile Z,
+ * number of t segments} for variants 2 and 3; 0 entries are chosen automatically, values
  * that do not divide the lattice fall back to automatic.  Every choice
  * computes the same sums; results agree to rounding.  Not thread-safe
  * against concurrent applies. */
 int lqcd_set_kernel_variant(int variant, const int32_t* pencil);
+
+/* Full kernel configuration (for tuning and tests; process-wide).
+ * variant: 0 automatic (the autotuner's entry for the arguments, else the
+ * default), 1, 2 or 3 as above; tile_y, tile_z, segments: pencil tile and t
+ * segments (0 = automatic); nontemporal: 1 = output stores bypass L2
+ * allocation.  NULL restores automatic selection.  ms is ignored. */
+typedef struct {
+  int32_t variant, tile_y, tile_z, segments, nontemporal;
+  double ms;  /* measured time of one launch (filled by the autotuner) */
+} lqcd_kernel_config;
+int lqcd_set_kernel_config(const lqcd_kernel_config* cfg);
+
+/* Autotuner: times every candidate kernel configuration for this apply
+ * (eo = 0: the full operator, eo = 1: one odd-even hop pass, the kernel a
+ * Schur apply runs twice) on the caller's buffers (eta is overwritten; for
+ * eo, psi and eta are half-lattice blocks), reps launches each, and records
+ * the fastest for automatic selection by every later apply with the same
+ * lattice, nrhs, precision and layout.  Synchronises `stream`.  best (may be
+ * NULL) receives the winner and its time per launch. */
+int lqcd_autotune(const lqcd_lattice* lat, const void* U, const void* psi, void* eta, int nrhs, int prec,
+                  int layout, int eo, int reps, lqcd_kernel_config* best, void* stream);
+/* Write / read the autotuner's table (text, one entry per line).  Load
+ * returns the number of entries read or a negative error. */
+int lqcd_tune_save(const char* path);
+int lqcd_tune_load(const char* path);
+void lqcd_tune_clear(void);
 
 /* eta = D psi (flags & LQCD_DAGGER: eta = D^dagger psi) for every rhs
  * (Sec. III-A.1 operator, Algorithm 1 fused into one pass; the rhs loop is
@@ -107,6 +134,43 @@ int dirac_apply(const lqcd_lattice* lat, const void* U, const void* psi, void* e
 int dirac_apply_eo(const lqcd_lattice* lat, const void* U, const void* psi_e, void* eta_e,
                    int nrhs, double m0, int layout, int prec, int flags, void* stream);
 
+/* ---- uneven batches of independent lattices ---- */
+#define LQCD_MAX_BATCH 16
+
+/* One lattice of a batch: its own gauge field, rhs count and mass.  psi and
+ * eta are full-lattice blocks in LQCD_LAYOUT2. */
+typedef struct {
+  lqcd_lattice lat;
+  const void* U;
+  const void* psi;
+  void* eta;
+  int32_t nrhs;
+  int32_t reserved;
+  double m0;
+} lqcd_problem;
+
+/* eta_k = D_k psi_k (or D_k^dagger psi_k) for every problem k in ONE
+ * persistent launch (the batched evaluation of Algorithm 1 over several
+ * lattices of different size and rhs count).  1 <= nprob <= LQCD_MAX_BATCH;
+ * all problems share the precision `prec`.  Same results as one dirac_apply
+ * per problem (same per-site arithmetic). */
+int dirac_apply_batch(int nprob, const lqcd_problem* probs, int prec, int flags, void* stream);
+
+/* Grid size of the persistent batch kernel (0 = four workgroups per CU). */
+int lqcd_set_batch_grid(int blocks);
+
+/* Autotuner for the persistent batch kernel: times grid sizes of 1, 2, 4, 8
+ * and 16 workgroups per CU on these problems (eta overwritten), keeps the
+ * fastest (lqcd_set_batch_grid) and returns it in best_grid (may be NULL). */
+int lqcd_autotune_batch(int nprob, const lqcd_problem* probs, int prec, int reps, int* best_grid, void* stream);
+
+/* Measured HBM ceiling (a STREAM-style probe, the paper's empirical memory
+ * ceiling of Sec. V-A, eq. (4)): kind 0 = copy b = a, 1 = triad
+ * a = b + s c, over n doubles per array (device buffers a, b, c of n doubles;
+ * c unused for copy).  Launches `reps` times and returns the mean time per
+ * launch in *ms.  Synchronises `stream`. */
+int lqcd_hbm_probe(int kind, double* a, double* b, const double* c, size_t n, int reps, double* ms, void* stream);
+
 /* Parameters of gmres_solve (Algorithm 2). */
 typedef struct {
   int32_t restart;       /* Krylov length m per cycle (restartLen); 1..64, default 30 */
@@ -119,7 +183,7 @@ typedef struct {
   double tol;            /* target ||b_i - D x_i|| <= tol ||b_i|| of the FULL system, per rhs */
   double inner_tol;      /* relative tolerance of each inner solve (modes 1, 2); 0 = default */
   int32_t max_outer;     /* cap on refinement steps (modes 1, 2), default 50 */
-  int32_t reserved;
+  int32_t dagger;        /* 1: solve D^dagger x = b instead (the adjoint solve of a gradient) */
 } lqcd_solver_params;
 
 /* Per-rhs results of gmres_solve (HOST memory, nrhs entries). */
@@ -151,6 +215,25 @@ size_t gmres_workspace_bytes(const lqcd_lattice* lat, int nrhs, const lqcd_solve
 int gmres_solve(const lqcd_lattice* lat, const void* U, const void* b, void* x, int nrhs,
                 double m0, int layout, const lqcd_solver_params* params, void* work,
                 size_t work_bytes, lqcd_rhs_stats* stats, void* stream);
+
+/* Gradient of a real loss with respect to the links through y = D psi
+ * (differentiation of the Sec. III-A.1 operator): with dL = Re <g, dy> and
+ * gradients of complex entries taken as dL/dRe + i dL/dIm,
+ *   G_mu(x) = coeff * sum_rhs sum_spin { [(1 - gamma_mu) g(x)] (x) psi(x+mu)^*
+ *                                        + psi(x) (x) [(1 + gamma_mu) g(x+mu)]^* }
+ * (colour outer products).  coeff = -1/2 gives dL/dU of an apply with
+ * upstream gradient g; for a solve x = D^-1 eta pass g = lambda = D^-dag dL/dx,
+ * psi = x and coeff = +1/2.  project = 1 returns instead the su(3) force
+ * TA(G U_mu(x)^dag), the steepest-ascent direction for U -> exp(h Q) U.
+ * U: FP64 gauge field (read only when project = 1); g, psi: FP64
+ * full-lattice blocks in `layout`; G: [4][V][3][3] FP64 output. */
+int link_force(const lqcd_lattice* lat, const void* U, const void* g, const void* psi, void* G, int nrhs,
+               int layout, double coeff, int project, void* stream);
+
+/* out[i] = sum over sites and components of conj(a_i) b_i for every rhs i
+ * (FP64 full-lattice blocks in `layout`; out: nrhs complex doubles, device). */
+int block_dot(const lqcd_lattice* lat, const void* a, const void* b, int nrhs, int layout, void* out,
+              void* stream);
 
 #ifdef __cplusplus
 }

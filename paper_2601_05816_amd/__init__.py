@@ -45,7 +45,23 @@ class SolverParams(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int32), ("max_restarts", ctypes.c_int32), ("eo", ctypes.c_int32),
                 ("mode", ctypes.c_int32), ("x_is_guess", ctypes.c_int32), ("fixed_iters", ctypes.c_int32),
                 ("tol", ctypes.c_double), ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("dagger", ctypes.c_int32)]
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("lat", Lattice), ("U", ctypes.c_void_p), ("psi", ctypes.c_void_p), ("eta", ctypes.c_void_p),
+                ("nrhs", ctypes.c_int32), ("reserved", ctypes.c_int32), ("m0", ctypes.c_double)]
+
+
+MAX_BATCH = 16
+
+
+class KernelConfig(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("tile_y", ctypes.c_int32), ("tile_z", ctypes.c_int32),
+                ("segments", ctypes.c_int32), ("nontemporal", ctypes.c_int32), ("ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class RhsStats(ctypes.Structure):
@@ -68,6 +84,24 @@ def load():
     lib.dirac_apply.argtypes = [lp, vp, vp, vp, i32, dbl, i32, i32, i32, vp]
     lib.dirac_apply_eo.argtypes = [lp, vp, vp, vp, i32, dbl, i32, i32, i32, vp]
     lib.lqcd_set_kernel_variant.argtypes = [i32, vp]
+    lib.dirac_apply_batch.argtypes = [i32, ctypes.POINTER(Problem), i32, i32, vp]
+    lib.dirac_apply_batch.restype = i32
+    lib.lqcd_set_batch_grid.argtypes = [i32]
+    lib.lqcd_set_batch_grid.restype = i32
+    lib.lqcd_set_kernel_config.argtypes = [ctypes.POINTER(KernelConfig)]
+    lib.lqcd_set_kernel_config.restype = i32
+    lib.lqcd_autotune.argtypes = [lp, vp, vp, vp, i32, i32, i32, i32, i32, ctypes.POINTER(KernelConfig), vp]
+    lib.lqcd_autotune.restype = i32
+    lib.lqcd_tune_save.argtypes = [ctypes.c_char_p]
+    lib.lqcd_tune_save.restype = i32
+    lib.lqcd_tune_load.argtypes = [ctypes.c_char_p]
+    lib.lqcd_tune_load.restype = i32
+    lib.lqcd_tune_clear.argtypes = []
+    lib.lqcd_tune_clear.restype = None
+    lib.lqcd_autotune_batch.argtypes = [i32, ctypes.POINTER(Problem), i32, i32, ctypes.POINTER(ctypes.c_int), vp]
+    lib.lqcd_autotune_batch.restype = i32
+    lib.lqcd_hbm_probe.argtypes = [i32, vp, vp, vp, ctypes.c_size_t, i32, ctypes.POINTER(ctypes.c_double), vp]
+    lib.lqcd_hbm_probe.restype = i32
     for name in ("lqcd_lattice_tables", "dirac_apply", "dirac_apply_eo", "lqcd_set_kernel_variant"):
         getattr(lib, name).restype = i32
     if hasattr(lib, "gmres_solve"):
@@ -78,6 +112,10 @@ def load():
         lib.gmres_solve.argtypes = [lp, vp, vp, vp, i32, dbl, i32, ctypes.POINTER(SolverParams), vp,
                                     ctypes.c_size_t, ctypes.POINTER(RhsStats), vp]
         lib.gmres_solve.restype = i32
+        lib.link_force.argtypes = [lp, vp, vp, vp, vp, i32, i32, dbl, i32, vp]
+        lib.link_force.restype = i32
+        lib.block_dot.argtypes = [lp, vp, vp, i32, i32, vp, vp]
+        lib.block_dot.restype = i32
     _lib = lib
     return lib
 
@@ -111,6 +149,27 @@ def set_kernel_variant(variant=0, pencil=None):
     if pencil is not None:
         arr = (ctypes.c_int32 * 3)(*[int(v) for v in pencil])
     _check(load().lqcd_set_kernel_variant(int(variant), arr))
+
+
+def set_kernel_config(variant=0, tile_y=0, tile_z=0, segments=0, nontemporal=0):
+    """Force a Wilson kernel configuration (variant 0 = automatic selection)."""
+    if variant == 0 and not (tile_y or tile_z or segments or nontemporal):
+        _check(load().lqcd_set_kernel_config(None))
+        return
+    c = KernelConfig(int(variant), int(tile_y), int(tile_z), int(segments), int(nontemporal), 0.0)
+    _check(load().lqcd_set_kernel_config(ctypes.byref(c)))
+
+
+def tune_save(path):
+    _check(load().lqcd_tune_save(str(path).encode()))
+
+
+def tune_load(path):
+    return _check(load().lqcd_tune_load(str(path).encode()))
+
+
+def tune_clear():
+    load().lqcd_tune_clear()
 
 
 # ------------------------------------------------------------- tensors
@@ -203,13 +262,14 @@ MODES = {"f64": 0, "ir-f32": 1, "ir-f16": 2}
 
 
 def solver_params(restart=30, max_restarts=200, eo=True, mode=0, tol=1e-10, inner_tol=0.0, max_outer=50,
-                  x_is_guess=False, fixed_iters=False):
+                  x_is_guess=False, fixed_iters=False, dagger=False):
     p = SolverParams()
     load().lqcd_solver_defaults(ctypes.byref(p))
     p.restart, p.max_restarts, p.eo = int(restart), int(max_restarts), int(bool(eo))
     p.mode = MODES[mode] if isinstance(mode, str) else int(mode)
     p.tol, p.inner_tol, p.max_outer = float(tol), float(inner_tol), int(max_outer)
     p.x_is_guess, p.fixed_iters = int(bool(x_is_guess)), int(bool(fixed_iters))
+    p.dagger = int(bool(dagger))
     return p
 
 
@@ -242,3 +302,96 @@ def gmres_solve(U, b, m0, layout=LAYOUT2, x0=None, work=None, **kw):
                                    float(m0), layout, ctypes.byref(p), work.data_ptr(), work.numel(), st, _stream()))
     stats = {k: np.array([getattr(s, k) for s in st]) for k, _ in RhsStats._fields_}
     return x, stats, rc
+
+
+def link_force(U, g, psi, coeff, layout=LAYOUT2, project=False, out=None):
+    """G_mu(x) = coeff sum_rhs sum_spin {[(1-g_mu) g(x)] (x) psi(x+mu)^* + psi(x) (x) [(1+g_mu) g(x+mu)]^*},
+    or the su(3) force TA(G U^dag) with project=True.  FP64 blocks."""
+    import torch
+
+    dims = _dims_of_links(U, F64)
+    nrhs, _ = _nrhs_of(g, F64, layout, 4)
+    out = torch.empty_like(U) if out is None else out
+    _check_device(U, g, psi, out)
+    _check(load().link_force(ctypes.byref(_lattice(dims)), U.data_ptr(), g.data_ptr(), psi.data_ptr(),
+                             out.data_ptr(), nrhs, layout, float(coeff), int(bool(project)), _stream()))
+    return out
+
+
+def block_dot(a, b, dims, layout=LAYOUT2):
+    """Per-rhs <a_i, b_i> (conjugate-linear in a) of two FP64 full-lattice blocks, as a complex128 tensor."""
+    import torch
+
+    nrhs, _ = _nrhs_of(a, F64, layout, 4)
+    out = torch.empty(nrhs, dtype=torch.complex128, device=a.device)
+    _check_device(a, b, out)
+    _check(load().block_dot(ctypes.byref(_lattice(dims)), a.data_ptr(), b.data_ptr(), nrhs, layout,
+                            out.data_ptr(), _stream()))
+    return out
+
+
+def dirac_apply_batch(problems, dagger=False, outs=None):
+    """eta_k = D_k psi_k for a list of (U_k, psi_k, m0_k) on independent lattices
+    (rhs-innermost blocks, one precision), in one persistent launch."""
+    import torch
+
+    if not 1 <= len(problems) <= MAX_BATCH:
+        raise ValueError(f"need 1..{MAX_BATCH} problems")
+    prec = _prec_of(problems[0][1])
+    arr = (Problem * len(problems))()
+    outs = [torch.empty_like(p[1]) for p in problems] if outs is None else outs
+    for k, ((U, psi, m0), eta) in enumerate(zip(problems, outs)):
+        if _prec_of(psi) != prec or _prec_of(U) != prec:
+            raise TypeError("all problems of a batch share one precision")
+        dims = _dims_of_links(U, prec)
+        nrhs, sdims = _nrhs_of(psi, prec, LAYOUT2, 4)
+        if tuple(sdims) != tuple(dims):
+            raise ValueError(f"problem {k}: spinor lattice {sdims} does not match {dims}")
+        _check_device(U, psi, eta)
+        arr[k].lat = _lattice(dims)
+        arr[k].U, arr[k].psi, arr[k].eta = U.data_ptr(), psi.data_ptr(), eta.data_ptr()
+        arr[k].nrhs, arr[k].m0 = nrhs, float(m0)
+    _check(load().dirac_apply_batch(len(problems), arr, prec, DAGGER if dagger else 0, _stream()))
+    return outs
+
+
+def set_batch_grid(blocks=0):
+    _check(load().lqcd_set_batch_grid(int(blocks)))
+
+
+def autotune(U, psi, eta, m0=0.0, layout=LAYOUT2, eo=False, reps=3):
+    """Time the candidate Wilson kernels on these buffers (eta overwritten) and
+    record the fastest for automatic selection.  Returns the winner as a dict."""
+    prec = _prec_of(psi)
+    dims = _dims_of_links(U, prec)
+    nrhs, _ = _nrhs_of(psi, prec, layout, 1 if eo else 4)
+    _check_device(U, psi, eta)
+    best = KernelConfig()
+    _check(load().lqcd_autotune(ctypes.byref(_lattice(dims)), U.data_ptr(), psi.data_ptr(), eta.data_ptr(), nrhs,
+                                prec, layout, int(bool(eo)), int(reps), ctypes.byref(best), _stream()))
+    return best.as_dict()
+
+
+def autotune_batch(problems, outs, reps=3):
+    """Pick the persistent grid size for dirac_apply_batch on these problems."""
+    prec = _prec_of(problems[0][1])
+    arr = (Problem * len(problems))()
+    for k, ((U, psi, m0), eta) in enumerate(zip(problems, outs)):
+        dims = _dims_of_links(U, prec)
+        nrhs, _ = _nrhs_of(psi, prec, LAYOUT2, 4)
+        arr[k].lat = _lattice(dims)
+        arr[k].U, arr[k].psi, arr[k].eta = U.data_ptr(), psi.data_ptr(), eta.data_ptr()
+        arr[k].nrhs, arr[k].m0 = nrhs, float(m0)
+    g = ctypes.c_int(0)
+    _check(load().lqcd_autotune_batch(len(problems), arr, prec, int(reps), ctypes.byref(g), _stream()))
+    return g.value
+
+
+def hbm_probe(a, b, c=None, kind="triad", reps=5):
+    """Mean time (ms) of a copy (b = a) or triad (a = b + s c) over float64 device tensors."""
+    n = a.numel()
+    ms = ctypes.c_double(0.0)
+    k = 0 if kind == "copy" else 1
+    _check(load().lqcd_hbm_probe(k, a.data_ptr(), b.data_ptr(), None if c is None else c.data_ptr(), n, int(reps),
+                                 ctypes.byref(ms), _stream()))
+    return ms.value

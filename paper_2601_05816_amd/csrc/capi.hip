@@ -87,18 +87,6 @@ int lqcd_lattice_tables(const lqcd_lattice* lat, int32_t* nbr, int32_t* eo_site)
   return LQCD_OK;
 }
 
-int lqcd_set_kernel_variant(int variant, const int32_t* pencil) {
-  if (variant < 0 || variant > 2) return fail(LQCD_ERR_ARG, "unknown kernel variant %d", variant);
-  if (pencil)
-    for (int i = 0; i < 3; ++i)
-      if (pencil[i] < 0) return fail(LQCD_ERR_ARG, "negative pencil parameter");
-  int p[3] = {0, 0, 0};
-  if (pencil)
-    for (int i = 0; i < 3; ++i) p[i] = pencil[i];
-  set_variant(variant, p);
-  return LQCD_OK;
-}
-
 int dirac_apply(const lqcd_lattice* lat, const void* U, const void* psi, void* eta, int nrhs, double m0,
                 int layout, int prec, int flags, void* stream) {
   int rc = check_lattice(lat);

@@ -88,6 +88,23 @@ __device__ __forceinline__ void st(h2_t* p, cx<float> a) {
   *p = v;
 }
 
+typedef double d2v_t __attribute__((ext_vector_type(2)));
+typedef float f2v_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void st_nt(double2* p, cx<double> a) {
+  d2v_t v = {a.re, a.im};
+  __builtin_nontemporal_store(v, (d2v_t*)p);
+}
+__device__ __forceinline__ void st_nt(float2* p, cx<float> a) {
+  f2v_t v = {a.re, a.im};
+  __builtin_nontemporal_store(v, (f2v_t*)p);
+}
+__device__ __forceinline__ void st_nt(h2_t* p, cx<float> a) {
+  h2_t v;
+  v.x = (_Float16)a.re;
+  v.y = (_Float16)a.im;
+  __builtin_nontemporal_store(v, p);
+}
+
 // ---------------------------------------------------------- block layout ---
 // Element (site, comp, rhs) of a spinor block with `nsites` sites, 12
 // components per site and nrhs right-hand sides.

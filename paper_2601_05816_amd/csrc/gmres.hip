@@ -180,6 +180,7 @@ struct Solver {
   lqcd_lattice lat;
   size_t V, nsite, nelem;
   int nrhs, m, eo, mode, plo;
+  bool dag;  // solve with D^dagger
   double m0, d;
   hipStream_t s;
   unsigned nblk;
@@ -243,11 +244,11 @@ struct Solver {
     const void* U = prec == LQCD_F64 ? U64 : Ulo;
     if (eo) {
       void* t = prec == LQCD_F64 ? tmp64 : tmplo;
-      hipError_t e = wilson_eo(&lat, U, in, nullptr, t, 1, nrhs, 0.0, 1.0, LQCD_LAYOUT2, prec, false, lv, s);
+      hipError_t e = wilson_eo(&lat, U, in, nullptr, t, 1, nrhs, 0.0, 1.0, LQCD_LAYOUT2, prec, dag, lv, s);
       if (e != hipSuccess) return e;
-      return wilson_eo(&lat, U, t, in, out, 0, nrhs, d, -0.25 / d, LQCD_LAYOUT2, prec, false, lv, s);
+      return wilson_eo(&lat, U, t, in, out, 0, nrhs, d, -0.25 / d, LQCD_LAYOUT2, prec, dag, lv, s);
     }
-    return wilson_full(&lat, U, in, out, nrhs, d, -0.5, LQCD_LAYOUT2, prec, false, s);
+    return wilson_full(&lat, U, in, out, nrhs, d, -0.5, LQCD_LAYOUT2, prec, dag, s);
   }
 
   // |x|^2 per rhs into nrm (scaled by sc)
@@ -378,6 +379,7 @@ static void setup(Solver& S, const lqcd_lattice* lat, int nrhs, const lqcd_solve
   S.m = p->restart;
   S.mode = p->mode;
   S.plo = p->mode == 1 ? LQCD_F32 : LQCD_F16;
+  S.dag = p->dagger != 0;
   S.nblk = reduce_grid(S.nelem);
 }
 
@@ -467,7 +469,7 @@ int gmres_solve(const lqcd_lattice* lat, const void* U, const void* b, void* x, 
     }
     if (S.eo) {
       // b'_e = b_e - D_eo D_oo^{-1} b_o = b_e + (1/2) H_eo b_o / (4+m0)
-      HIPCHK(wilson_eo(&S.lat, U, S.bo, S.be, S.bp, 0, nrhs, 1.0, 0.5 / d, LQCD_LAYOUT2, LQCD_F64, false, nullptr, s));
+      HIPCHK(wilson_eo(&S.lat, U, S.bo, S.be, S.bp, 0, nrhs, 1.0, 0.5 / d, LQCD_LAYOUT2, LQCD_F64, S.dag, nullptr, s));
     }
     if (S.mode == 0) {
       rc = run_gmres(S, LQCD_F64, S.xe, S.bp, S.bref, tol, params->max_restarts, fixed, x_zero, 1.0, hs, pinned);
@@ -512,20 +514,20 @@ int gmres_solve(const lqcd_lattice* lat, const void* U, const void* b, void* x, 
     double nr_e_scale = 1.0;
     if (S.eo) {
       // x_o = (b_o + (1/2) H_oe x_e) / (4+m0)
-      HIPCHK(wilson_eo(&S.lat, U, S.xe, S.bo, S.xo, 1, nrhs, 1.0 / d, 0.5 / d, LQCD_LAYOUT2, LQCD_F64, false, nullptr,
+      HIPCHK(wilson_eo(&S.lat, U, S.xe, S.bo, S.xo, 1, nrhs, 1.0 / d, 0.5 / d, LQCD_LAYOUT2, LQCD_F64, S.dag, nullptr,
                        s));
       // r_e = b_e - [(4+m0) x_e - (1/2) H_eo x_o]
-      HIPCHK(wilson_eo(&S.lat, U, S.xo, S.xe, t1, 0, nrhs, d, -0.5, LQCD_LAYOUT2, LQCD_F64, false, nullptr, s));
+      HIPCHK(wilson_eo(&S.lat, U, S.xo, S.xe, t1, 0, nrhs, d, -0.5, LQCD_LAYOUT2, LQCD_F64, S.dag, nullptr, s));
       HIPCHK(b_minus_y(LQCD_F64, S.be, t1, nel, nrhs, nullptr, S.part, S.nblk, s));
       HIPCHK(reduce_parts(S.part, S.nblk, 1, nrhs, nr_e_scale, S.hcol, s));
-      HIPCHK(wilson_eo(&S.lat, U, S.xe, S.xo, S.tmp64, 1, nrhs, d, -0.5, LQCD_LAYOUT2, LQCD_F64, false, nullptr, s));
+      HIPCHK(wilson_eo(&S.lat, U, S.xe, S.xo, S.tmp64, 1, nrhs, d, -0.5, LQCD_LAYOUT2, LQCD_F64, S.dag, nullptr, s));
       HIPCHK(b_minus_y(LQCD_F64, S.bo, S.tmp64, nel, nrhs, nullptr, S.part, S.nblk, s));
       HIPCHK(reduce_parts(S.part, S.nblk, 1, nrhs, 1.0, S.nrm, s));
       HIPCHK(hipMemcpyAsync(S.part, S.hcol, nrhs * sizeof(zd), hipMemcpyDeviceToDevice, s));
       HIPCHK(hipMemcpyAsync(S.part + nrhs, S.nrm, nrhs * sizeof(zd), hipMemcpyDeviceToDevice, s));
       HIPCHK(reduce_parts(S.part, 2, 1, nrhs, 1.0, S.nrm, s));
     } else {
-      HIPCHK(wilson_full(&S.lat, U, S.xe, t1, nrhs, d, -0.5, LQCD_LAYOUT2, LQCD_F64, false, s));
+      HIPCHK(wilson_full(&S.lat, U, S.xe, t1, nrhs, d, -0.5, LQCD_LAYOUT2, LQCD_F64, S.dag, s));
       HIPCHK(b_minus_y(LQCD_F64, S.be, t1, nel, nrhs, nullptr, S.part, S.nblk, s));
       HIPCHK(reduce_parts(S.part, S.nblk, 1, nrhs, 1.0, S.nrm, s));
     }

@@ -18,15 +18,25 @@ hipError_t wilson_eo(const lqcd_lattice* lat, const void* U, const void* in, con
                      int nrhs, double alpha, double beta, int layout, int prec, bool dagger, const int* live,
                      hipStream_t s);
 
+// Kernel configuration of one apply.  variant: 1 one (site, rhs) per work
+// item, 2 time-streaming pencils with links staged in LDS, 3 pencils without
+// staging; ty, tz, nseg: pencil tile and t segments (0 = automatic).
+struct kcfg {
+  int variant, ty, tz, nseg, nt;  // nt: non-temporal output stores (pencil variants)
+};
+enum { KIND_FULL = 0, KIND_EO = 1 };
+
 // Time-streaming ("pencil") variants of the two kernels above (pencil.hip).
 hipError_t wilson_full_pencil(const lqcd_lattice* lat, const void* U, const void* psi, void* eta, int nrhs,
-                              double diag, double hopc, int layout, int prec, bool dagger, hipStream_t s);
+                              double diag, double hopc, int layout, int prec, bool dagger, const kcfg& c,
+                              hipStream_t s);
 hipError_t wilson_eo_pencil(const lqcd_lattice* lat, const void* U, const void* in, const void* xin, void* out,
                             int p, int nrhs, double alpha, double beta, int layout, int prec, bool dagger,
-                            const int* live, hipStream_t s);
-// Kernel choice: 0 automatic, 1 one site per work item, 2 pencils; pencil[3]
-// = (tile Y, tile Z, t segments) overrides, 0 = automatic (pencil may be null).
+                            const int* live, const kcfg& c, hipStream_t s);
+
+// Configuration for an apply (tune.hip): the process-wide forced setting if
+// any, else the autotuner's entry for these arguments, else the default.
+kcfg choose_cfg(int kind, const lqcd_lattice* lat, int nrhs, int prec, int layout);
 void set_variant(int v, const int* pencil);
-int get_variant();
 
 }  // namespace lq

@@ -29,6 +29,7 @@ struct pencil_geo {
   int nseg, Lt;      // t segments and their length
   int bpt;           // workgroups per tile and segment
   int ntiles;
+  int nt;            // non-temporal output stores
 };
 
 // (column coordinates, rhs, t0) of this work item, or false if idle.
@@ -156,13 +157,164 @@ __global__ __launch_bounds__(256) void k_wilson_full_p(const typename prec_trait
     const size_t s1 = (size_t)t1 * S0 + c0;
     spinor<R> p1 = load_spinor<S, R>(psi, blk<LAYOUT>::base(s1, rhs, V, nrhs), cs);
     add_hop<0, -SG, false, S, R>(acc, p1, U0 + site * 9, hopc);
-    store_spinor<S, R>(eta, blk<LAYOUT>::base(site, rhs, V, nrhs), cs, acc);
+    if (pg.nt) store_spinor_nt<S, R>(eta, blk<LAYOUT>::base(site, rhs, V, nrhs), cs, acc);
+    else store_spinor<S, R>(eta, blk<LAYOUT>::base(site, rhs, V, nrhs), cs, acc);
     if (it + 1 < pg.Lt) {
 #pragma unroll
       for (int i = 0; i < 12; ++i) acc.c[i / 3][i % 3] = scale(diag, p1.c[i / 3][i % 3]);
       reconstruct<0, SG>(acc, hscale(hopc, colour_mul<true>(U0 + site * 9, hplus)));
       hplus = project<0, SG>(p1);
     }
+  }
+}
+
+// ------------------------------------------- full lattice, links via LDS
+// Same pencil walk; the links of a time step are fetched once per wavefront
+// with coalesced loads into a wave-private LDS slice and read from there by
+// all lanes of a column (the rhs that share the column), instead of one
+// vector-memory load per lane.  Rhs-fastest layouts only; NCW bounds the
+// number of columns one wavefront touches (64 / nrhs + 1).
+// Link slots per column and step: 0 U_0(x), 1..3 U_mu(x) (mu = 1 z, 2 y, 3 x),
+// 4..6 U_mu(x - mu).
+template <int PREC, int LAYOUT, int SG, int NCW>
+__global__ __launch_bounds__(256) void k_wilson_full_pl(const typename prec_traits<PREC>::store* __restrict__ U,
+                                                        const typename prec_traits<PREC>::store* __restrict__ psi,
+                                                        typename prec_traits<PREC>::store* __restrict__ eta,
+                                                        pencil_geo pg, int nrhs,
+                                                        typename prec_traits<PREC>::real diag,
+                                                        typename prec_traits<PREC>::real hopc) {
+  typedef typename prec_traits<PREC>::store S;
+  typedef typename prec_traits<PREC>::real R;
+  __shared__ S lds_all[4][NCW * 63];
+  const unsigned b = blockIdx.x;
+  const unsigned k8 = b & 7u, ib = b >> 3;
+  const unsigned u = ib / pg.bpt, q = ib % pg.bpt;
+  const unsigned grp = u / pg.nseg, seg = u % pg.nseg;
+  const unsigned tile = grp * 8u + k8;
+  if (tile >= (unsigned)pg.ntiles) return;  // whole workgroup idle
+  const unsigned CT = (unsigned)pg.TX * pg.TY * pg.TZ;
+  const unsigned wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+  const unsigned tin = q * blockDim.x + threadIdx.x;
+  const unsigned tw0 = q * blockDim.x + wave * 64u;
+  if (tw0 >= CT * (unsigned)nrhs) return;  // whole wavefront idle (no LDS sharing across waves)
+  const unsigned colw0 = tw0 / nrhs;
+  unsigned colw1 = (tw0 + 63u) / nrhs;
+  if (colw1 > CT - 1) colw1 = CT - 1;
+  const int ncw = (int)(colw1 - colw0 + 1);
+  const bool active = tin < CT * (unsigned)nrhs;
+  const unsigned col = active ? tin / nrhs : colw0;
+  const int rhs = (int)(tin % nrhs);
+  const int cl = (int)(col - colw0);
+  S* lds = lds_all[wave];
+
+  const int T = pg.n[0], NZ = pg.n[1], NY = pg.n[2], NX = pg.n[3];
+  const int tx = tile % pg.NTX, ty = (tile / pg.NTX) % pg.NTY, tz = tile / (pg.NTX * pg.NTY);
+  const int t0 = (int)seg * pg.Lt;
+  const size_t V = pg.V, S0 = (size_t)NZ * NY * NX;
+  const int cs = blk<LAYOUT>::cstride(nrhs);
+  auto colsite = [&](unsigned c, int& x, int& y, int& z) {
+    x = tx * pg.TX + (int)(c % pg.TX);
+    y = ty * pg.TY + (int)((c / pg.TX) % pg.TY);
+    z = tz * pg.TZ + (int)(c / (pg.TX * pg.TY));
+  };
+  int x, y, z;
+  colsite(col, x, y, z);
+  const size_t c0 = ((size_t)z * NY + y) * NX + x;
+  const size_t cxf = c0 - x + (x + 1 < NX ? x + 1 : 0), cxb = c0 - x + (x > 0 ? x - 1 : NX - 1);
+  const size_t cyf = c0 + (size_t)((y + 1 < NY ? y + 1 : 0) - y) * NX;
+  const size_t cyb = c0 + (size_t)((y > 0 ? y - 1 : NY - 1) - y) * NX;
+  const size_t czf = c0 + (size_t)((z + 1 < NZ ? z + 1 : 0) - z) * NY * NX;
+  const size_t czb = c0 + (size_t)((z > 0 ? z - 1 : NZ - 1) - z) * NY * NX;
+  const S* U0 = U;
+
+  // stage the 7 links of every column of this wavefront at time t
+  auto stage = [&](int t) {
+    const size_t toff = (size_t)t * S0;
+    const int nel = ncw * 63;
+    for (int e = (int)lane; e < nel; e += 64) {
+      const int slot = e / (9 * ncw);
+      const int rem = e - slot * 9 * ncw;
+      const int c = rem / 9, kk = rem - c * 9;
+      int xx, yy, zz;
+      colsite(colw0 + (unsigned)c, xx, yy, zz);
+      size_t sc = ((size_t)zz * NY + yy) * NX + xx;
+      int mu = slot;
+      if (slot >= 4) {
+        mu = slot - 3;
+        if (mu == 1) sc += (size_t)((zz > 0 ? zz - 1 : NZ - 1) - zz) * NY * NX;
+        else if (mu == 2) sc += (size_t)((yy > 0 ? yy - 1 : NY - 1) - yy) * NX;
+        else sc += (size_t)((xx > 0 ? xx - 1 : NX - 1) - xx);
+      }
+      lds[(c * 7 + slot) * 9 + kk] = U[((size_t)mu * V + toff + sc) * 9 + kk];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
+  const S* L = lds + cl * 7 * 9;
+
+  spinor<R> acc;
+  half_spinor<R> hplus;
+  {
+    const int tm = t0 > 0 ? t0 - 1 : T - 1;
+    const size_t sm = (size_t)tm * S0 + c0;
+    spinor<R> pm = load_spinor<S, R>(psi, blk<LAYOUT>::base(sm, rhs, V, nrhs), cs);
+#pragma unroll
+    for (int i = 0; i < 12; ++i) acc.c[i / 3][i % 3] = {R(0), R(0)};
+    add_hop<0, SG, true, S, R>(acc, pm, U0 + sm * 9, hopc);
+    const size_t s0 = (size_t)t0 * S0 + c0;
+    spinor<R> p0 = load_spinor<S, R>(psi, blk<LAYOUT>::base(s0, rhs, V, nrhs), cs);
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+      cx<R> a = acc.c[i / 3][i % 3], bb = p0.c[i / 3][i % 3];
+      acc.c[i / 3][i % 3] = {fma(diag, bb.re, a.re), fma(diag, bb.im, a.im)};
+    }
+    hplus = project<0, SG>(p0);
+  }
+  for (int it = 0; it < pg.Lt; ++it) {
+    const int t = t0 + it;
+    const size_t toff = (size_t)t * S0;
+    const size_t site = toff + c0;
+    stage(t);
+    {
+      spinor<R> p = load_spinor<S, R>(psi, blk<LAYOUT>::base(toff + cxf, rhs, V, nrhs), cs);
+      add_hop<3, -SG, false, S, R>(acc, p, L + 3 * 9, hopc);
+    }
+    {
+      spinor<R> p = load_spinor<S, R>(psi, blk<LAYOUT>::base(toff + cxb, rhs, V, nrhs), cs);
+      add_hop<3, SG, true, S, R>(acc, p, L + 6 * 9, hopc);
+    }
+    {
+      spinor<R> p = load_spinor<S, R>(psi, blk<LAYOUT>::base(toff + cyf, rhs, V, nrhs), cs);
+      add_hop<2, -SG, false, S, R>(acc, p, L + 2 * 9, hopc);
+    }
+    {
+      spinor<R> p = load_spinor<S, R>(psi, blk<LAYOUT>::base(toff + cyb, rhs, V, nrhs), cs);
+      add_hop<2, SG, true, S, R>(acc, p, L + 5 * 9, hopc);
+    }
+    {
+      spinor<R> p = load_spinor<S, R>(psi, blk<LAYOUT>::base(toff + czf, rhs, V, nrhs), cs);
+      add_hop<1, -SG, false, S, R>(acc, p, L + 1 * 9, hopc);
+    }
+    {
+      spinor<R> p = load_spinor<S, R>(psi, blk<LAYOUT>::base(toff + czb, rhs, V, nrhs), cs);
+      add_hop<1, SG, true, S, R>(acc, p, L + 4 * 9, hopc);
+    }
+    const int t1 = t + 1 < T ? t + 1 : 0;
+    const size_t s1 = (size_t)t1 * S0 + c0;
+    spinor<R> p1 = load_spinor<S, R>(psi, blk<LAYOUT>::base(s1, rhs, V, nrhs), cs);
+    add_hop<0, -SG, false, S, R>(acc, p1, L, hopc);
+    if (active) {
+      if (pg.nt) store_spinor_nt<S, R>(eta, blk<LAYOUT>::base(site, rhs, V, nrhs), cs, acc);
+      else store_spinor<S, R>(eta, blk<LAYOUT>::base(site, rhs, V, nrhs), cs, acc);
+    }
+    if (it + 1 < pg.Lt) {
+#pragma unroll
+      for (int i = 0; i < 12; ++i) acc.c[i / 3][i % 3] = scale(diag, p1.c[i / 3][i % 3]);
+      reconstruct<0, SG>(acc, hscale(hopc, colour_mul<true>(L, hplus)));
+      hplus = project<0, SG>(p1);
+    }
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -270,20 +422,12 @@ __global__ __launch_bounds__(256) void k_wilson_eo_p(const typename prec_traits<
 #pragma unroll
       for (int i = 0; i < 12; ++i) acc.c[i / 3][i % 3] = scale(beta, acc.c[i / 3][i % 3]);
     }
-    store_spinor<S, R>(out, me, cs, acc);
+    if (pg.nt) store_spinor_nt<S, R>(out, me, cs, acc);
+    else store_spinor<S, R>(out, me, cs, acc);
   }
 }
 
 // ------------------------------------------------------------ configuration
-static int g_variant = 0;                 // 0 auto, 1 site kernel, 2 pencil kernel
-static int g_pencil[3] = {0, 0, 0};       // TY, TZ, nseg overrides (0 = automatic)
-
-void set_variant(int v, const int* pencil) {
-  g_variant = v;
-  for (int i = 0; i < 3; ++i) g_pencil[i] = pencil ? pencil[i] : 0;
-}
-int get_variant() { return g_variant; }
-
 static int largest_divisor_at_most(int n, int cap) {
   if (cap < 1) cap = 1;
   for (int d = cap < n ? cap : n; d >= 1; --d)
@@ -293,8 +437,9 @@ static int largest_divisor_at_most(int n, int cap) {
 
 // Tile: all of X, then as much of Y and Z as one XCD keeps resident (about
 // 16384 work items); segments: enough work items for several waves of
-// residency on the whole chip.
-static pencil_geo make_pencil(const lqcd_lattice* lat, int nrhs, bool eo) {
+// residency on the whole chip.  Entries of c that are > 0 and divide the
+// lattice override the automatic choice.
+static pencil_geo make_pencil(const lqcd_lattice* lat, int nrhs, bool eo, const kcfg& c) {
   pencil_geo pg;
   for (int i = 0; i < 4; ++i) pg.n[i] = lat->dims[i];
   pg.V = (size_t)pg.n[0] * pg.n[1] * pg.n[2] * pg.n[3];
@@ -303,10 +448,8 @@ static pencil_geo make_pencil(const lqcd_lattice* lat, int nrhs, bool eo) {
   const int target_cols = (16384 / nrhs) > 0 ? 16384 / nrhs : 1;
   int rest = target_cols / pg.TX;
   if (rest < 1) rest = 1;
-  int TY = g_pencil[0] > 0 ? g_pencil[0] : largest_divisor_at_most(NY, rest);
-  int TZ = g_pencil[1] > 0 ? g_pencil[1] : largest_divisor_at_most(NZ, rest / TY);
-  if (NY % TY) TY = 1;
-  if (NZ % TZ) TZ = 1;
+  int TY = (c.ty > 0 && NY % c.ty == 0) ? c.ty : largest_divisor_at_most(NY, rest);
+  int TZ = (c.tz > 0 && NZ % c.tz == 0) ? c.tz : largest_divisor_at_most(NZ, rest / TY);
   pg.TY = TY;
   pg.TZ = TZ;
   pg.NTX = 1;
@@ -315,8 +458,8 @@ static pencil_geo make_pencil(const lqcd_lattice* lat, int nrhs, bool eo) {
   pg.ntiles = pg.NTY * pg.NTZ;
   const size_t cols = (size_t)pg.TX * NY * NZ;
   int nseg = 1;
-  if (g_pencil[2] > 0 && T % g_pencil[2] == 0) {
-    nseg = g_pencil[2];
+  if (c.nseg > 0 && T % c.nseg == 0) {
+    nseg = c.nseg;
   } else {
     const size_t want = 524288;
     while (nseg < T && cols * (size_t)nrhs * nseg < want) {
@@ -329,6 +472,7 @@ static pencil_geo make_pencil(const lqcd_lattice* lat, int nrhs, bool eo) {
   pg.Lt = T / nseg;
   const size_t items = (size_t)pg.TX * TY * TZ * nrhs;
   pg.bpt = (int)((items + 255) / 256);
+  pg.nt = c.nt;
   return pg;
 }
 
@@ -339,20 +483,33 @@ static unsigned pencil_blocks(const pencil_geo& pg) {
 
 template <int PREC, int LAYOUT, int SG>
 static void launch_full_p(const lqcd_lattice* lat, const void* U, const void* psi, void* eta, int nrhs, double diag,
-                          double hopc, hipStream_t s) {
+                          double hopc, const kcfg& c, hipStream_t s) {
   typedef typename prec_traits<PREC>::store S;
   typedef typename prec_traits<PREC>::real R;
-  pencil_geo pg = make_pencil(lat, nrhs, false);
+  pencil_geo pg = make_pencil(lat, nrhs, false, c);
+  if (LAYOUT != LQCD_RHS_OUTER && c.variant == 2 && nrhs >= 4) {
+    const dim3 grid(pencil_blocks(pg)), blk(256);
+    if (nrhs >= 16)
+      hipLaunchKernelGGL((k_wilson_full_pl<PREC, LAYOUT, SG, 5>), grid, blk, 0, s, (const S*)U, (const S*)psi,
+                         (S*)eta, pg, nrhs, (R)diag, (R)hopc);
+    else if (nrhs >= 8)
+      hipLaunchKernelGGL((k_wilson_full_pl<PREC, LAYOUT, SG, 9>), grid, blk, 0, s, (const S*)U, (const S*)psi,
+                         (S*)eta, pg, nrhs, (R)diag, (R)hopc);
+    else
+      hipLaunchKernelGGL((k_wilson_full_pl<PREC, LAYOUT, SG, 17>), grid, blk, 0, s, (const S*)U, (const S*)psi,
+                         (S*)eta, pg, nrhs, (R)diag, (R)hopc);
+    return;
+  }
   hipLaunchKernelGGL((k_wilson_full_p<PREC, LAYOUT, SG>), dim3(pencil_blocks(pg)), dim3(256), 0, s, (const S*)U,
                      (const S*)psi, (S*)eta, pg, nrhs, (R)diag, (R)hopc);
 }
 
 template <int PREC, int LAYOUT, int SG>
 static void launch_eo_p(const lqcd_lattice* lat, const void* U, const void* in, const void* xin, void* out, int p,
-                        int nrhs, double alpha, double beta, const int* live, hipStream_t s) {
+                        int nrhs, double alpha, double beta, const int* live, const kcfg& c, hipStream_t s) {
   typedef typename prec_traits<PREC>::store S;
   typedef typename prec_traits<PREC>::real R;
-  pencil_geo pg = make_pencil(lat, nrhs, true);
+  pencil_geo pg = make_pencil(lat, nrhs, true, c);
   hipLaunchKernelGGL((k_wilson_eo_p<PREC, LAYOUT, SG>), dim3(pencil_blocks(pg)), dim3(256), 0, s, (const S*)U,
                      (const S*)in, (const S*)xin, (S*)out, pg, p, nrhs, (R)alpha, (R)beta, live);
 }
@@ -375,15 +532,16 @@ static void launch_eo_p(const lqcd_lattice* lat, const void* U, const void* in, 
   } while (0)
 
 hipError_t wilson_full_pencil(const lqcd_lattice* lat, const void* U, const void* psi, void* eta, int nrhs,
-                              double diag, double hopc, int layout, int prec, bool dagger, hipStream_t s) {
-  LQ_DISPATCH(prec, layout, (dagger ? 1 : 0), launch_full_p, lat, U, psi, eta, nrhs, diag, hopc, s);
+                              double diag, double hopc, int layout, int prec, bool dagger, const kcfg& c,
+                              hipStream_t s) {
+  LQ_DISPATCH(prec, layout, (dagger ? 1 : 0), launch_full_p, lat, U, psi, eta, nrhs, diag, hopc, c, s);
   return hipGetLastError();
 }
 
 hipError_t wilson_eo_pencil(const lqcd_lattice* lat, const void* U, const void* in, const void* xin, void* out,
                             int p, int nrhs, double alpha, double beta, int layout, int prec, bool dagger,
-                            const int* live, hipStream_t s) {
-  LQ_DISPATCH(prec, layout, (dagger ? 1 : 0), launch_eo_p, lat, U, in, xin, out, p, nrhs, alpha, beta, live, s);
+                            const int* live, const kcfg& c, hipStream_t s) {
+  LQ_DISPATCH(prec, layout, (dagger ? 1 : 0), launch_eo_p, lat, U, in, xin, out, p, nrhs, alpha, beta, live, c, s);
   return hipGetLastError();
 }
 

@@ -1,0 +1,62 @@
+// STREAM-style HBM probe: the empirical memory ceiling against which the
+// paper measures its kernels (Sec. V-A, eq. (4): STREAM Triad bandwidth times
+// arithmetic intensity).  Copy and triad over double arrays with 16-byte
+// vector accesses and a grid-stride loop sized to the chip.
+#include "common.h"
+
+namespace lq {
+int fail(int code, const char* fmt, ...);
+int hip_status(hipError_t e, const char* what);
+
+__global__ __launch_bounds__(256) void k_copy(const double2* __restrict__ a, double2* __restrict__ b, size_t n2) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += (size_t)gridDim.x * blockDim.x)
+    b[i] = a[i];
+}
+
+__global__ __launch_bounds__(256) void k_triad(double2* __restrict__ a, const double2* __restrict__ b,
+                                               const double2* __restrict__ c, double s, size_t n2) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += (size_t)gridDim.x * blockDim.x) {
+    const double2 x = b[i], y = c[i];
+    a[i] = make_double2(fma(s, y.x, x.x), fma(s, y.y, x.y));
+  }
+}
+}  // namespace lq
+
+using namespace lq;
+
+extern "C" int lqcd_hbm_probe(int kind, double* a, double* b, const double* c, size_t n, int reps, double* ms,
+                              void* stream) {
+  if (!a || !b || (kind == 1 && !c) || !ms || (n & 1) || n == 0)
+    return fail(LQCD_ERR_ARG, "lqcd_hbm_probe: bad arguments (n must be even and > 0)");
+  if (kind != 0 && kind != 1) return fail(LQCD_ERR_ARG, "lqcd_hbm_probe: kind must be 0 (copy) or 1 (triad)");
+  if (reps < 1) reps = 5;
+  hipStream_t s = (hipStream_t)stream;
+  int dev = 0, ncu = 256;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  const size_t n2 = n / 2;
+  size_t nb = (size_t)ncu * 8;
+  if (nb * 256 > n2) nb = (n2 + 255) / 256;
+  auto launch = [&]() {
+    if (kind == 0)
+      hipLaunchKernelGGL(k_copy, dim3((unsigned)nb), dim3(256), 0, s, (const double2*)a, (double2*)b, n2);
+    else
+      hipLaunchKernelGGL(k_triad, dim3((unsigned)nb), dim3(256), 0, s, (double2*)a, (const double2*)b,
+                         (const double2*)c, 3.0, n2);
+  };
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(LQCD_ERR_HIP, "lqcd_hbm_probe: event creation failed");
+  launch();
+  (void)hipEventRecord(e0, s);
+  for (int r = 0; r < reps; ++r) launch();
+  (void)hipEventRecord(e1, s);
+  hipError_t e = hipEventSynchronize(e1);
+  float t = 0.f;
+  (void)hipEventElapsedTime(&t, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return hip_status(e, "lqcd_hbm_probe");
+  *ms = t / reps;
+  return hip_status(hipGetLastError(), "lqcd_hbm_probe launch");
+}

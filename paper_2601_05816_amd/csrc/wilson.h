@@ -99,6 +99,14 @@ __device__ __forceinline__ void store_spinor(S* __restrict__ p, size_t base, int
   for (int i = 0; i < 12; ++i) st(p + base + (size_t)i * cs, v.c[i / 3][i % 3]);
 }
 
+// Same, with non-temporal stores: the output is not read again by the
+// kernel, so it should not displace reusable neighbour spinors from L2.
+template <typename S, typename R>
+__device__ __forceinline__ void store_spinor_nt(S* __restrict__ p, size_t base, int cs, const spinor<R>& v) {
+#pragma unroll
+  for (int i = 0; i < 12; ++i) st_nt(p + base + (size_t)i * cs, v.c[i / 3][i % 3]);
+}
+
 // One direction mu: forward neighbour (block offset fb, link U_mu(x) at uf)
 // and backward neighbour (block offset bb, link U_mu(x-mu) at ub).
 // SG = +1 for D, -1 for D^dagger.

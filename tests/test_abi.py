@@ -54,3 +54,20 @@ def test_invalid_arguments_rejected_on_host():
     assert lib.dirac_apply_eo(ctypes.byref(good), 1, 1, 1, 2, -4.0, lq.LAYOUT2, lq.F64, 0, None) == -7
     nbr = np.empty((1, 8), dtype=np.int32)
     assert lib.lqcd_lattice_tables(ctypes.byref(bad), nbr.ctypes.data, None) == -2
+
+
+def test_tune_table_roundtrip(tmp_path):
+    """The autotuner's table is plain text; loading skips malformed lines."""
+    lib = lq.load()
+    lq.tune_clear()
+    p = tmp_path / "tune.txt"
+    p.write_text("# header\n0 64 32 32 32 16 0 2 : 2 4 4 1 1 4.8\nnot a line\n1 8 8 8 8 4 1 2 : 9 0 0 0 0 1.0\n")
+    assert lq.tune_load(p) == 1
+    q = tmp_path / "out.txt"
+    lq.tune_save(q)
+    lines = [l for l in q.read_text().splitlines() if not l.startswith("#")]
+    assert lines == ["0 64 32 32 32 16 0 2 : 2 4 4 1 1 4.800000"]
+    lq.tune_clear()
+    lq.set_kernel_config(0)
+    with pytest.raises(lq.LqcdError):
+        lq.set_kernel_config(7)

@@ -16,6 +16,14 @@ from oracle import dirac, evenodd, geometry
 from helpers import from_dev, from_layout_np, rel_err_per_rhs, rounded, to_dev, to_layout_np
 
 pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(params=[1, 2, 3], ids=["site", "pencil_lds", "pencil"], autouse=True)
+def kernel_variant(request, gpu_lib):
+    """Run every apply test with both Wilson kernel variants."""
+    gpu_lib.set_kernel_variant(request.param)
+    yield request.param
+    gpu_lib.set_kernel_variant(0)
 TOL = {lq.F64: 1e-12, lq.F32: 1e-5, lq.F16: 1e-3}
 LAYOUTS = [lq.RHS_OUTER, lq.LAYOUT1, lq.LAYOUT2]
 
@@ -150,3 +158,51 @@ def test_full_size_pure_gauge_plane_waves(gpu_lib):
     got2 = np.moveaxis(out2.reshape(-1, 4, 3, nrhs)[torch.from_numpy(few).to("cuda")].cpu().numpy(), -1, 0)
     want2 = dirac.apply_dw_sites(U, psi2, m0, few)
     assert np.all(rel_err_per_rhs(got2, want2) <= TOL[lq.F64])
+
+
+@pytest.mark.parametrize("pencil", [(1, 1, 1), (2, 1, 3), (1, 2, 6), (3, 2, 2), (0, 0, 12)])
+def test_pencil_tilings(gpu_lib, kernel_variant, pencil):
+    """Every tile shape and segment count gives the same result (the mapping
+    of work items to columns, rhs and t segments is a bijection)."""
+    if kernel_variant == 1:
+        pytest.skip("pencil parameters apply to the pencil kernels")
+    gpu_lib.set_kernel_variant(kernel_variant, pencil)
+    dims = (12, 4, 6, 4)
+    U = syn.gauge_field(dims, "haar", config=9)
+    psi = syn.spinor_block(dims, 5, config=9)
+    for layout in LAYOUTS:
+        got = _apply_gpu(U, psi, 0.2, layout, lq.F64)
+        assert np.all(rel_err_per_rhs(got, dirac.apply_dw(U, psi, 0.2)) <= TOL[lq.F64])
+        psi_e = geometry.to_half(psi, dims, 0)
+        got = _apply_eo_gpu(U, psi_e, 0.2, layout, lq.F64)
+        assert np.all(rel_err_per_rhs(got, evenodd.apply_schur(U, psi_e, 0.2)) <= TOL[lq.F64])
+
+
+@pytest.mark.parametrize("nt", [0, 1])
+def test_nontemporal_stores_and_autotuned_choice(gpu_lib, kernel_variant, nt):
+    """Non-temporal output stores, and whatever configuration the autotuner
+    records, give the oracle's result."""
+    import torch
+
+    if kernel_variant == 1:
+        pytest.skip("covered once")
+    dims = (8, 4, 6, 4)
+    U = syn.gauge_field(dims, "near_identity", config=10)
+    psi = syn.spinor_block(dims, 16, config=10)
+    want = dirac.apply_dw(U, psi, -0.05)
+    gpu_lib.set_kernel_config(kernel_variant, 0, 0, 0, nt)
+    got = _apply_gpu(U, psi, -0.05, lq.LAYOUT2, lq.F64)
+    assert np.all(rel_err_per_rhs(got, want) <= TOL[lq.F64])
+    psi_e = geometry.to_half(psi, dims, 0)
+    got = _apply_eo_gpu(U, psi_e, -0.05, lq.LAYOUT2, lq.F64)
+    assert np.all(rel_err_per_rhs(got, evenodd.apply_schur(U, psi_e, -0.05)) <= TOL[lq.F64])
+    # automatic selection after tuning this exact problem
+    gpu_lib.set_kernel_config(0)
+    gpu_lib.tune_clear()
+    Ud = to_dev(U, lq.F64)
+    pd = to_dev(to_layout_np(psi, lq.LAYOUT2), lq.F64)
+    best = gpu_lib.autotune(Ud, pd, torch.empty_like(pd), layout=lq.LAYOUT2, reps=1)
+    assert best["variant"] in (1, 2, 3) and best["ms"] > 0
+    got = from_layout_np(from_dev(lq.dirac_apply(Ud, pd, -0.05, layout=lq.LAYOUT2), lq.F64), lq.LAYOUT2, 4)
+    assert np.all(rel_err_per_rhs(got, want) <= TOL[lq.F64])
+    gpu_lib.tune_clear()

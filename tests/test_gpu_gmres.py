@@ -159,3 +159,16 @@ def test_errors(gpu_lib):
     rc = lq.load().gmres_solve(ctypes.byref(lq._lattice(dims)), U.data_ptr(), b.data_ptr(), b.data_ptr(), 2, 0.1,
                                lq.LAYOUT2, ctypes.byref(p), small.data_ptr(), 16, None, None)
     assert rc == -6
+
+
+@pytest.mark.parametrize("eo", [False, True])
+@pytest.mark.parametrize("mode", ["f64", "ir-f32"])
+def test_adjoint_solve(gpu_lib, eo, mode):
+    """dagger = 1 solves D^dagger x = b (the adjoint solve of a gradient)."""
+    dims = (4, 4, 6, 4)
+    m0 = 0.1
+    U = syn.gauge_field(dims, "near_identity", config=8, eps=0.3)
+    b = syn.spinor_block(dims, 3, config=8)
+    x, st, rc = _solve(U, b, m0, eo=eo, mode=mode, tol=1e-10, dagger=True)
+    assert rc == lq.OK
+    assert np.all(rel_err_per_rhs(dirac.apply_dw_dagger(U, x, m0), b) <= 1e-10)
