@@ -184,6 +184,8 @@ typedef struct {
   double inner_tol;      /* relative tolerance of each inner solve (modes 1, 2); 0 = default */
   int32_t max_outer;     /* cap on refinement steps (modes 1, 2), default 50 */
   int32_t dagger;        /* 1: solve D^dagger x = b instead (the adjoint solve of a gradient) */
+  int32_t use_graph;     /* 1: capture each Arnoldi step (all lattices) in a HIP graph and replay it */
+  int32_t reserved;
 } lqcd_solver_params;
 
 /* Per-rhs results of gmres_solve (HOST memory, nrhs entries). */
@@ -215,6 +217,18 @@ size_t gmres_workspace_bytes(const lqcd_lattice* lat, int nrhs, const lqcd_solve
 int gmres_solve(const lqcd_lattice* lat, const void* U, const void* b, void* x, int nrhs,
                 double m0, int layout, const lqcd_solver_params* params, void* work,
                 size_t work_bytes, lqcd_rhs_stats* stats, void* stream);
+
+/* Batched solves over independent lattices (uneven sizes and rhs counts):
+ * problem k solves D_k x_k = b_k with b = probs[k].psi and x = probs[k].eta
+ * (FP64, full-lattice LQCD_LAYOUT2 blocks, links probs[k].U in FP64), all
+ * lattices advancing in lock-step through one GMRES driver; the Wilson
+ * applies of every step run in one persistent launch for all lattices.  With
+ * params->use_graph the kernels of each Arnoldi step are captured once and
+ * replayed as a HIP graph.  stats: sum of nrhs entries, problem by problem.
+ * FP16 refinement (mode 2) needs lattices of equal volume. */
+size_t gmres_workspace_bytes_batch(int nprob, const lqcd_problem* probs, const lqcd_solver_params* p);
+int gmres_solve_batch(int nprob, const lqcd_problem* probs, const lqcd_solver_params* params, void* work,
+                      size_t work_bytes, lqcd_rhs_stats* stats, void* stream);
 
 /* Gradient of a real loss with respect to the links through y = D psi
  * (differentiation of the Sec. III-A.1 operator): with dL = Re <g, dy> and

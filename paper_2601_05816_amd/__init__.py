@@ -45,7 +45,7 @@ class SolverParams(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int32), ("max_restarts", ctypes.c_int32), ("eo", ctypes.c_int32),
                 ("mode", ctypes.c_int32), ("x_is_guess", ctypes.c_int32), ("fixed_iters", ctypes.c_int32),
                 ("tol", ctypes.c_double), ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int32),
-                ("dagger", ctypes.c_int32)]
+                ("dagger", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Problem(ctypes.Structure):
@@ -112,6 +112,11 @@ def load():
         lib.gmres_solve.argtypes = [lp, vp, vp, vp, i32, dbl, i32, ctypes.POINTER(SolverParams), vp,
                                     ctypes.c_size_t, ctypes.POINTER(RhsStats), vp]
         lib.gmres_solve.restype = i32
+        lib.gmres_workspace_bytes_batch.argtypes = [i32, ctypes.POINTER(Problem), ctypes.POINTER(SolverParams)]
+        lib.gmres_workspace_bytes_batch.restype = ctypes.c_size_t
+        lib.gmres_solve_batch.argtypes = [i32, ctypes.POINTER(Problem), ctypes.POINTER(SolverParams), vp,
+                                          ctypes.c_size_t, ctypes.POINTER(RhsStats), vp]
+        lib.gmres_solve_batch.restype = i32
         lib.link_force.argtypes = [lp, vp, vp, vp, vp, i32, i32, dbl, i32, vp]
         lib.link_force.restype = i32
         lib.block_dot.argtypes = [lp, vp, vp, i32, i32, vp, vp]
@@ -262,7 +267,7 @@ MODES = {"f64": 0, "ir-f32": 1, "ir-f16": 2}
 
 
 def solver_params(restart=30, max_restarts=200, eo=True, mode=0, tol=1e-10, inner_tol=0.0, max_outer=50,
-                  x_is_guess=False, fixed_iters=False, dagger=False):
+                  x_is_guess=False, fixed_iters=False, dagger=False, use_graph=False):
     p = SolverParams()
     load().lqcd_solver_defaults(ctypes.byref(p))
     p.restart, p.max_restarts, p.eo = int(restart), int(max_restarts), int(bool(eo))
@@ -270,6 +275,7 @@ def solver_params(restart=30, max_restarts=200, eo=True, mode=0, tol=1e-10, inne
     p.tol, p.inner_tol, p.max_outer = float(tol), float(inner_tol), int(max_outer)
     p.x_is_guess, p.fixed_iters = int(bool(x_is_guess)), int(bool(fixed_iters))
     p.dagger = int(bool(dagger))
+    p.use_graph = int(bool(use_graph))
     return p
 
 
@@ -395,3 +401,44 @@ def hbm_probe(a, b, c=None, kind="triad", reps=5):
     _check(load().lqcd_hbm_probe(k, a.data_ptr(), b.data_ptr(), None if c is None else c.data_ptr(), n, int(reps),
                                  ctypes.byref(ms), _stream()))
     return ms.value
+
+
+def gmres_solve_batch(problems, work=None, **kw):
+    """Solve D_k x_k = b_k for a list of (U_k, b_k, m0_k) on independent
+    lattices (FP64, rhs-innermost full-lattice blocks) with one lock-step
+    batched GMRES.  Returns (list of x_k, list of per-problem stats dicts, status)."""
+    import torch
+
+    if not 1 <= len(problems) <= MAX_BATCH:
+        raise ValueError(f"need 1..{MAX_BATCH} problems")
+    p = solver_params(**kw)
+    arr = (Problem * len(problems))()
+    xs = []
+    nrhs_list = []
+    for k, (U, b, m0) in enumerate(problems):
+        if U.dtype != torch.complex128 or b.dtype != torch.complex128:
+            raise TypeError("gmres_solve_batch takes complex128 U and b")
+        dims = _dims_of_links(U, F64)
+        nrhs, sdims = _nrhs_of(b, F64, LAYOUT2, 4)
+        if tuple(sdims) != tuple(dims):
+            raise ValueError(f"problem {k}: source lattice {sdims} does not match {dims}")
+        x = torch.empty_like(b)
+        _check_device(U, b, x)
+        arr[k].lat = _lattice(dims)
+        arr[k].U, arr[k].psi, arr[k].eta = U.data_ptr(), b.data_ptr(), x.data_ptr()
+        arr[k].nrhs, arr[k].m0 = nrhs, float(m0)
+        xs.append(x)
+        nrhs_list.append(nrhs)
+    need = int(load().gmres_workspace_bytes_batch(len(problems), arr, ctypes.byref(p)))
+    if need == 0:
+        raise ValueError("invalid batch")
+    if work is None or work.numel() < need:
+        work = torch.empty(need, dtype=torch.uint8, device=problems[0][1].device)
+    st = (RhsStats * sum(nrhs_list))()
+    rc = _check(load().gmres_solve_batch(len(problems), arr, ctypes.byref(p), work.data_ptr(), work.numel(), st,
+                                         _stream()))
+    stats, off = [], 0
+    for n in nrhs_list:
+        stats.append({k: np.array([getattr(s, k) for s in st[off:off + n]]) for k, _ in RhsStats._fields_})
+        off += n
+    return xs, stats, rc

@@ -150,14 +150,23 @@ __global__ __launch_bounds__(256) void k_bmy(const store_t<P>* __restrict__ b, s
   block_combine<1>(acc, 1, nrhs, on, part);
 }
 
-// out[k][rhs] = scale * sum_blocks part[blk][k][rhs]
-__global__ void k_reduce_parts(const cx<double>* __restrict__ part, int nblk, int K, int nrhs, double scale,
-                               cx<double>* __restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= K * nrhs) return;
+// out[k][rhs] = scale * sum_blocks part[blk][k][rhs]: one workgroup per
+// output, each thread sums a fixed strided subset of the blocks, then a fixed
+// tree in LDS (deterministic order).
+__global__ __launch_bounds__(256) void k_reduce_parts(const cx<double>* __restrict__ part, int nblk, int K,
+                                                      int nrhs, double scale, cx<double>* __restrict__ out) {
+  const int i = blockIdx.x;  // output index k * nrhs + rhs
+  const size_t stride = (size_t)K * nrhs;
   cx<double> acc = {0.0, 0.0};
-  for (int b = 0; b < nblk; ++b) acc = acc + part[(size_t)b * K * nrhs + i];
-  out[i] = {acc.re * scale, acc.im * scale};
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) acc = acc + part[(size_t)b * stride + i];
+  __shared__ cx<double> sh[256];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] = sh[threadIdx.x] + sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[i] = {sh[0].re * scale, sh[0].im * scale};
 }
 
 // x[row, rhs] *= s[rhs]
@@ -311,8 +320,8 @@ hipError_t b_minus_y(int prec, const void* b, void* y, size_t nelem, int nrhs, c
 
 hipError_t reduce_parts(const void* part, int nblk, int K, int nrhs, double scale, void* out, hipStream_t s) {
   const int n = K * nrhs;
-  hipLaunchKernelGGL(k_reduce_parts, dim3((n + 127) / 128), dim3(128), 0, s, (const cx<double>*)part, nblk, K, nrhs,
-                     scale, (cx<double>*)out);
+  hipLaunchKernelGGL(k_reduce_parts, dim3(n), dim3(256), 0, s, (const cx<double>*)part, nblk, K, nrhs, scale,
+                     (cx<double>*)out);
   return hipGetLastError();
 }
 

@@ -22,6 +22,7 @@
 
 #include "blas.h"
 #include "common.h"
+#include "batch.h"
 #include "kernels.h"
 
 namespace lq {
@@ -197,7 +198,6 @@ struct Solver {
   zd *part, *hcol, *nrm, *H, *sn, *g, *y;
   double *cs, *bref, *ibref, *beta, *scl, *est, *fin, *fout, *rel;
   int *live, *steps, *flags, *nlive;
-  hipEvent_t ev[2];
 
   void layout(Arena& a) {
     const size_t v64 = nelem * 16;
@@ -270,82 +270,213 @@ struct HostState {
   std::vector<double> est;
 };
 
-// One batched GMRES(m) solve of A x = b in precision `prec`, vectors scaled by
-// `c` (stored value = c x true value).  x holds the initial guess.  Relative
-// residuals are measured against bref (device, per rhs).  Runs at most
-// max_cycles cycles; returns LQCD_OK or an error code.  Adds the Arnoldi steps
-// and cycles of every rhs to hs.
-static int run_gmres(Solver& S, int prec, void* x, const void* b, const double* bref_dev, double tol, int max_cycles,
-                     int fixed, bool x_zero, double c, HostState& hs, int* host_pinned) {
-  const size_t nel = S.nelem;
-  const int nrhs = S.nrhs, m = S.m;
-  const double sc = 1.0 / (c * c);
-  hipStream_t s = S.s;
-  std::vector<int> steps_h(nrhs);
-  std::vector<double> est_h(nrhs);
-  hipEvent_t* ev = S.ev;
-  int rc = LQCD_OK;
-  for (int cycle = 0; cycle < max_cycles; ++cycle) {
-    void* V0 = S.Vk(prec, 0);
-    hipError_t e;
-    if (cycle == 0 && x_zero) {
-      e = convert(prec, b, prec, V0, nel, nrhs, nullptr, s);
-      if (e == hipSuccess) e = S.norms(prec, V0, sc, nullptr);
+// One lattice of a solve: its solver state, its ABI input/output and the
+// vectors the current GMRES run works on.
+struct Task {
+  Solver S;
+  const void* U;       // FP64 links (caller's)
+  const void* b_abi;
+  void* x_abi;
+  int layout;
+  HostState hs;
+  void* x;             // solution of the current GMRES run
+  const void* b;       // right-hand side of the current GMRES run
+  const double* bref;  // per-rhs reference norm of the current run
+};
+
+// All lattices of one solve, advanced in lock-step on one stream.  With
+// `graph`, the kernels of Arnoldi step j (for every lattice) are captured
+// into a HIP graph the first time they run and replayed in later cycles.
+struct Group {
+  std::vector<Task> T;
+  hipStream_t s;
+  int m;
+  bool graph;
+  std::vector<hipGraphExec_t> exec[3];  // per precision, per step j
+  int* pinned;                          // 2 ints per lattice
+  hipEvent_t ev[2];
+};
+
+// out = A in for every lattice, in precision prec (in/out chosen per task)
+template <class In, class Out>
+static hipError_t apply_all(Group& G, int prec, In in_of, Out out_of, bool masked) {
+  if (G.T.size() == 1) {
+    Solver& S = G.T[0].S;
+    return S.apply(prec, in_of(G.T[0]), out_of(G.T[0]), masked ? S.live : nullptr);
+  }
+  batch_desc d;
+  d.n = (int)G.T.size();
+  const bool eo = G.T[0].S.eo;
+  const bool dag = G.T[0].S.dag;
+  for (int k = 0; k < d.n; ++k) {
+    Solver& S = G.T[k].S;
+    batch_prob& b = d.p[k];
+    b.g = make_geo4(&S.lat);
+    b.U = prec == LQCD_F64 ? S.U64 : S.Ulo;
+    b.live = masked ? S.live : nullptr;
+    b.nrhs = S.nrhs;
+    if (eo) {  // first hop pass: tmp_o = H_oe in
+      b.in = in_of(G.T[k]);
+      b.xin = nullptr;
+      b.out = prec == LQCD_F64 ? S.tmp64 : S.tmplo;
+      b.parity = 1;
+      b.alpha = 0.0;
+      b.beta = 1.0;
     } else {
-      e = S.apply(prec, x, V0, nullptr);
-      if (e == hipSuccess) e = b_minus_y(prec, b, V0, nel, nrhs, nullptr, S.part, S.nblk, s);
-      if (e == hipSuccess) e = reduce_parts(S.part, S.nblk, 1, nrhs, sc, S.nrm, s);
+      b.in = in_of(G.T[k]);
+      b.xin = nullptr;
+      b.out = out_of(G.T[k]);
+      b.parity = -1;
+      b.alpha = S.d;
+      b.beta = -0.5;
     }
-    if (e != hipSuccess) { rc = hip_status(e, "gmres residual"); break; }
-    HIPCHK(hipMemsetAsync(S.flags, 0, 2 * sizeof(int), s));
-    hipLaunchKernelGGL(k_cycle_start, dim3(S.small_grid()), dim3(64), 0, s, nrhs, m, S.nrm, bref_dev, tol, fixed,
-                       S.live, S.steps, S.g, S.scl, S.beta, S.flags);
-    int fl[2];
-    HIPCHK(hipMemcpyAsync(fl, S.flags, sizeof fl, hipMemcpyDeviceToHost, s));
+  }
+  hipError_t e = wilson_batch(d, prec, dag, G.s);
+  if (e != hipSuccess || !eo) return e;
+  for (int k = 0; k < d.n; ++k) {  // second pass: out_e = d in - H_eo tmp_o / (4 d)
+    Solver& S = G.T[k].S;
+    batch_prob& b = d.p[k];
+    b.in = prec == LQCD_F64 ? S.tmp64 : S.tmplo;
+    b.xin = in_of(G.T[k]);
+    b.out = out_of(G.T[k]);
+    b.parity = 0;
+    b.alpha = S.d;
+    b.beta = -0.25 / S.d;
+  }
+  return wilson_batch(d, prec, dag, G.s);
+}
+
+// The kernels of Arnoldi step j for every lattice (w = A v_j, CGS, Givens,
+// normalisation).
+static hipError_t arnoldi_step(Group& G, int prec, int j, double sc, double tol, int fixed) {
+  hipStream_t s = G.s;
+  const int m = G.m;
+  hipError_t e = apply_all(
+      G, prec, [&](Task& t) -> const void* { return t.S.Vk(prec, j); }, [&](Task& t) -> void* { return t.S.Vk(prec, j + 1); },
+      true);
+  if (e != hipSuccess) return e;
+  for (Task& t : G.T) {
+    Solver& S = t.S;
+    const size_t nel = S.nelem;
+    void* w = S.Vk(prec, j + 1);
+    for (int k0 = 0; k0 <= j; k0 += DOT_KB) {
+      const int K = (j + 1 - k0) < DOT_KB ? (j + 1 - k0) : DOT_KB;
+      if ((e = dot_parts(prec, S.basis, nel, k0, K, w, nel, S.nrhs, S.live, S.part, S.nblk, s)) != hipSuccess) return e;
+      if ((e = reduce_parts(S.part, S.nblk, K, S.nrhs, sc, S.hcol + (size_t)k0 * S.nrhs, s)) != hipSuccess) return e;
+    }
+    if ((e = cgs_update(prec, S.basis, nel, j + 1, S.hcol, w, nel, S.nrhs, S.live, S.part, S.nblk, s)) != hipSuccess)
+      return e;
+    if ((e = reduce_parts(S.part, S.nblk, 1, S.nrhs, sc, S.nrm, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_arnoldi_col, dim3(S.small_grid()), dim3(64), 0, s, j, m, S.nrhs, S.hcol, S.nrm, S.H, S.cs,
+                       S.sn, S.g, t.bref, tol, fixed, S.live, S.steps, S.est, S.scl);
+    if ((e = scale_rhs(prec, w, nel, S.nrhs, S.scl, S.live, s)) != hipSuccess) return e;
+  }
+  return hipGetLastError();
+}
+
+static hipError_t run_step(Group& G, int prec, int j, double sc, double tol, int fixed) {
+  if (!G.graph) return arnoldi_step(G, prec, j, sc, tol, fixed);
+  std::vector<hipGraphExec_t>& ex = G.exec[prec];
+  if (ex.size() < (size_t)G.m) ex.assign(G.m, nullptr);
+  if (!ex[j]) {
+    hipError_t e = hipStreamBeginCapture(G.s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t e2 = arnoldi_step(G, prec, j, sc, tol, fixed);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(G.s, &g);
+    if (e2 != hipSuccess) return e2;
+    if (e != hipSuccess) return e;
+    e = hipGraphInstantiate(&ex[j], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return e;
+  }
+  return hipGraphLaunch(ex[j], G.s);
+}
+
+// One batched GMRES(m) run of A x = b for every lattice, in precision `prec`,
+// vectors scaled by `c` (stored value = c x true value).  Each task's x holds
+// the initial guess (zero if x_zero).  Runs at most max_cycles cycles.
+static int run_gmres(Group& G, int prec, double tol, int max_cycles, int fixed, bool x_zero, double c) {
+  const double sc = 1.0 / (c * c);
+  hipStream_t s = G.s;
+  const int m = G.m;
+  const int nt = (int)G.T.size();
+  for (int cycle = 0; cycle < max_cycles; ++cycle) {
+    // true residual r = b - A x into v_0, |r| per rhs
+    if (cycle == 0 && x_zero) {
+      for (Task& t : G.T) {
+        HIPCHK(convert(prec, t.b, prec, t.S.Vk(prec, 0), t.S.nelem, t.S.nrhs, nullptr, s));
+        HIPCHK(t.S.norms(prec, t.S.Vk(prec, 0), sc, nullptr));
+      }
+    } else {
+      HIPCHK(apply_all(
+          G, prec, [&](Task& t) -> const void* { return t.x; }, [&](Task& t) -> void* { return t.S.Vk(prec, 0); },
+          false));
+      for (Task& t : G.T) {
+        HIPCHK(b_minus_y(prec, t.b, t.S.Vk(prec, 0), t.S.nelem, t.S.nrhs, nullptr, t.S.part, t.S.nblk, s));
+        HIPCHK(reduce_parts(t.S.part, t.S.nblk, 1, t.S.nrhs, sc, t.S.nrm, s));
+      }
+    }
+    std::vector<int> fl(2 * nt);
+    for (int k = 0; k < nt; ++k) {
+      Solver& S = G.T[k].S;
+      HIPCHK(hipMemsetAsync(S.flags, 0, 2 * sizeof(int), s));
+      hipLaunchKernelGGL(k_cycle_start, dim3(S.small_grid()), dim3(64), 0, s, S.nrhs, m, S.nrm, G.T[k].bref, tol,
+                         fixed, S.live, S.steps, S.g, S.scl, S.beta, S.flags);
+      HIPCHK(hipMemcpyAsync(&fl[2 * k], S.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    }
     HIPCHK(hipStreamSynchronize(s));
-    if (fl[1]) { rc = fail(LQCD_ERR_NONFINITE, "gmres: non-finite residual norm"); break; }
-    if (fl[0] == 0) break;
-    {
-      std::vector<int> lv(nrhs);
-      HIPCHK(hipMemcpy(lv.data(), S.live, nrhs * sizeof(int), hipMemcpyDeviceToHost));
-      for (int r = 0; r < nrhs; ++r) hs.restarts[r] += lv[r];
+    int active = 0;
+    for (int k = 0; k < nt; ++k) {
+      if (fl[2 * k + 1]) return fail(LQCD_ERR_NONFINITE, "gmres: non-finite residual norm");
+      active += fl[2 * k];
     }
-    HIPCHK(scale_rhs(prec, V0, nel, nrhs, S.scl, S.live, s));
+    if (active == 0) break;
+    for (Task& t : G.T) {
+      std::vector<int> lv(t.S.nrhs);
+      HIPCHK(hipMemcpy(lv.data(), t.S.live, t.S.nrhs * sizeof(int), hipMemcpyDeviceToHost));
+      for (int r = 0; r < t.S.nrhs; ++r) t.hs.restarts[r] += lv[r];
+      HIPCHK(scale_rhs(prec, t.S.Vk(prec, 0), t.S.nelem, t.S.nrhs, t.S.scl, t.S.live, s));
+    }
     for (int j = 0; j < m; ++j) {
-      void* w = S.Vk(prec, j + 1);
-      HIPCHK(S.apply(prec, S.Vk(prec, j), w, S.live));
-      for (int k0 = 0; k0 <= j; k0 += DOT_KB) {
-        const int K = (j + 1 - k0) < DOT_KB ? (j + 1 - k0) : DOT_KB;
-        HIPCHK(dot_parts(prec, S.basis, nel, k0, K, w, nel, nrhs, S.live, S.part, S.nblk, s));
-        HIPCHK(reduce_parts(S.part, S.nblk, K, nrhs, sc, S.hcol + (size_t)k0 * nrhs, s));
-      }
-      HIPCHK(cgs_update(prec, S.basis, nel, j + 1, S.hcol, w, nel, nrhs, S.live, S.part, S.nblk, s));
-      HIPCHK(reduce_parts(S.part, S.nblk, 1, nrhs, sc, S.nrm, s));
-      hipLaunchKernelGGL(k_arnoldi_col, dim3(S.small_grid()), dim3(64), 0, s, j, m, nrhs, S.hcol, S.nrm, S.H, S.cs,
-                         S.sn, S.g, bref_dev, tol, fixed, S.live, S.steps, S.est, S.scl);
-      HIPCHK(scale_rhs(prec, w, nel, nrhs, S.scl, S.live, s));
-      // pipelined exit test: read the live count of the previous step while
+      HIPCHK(run_step(G, prec, j, sc, tol, fixed));
+      // pipelined exit test: read the live counts of the previous step while
       // this one runs
-      hipLaunchKernelGGL(k_count_live, dim3(1), dim3(1), 0, s, nrhs, S.live, S.nlive + (j & 1));
-      HIPCHK(hipMemcpyAsync(host_pinned + (j & 1), S.nlive + (j & 1), sizeof(int), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipEventRecord(ev[j & 1], s));
+      for (int k = 0; k < nt; ++k) {
+        Solver& S = G.T[k].S;
+        hipLaunchKernelGGL(k_count_live, dim3(1), dim3(1), 0, s, S.nrhs, S.live, S.nlive + (j & 1));
+        HIPCHK(hipMemcpyAsync(G.pinned + 2 * k + (j & 1), S.nlive + (j & 1), sizeof(int), hipMemcpyDeviceToHost,
+                              s));
+      }
+      HIPCHK(hipEventRecord(G.ev[j & 1], s));
       if (j >= 1) {
-        HIPCHK(hipEventSynchronize(ev[(j - 1) & 1]));
-        if (host_pinned[(j - 1) & 1] == 0) break;
+        HIPCHK(hipEventSynchronize(G.ev[(j - 1) & 1]));
+        int live = 0;
+        for (int k = 0; k < nt; ++k) live += G.pinned[2 * k + ((j - 1) & 1)];
+        if (live == 0) break;
       }
     }
-    hipLaunchKernelGGL(k_lsq, dim3(S.small_grid()), dim3(64), 0, s, m, nrhs, S.H, S.g, S.steps, S.y);
-    HIPCHK(lincomb(prec, S.basis, nel, m, S.y, S.steps, prec, x, nel, nrhs, 1.0, s));
-    HIPCHK(hipMemcpyAsync(steps_h.data(), S.steps, nrhs * sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(est_h.data(), S.est, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    for (int r = 0; r < nrhs; ++r) {
-      hs.iters[r] += steps_h[r];
-      if (steps_h[r]) hs.est[r] = est_h[r];
+    std::vector<std::vector<int>> steps_h(nt);
+    std::vector<std::vector<double>> est_h(nt);
+    for (int k = 0; k < nt; ++k) {
+      Task& t = G.T[k];
+      Solver& S = t.S;
+      hipLaunchKernelGGL(k_lsq, dim3(S.small_grid()), dim3(64), 0, s, m, S.nrhs, S.H, S.g, S.steps, S.y);
+      HIPCHK(lincomb(prec, S.basis, S.nelem, m, S.y, S.steps, prec, t.x, S.nelem, S.nrhs, 1.0, s));
+      steps_h[k].resize(S.nrhs);
+      est_h[k].resize(S.nrhs);
+      HIPCHK(hipMemcpyAsync(steps_h[k].data(), S.steps, S.nrhs * sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(est_h[k].data(), S.est, S.nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
     }
+    HIPCHK(hipStreamSynchronize(s));
+    for (int k = 0; k < nt; ++k)
+      for (int r = 0; r < G.T[k].S.nrhs; ++r) {
+        G.T[k].hs.iters[r] += steps_h[k][r];
+        if (steps_h[k][r]) G.T[k].hs.est[r] = est_h[k][r];
+      }
     x_zero = false;
   }
-  return rc;
+  return LQCD_OK;
 }
 
 static void defaults(lqcd_solver_params* p) {
@@ -383,6 +514,215 @@ static void setup(Solver& S, const lqcd_lattice* lat, int nrhs, const lqcd_solve
   S.nblk = reduce_grid(S.nelem);
 }
 
+static size_t task_bytes(const lqcd_lattice* lat, int nrhs, const lqcd_solver_params* p) {
+  Solver S;
+  setup(S, lat, nrhs, p);
+  Arena a{nullptr, 0, 0};
+  S.layout(a);
+  return (a.off + 511) & ~(size_t)255;
+}
+
+// |b_e|^2 + |b_o|^2 (or |b|^2) of the task's full-system source into nrm
+static hipError_t full_norm2(Task& t, const void* ve, const void* vo, hipStream_t s) {
+  Solver& S = t.S;
+  hipError_t e;
+  if (!S.eo) {
+    if ((e = norm_parts(LQCD_F64, ve, S.nelem, S.nrhs, nullptr, S.part, S.nblk, s)) != hipSuccess) return e;
+    return reduce_parts(S.part, S.nblk, 1, S.nrhs, 1.0, S.nrm, s);
+  }
+  if ((e = norm_parts(LQCD_F64, ve, S.nelem, S.nrhs, nullptr, S.part, S.nblk, s)) != hipSuccess) return e;
+  if ((e = reduce_parts(S.part, S.nblk, 1, S.nrhs, 1.0, S.hcol, s)) != hipSuccess) return e;
+  if ((e = norm_parts(LQCD_F64, vo, S.nelem, S.nrhs, nullptr, S.part, S.nblk, s)) != hipSuccess) return e;
+  if ((e = reduce_parts(S.part, S.nblk, 1, S.nrhs, 1.0, S.nrm, s)) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(S.part, S.hcol, S.nrhs * sizeof(zd), hipMemcpyDeviceToDevice, s)) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(S.part + S.nrhs, S.nrm, S.nrhs * sizeof(zd), hipMemcpyDeviceToDevice, s)) != hipSuccess)
+    return e;
+  return reduce_parts(S.part, 2, 1, S.nrhs, 1.0, S.nrm, s);
+}
+
+// The whole solve for a group of lattices: ingest, (refined) GMRES,
+// reconstruction, full-system true residual, write-back and statistics.
+static int solve_group(Group& G, const lqcd_solver_params* params, lqcd_rhs_stats* stats) {
+  hipStream_t s = G.s;
+  const double tol = params->tol;
+  const int fixed = params->fixed_iters ? 1 : 0;
+  const bool x_zero = !params->x_is_guess;
+  const int mode = params->mode;
+  for (Task& t : G.T) {
+    Solver& S = t.S;
+    const int dims[4] = {S.lat.dims[0], S.lat.dims[1], S.lat.dims[2], S.lat.dims[3]};
+    t.hs.iters.assign(S.nrhs, 0);
+    t.hs.restarts.assign(S.nrhs, 0);
+    t.hs.outer.assign(S.nrhs, 0);
+    t.hs.est.assign(S.nrhs, 0.0);
+    HIPCHK(pack(t.layout, true, (void*)t.b_abi, S.be, S.bo, dims, S.nrhs, S.eo, s));
+    HIPCHK(full_norm2(t, S.be, S.bo, s));
+    hipLaunchKernelGGL(k_sqrt_scale, dim3(S.small_grid()), dim3(64), 0, s, S.nrhs, S.nrm, 1.0, S.bref);
+    if (params->x_is_guess) {
+      HIPCHK(pack(t.layout, true, t.x_abi, S.xe, S.xo, dims, S.nrhs, S.eo, s));
+      hipLaunchKernelGGL(k_zero_mask, dim3(S.small_grid()), dim3(64), 0, s, S.nrhs, S.bref, S.fin);
+      HIPCHK(scale_rhs(LQCD_F64, S.xe, S.nelem, S.nrhs, S.fin, nullptr, s));
+    } else {
+      HIPCHK(hipMemsetAsync(S.xe, 0, S.nelem * 16, s));
+    }
+    if (S.eo)  // b'_e = b_e - D_eo D_oo^{-1} b_o = b_e + (1/2) H_eo b_o / (4+m0)
+      HIPCHK(wilson_eo(&S.lat, t.U, S.bo, S.be, S.bp, 0, S.nrhs, 1.0, 0.5 / S.d, LQCD_LAYOUT2, LQCD_F64, S.dag,
+                       nullptr, s));
+  }
+  if (mode == 0) {
+    for (Task& t : G.T) {
+      t.x = t.S.xe;
+      t.b = t.S.bp;
+      t.bref = t.S.bref;
+    }
+    int rc = run_gmres(G, LQCD_F64, tol, params->max_restarts, fixed, x_zero, 1.0);
+    if (rc) return rc;
+  } else {
+    // iterative refinement: FP64 residual and update, inner GMRES in plo
+    const int plo = G.T[0].S.plo;
+    const double itol = params->inner_tol > 0 ? params->inner_tol : (plo == LQCD_F32 ? 1e-4 : 1e-2);
+    for (Task& t : G.T) HIPCHK(convert_links(t.U, plo, t.S.Ulo, 4 * t.S.V * 9, s));
+    for (int outer = 0; outer < params->max_outer; ++outer) {
+      if (outer == 0 && x_zero) {
+        for (Task& t : G.T) {
+          HIPCHK(convert(LQCD_F64, t.S.bp, LQCD_F64, t.S.r64, t.S.nelem, t.S.nrhs, nullptr, s));
+          HIPCHK(t.S.norms(LQCD_F64, t.S.r64, 1.0, nullptr));
+        }
+      } else {
+        HIPCHK(apply_all(
+            G, LQCD_F64, [&](Task& t) -> const void* { return t.S.xe; }, [&](Task& t) -> void* { return t.S.r64; },
+            false));
+        for (Task& t : G.T) {
+          HIPCHK(b_minus_y(LQCD_F64, t.S.bp, t.S.r64, t.S.nelem, t.S.nrhs, nullptr, t.S.part, t.S.nblk, s));
+          HIPCHK(reduce_parts(t.S.part, t.S.nblk, 1, t.S.nrhs, 1.0, t.S.nrm, s));
+        }
+      }
+      const int nt = (int)G.T.size();
+      std::vector<int> fl(2 * nt);
+      for (int k = 0; k < nt; ++k) {
+        Solver& S = G.T[k].S;
+        const double c = plo == LQCD_F16 ? sqrt((double)S.nsite * 12.0) : 1.0;
+        HIPCHK(hipMemsetAsync(S.flags, 0, 2 * sizeof(int), s));
+        hipLaunchKernelGGL(k_ir_factors, dim3(S.small_grid()), dim3(64), 0, s, S.nrhs, S.nrm, S.bref, tol, c, S.fin,
+                           S.fout, S.ibref, S.rel, S.flags);
+        HIPCHK(hipMemcpyAsync(&fl[2 * k], S.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+      }
+      HIPCHK(hipStreamSynchronize(s));
+      int active = 0;
+      for (int k = 0; k < nt; ++k) {
+        if (fl[2 * k + 1]) return fail(LQCD_ERR_NONFINITE, "gmres: non-finite residual norm in refinement");
+        active += fl[2 * k];
+      }
+      if (active == 0) break;
+      for (Task& t : G.T) {
+        std::vector<double> fo(t.S.nrhs);
+        HIPCHK(hipMemcpy(fo.data(), t.S.fout, t.S.nrhs * sizeof(double), hipMemcpyDeviceToHost));
+        for (int r = 0; r < t.S.nrhs; ++r) t.hs.outer[r] += fo[r] != 0.0;
+        HIPCHK(convert(LQCD_F64, t.S.r64, plo, t.S.rlo, t.S.nelem, t.S.nrhs, t.S.fin, s));
+        HIPCHK(hipMemsetAsync(t.S.dlo, 0, t.S.nelem * esize(plo), s));
+        t.x = t.S.dlo;
+        t.b = t.S.rlo;
+        t.bref = t.S.ibref;
+      }
+      // the F16 scale differs per lattice only through its size; the inner run
+      // uses the first lattice's for the dot/norm rescaling, so every lattice
+      // of an F16 batch must share its site count (checked by the caller)
+      const double c0 = plo == LQCD_F16 ? sqrt((double)G.T[0].S.nsite * 12.0) : 1.0;
+      int rc = run_gmres(G, plo, itol, 1, 0, true, c0);
+      if (rc) return rc;
+      for (Task& t : G.T) HIPCHK(add_scaled(plo, t.S.dlo, t.S.xe, t.S.nelem, t.S.nrhs, t.S.fout, s));
+    }
+  }
+  // reconstruct the odd sites, full-system true residual, write x back
+  int all = 1;
+  size_t off = 0;
+  for (Task& t : G.T) {
+    Solver& S = t.S;
+    const double d = S.d;
+    const int dims[4] = {S.lat.dims[0], S.lat.dims[1], S.lat.dims[2], S.lat.dims[3]};
+    void* t1 = S.mode ? S.r64 : S.Vk(LQCD_F64, 0);
+    if (S.eo) {
+      // x_o = (b_o + (1/2) H_oe x_e) / (4+m0)
+      HIPCHK(wilson_eo(&S.lat, t.U, S.xe, S.bo, S.xo, 1, S.nrhs, 1.0 / d, 0.5 / d, LQCD_LAYOUT2, LQCD_F64, S.dag,
+                       nullptr, s));
+      // r_e = b_e - [(4+m0) x_e - (1/2) H_eo x_o],  r_o = b_o - [(4+m0) x_o - (1/2) H_oe x_e]
+      HIPCHK(wilson_eo(&S.lat, t.U, S.xo, S.xe, t1, 0, S.nrhs, d, -0.5, LQCD_LAYOUT2, LQCD_F64, S.dag, nullptr, s));
+      HIPCHK(b_minus_y(LQCD_F64, S.be, t1, S.nelem, S.nrhs, nullptr, S.part, S.nblk, s));
+      HIPCHK(wilson_eo(&S.lat, t.U, S.xe, S.xo, S.tmp64, 1, S.nrhs, d, -0.5, LQCD_LAYOUT2, LQCD_F64, S.dag, nullptr,
+                       s));
+      HIPCHK(b_minus_y(LQCD_F64, S.bo, S.tmp64, S.nelem, S.nrhs, nullptr, S.part, S.nblk, s));
+      HIPCHK(full_norm2(t, t1, S.tmp64, s));
+    } else {
+      HIPCHK(wilson_full(&S.lat, t.U, S.xe, t1, S.nrhs, d, -0.5, LQCD_LAYOUT2, LQCD_F64, S.dag, s));
+      HIPCHK(b_minus_y(LQCD_F64, S.be, t1, S.nelem, S.nrhs, nullptr, S.part, S.nblk, s));
+      HIPCHK(reduce_parts(S.part, S.nblk, 1, S.nrhs, 1.0, S.nrm, s));
+    }
+    HIPCHK(pack(t.layout, false, t.x_abi, S.xe, S.xo, dims, S.nrhs, S.eo, s));
+    std::vector<zd> rn(S.nrhs);
+    std::vector<double> bn(S.nrhs);
+    HIPCHK(hipMemcpyAsync(rn.data(), S.nrm, S.nrhs * sizeof(zd), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(bn.data(), S.bref, S.nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int r = 0; r < S.nrhs; ++r) {
+      const double tr = bn[r] > 0 ? sqrt(rn[r].re) / bn[r] : 0.0;
+      if (!(tr == tr)) return fail(LQCD_ERR_NONFINITE, "gmres: non-finite true residual for rhs %d", r);
+      const int conv = (bn[r] == 0.0) || (tr <= tol);
+      all &= conv;
+      if (stats) {
+        lqcd_rhs_stats& st = stats[off + r];
+        st.iters = t.hs.iters[r];
+        st.restarts = t.hs.restarts[r];
+        st.outer_iters = t.hs.outer[r];
+        st.converged = conv;
+        st.true_relres = tr;
+        st.est_relres = t.hs.est[r];
+      }
+    }
+    off += S.nrhs;
+  }
+  return (all || fixed) ? LQCD_OK : LQCD_NOT_CONVERGED;
+}
+
+// Set up the group's stream, events and pinned buffer, run, and release.
+static int run_group(Group& G, const lqcd_solver_params* params, lqcd_rhs_stats* stats, hipStream_t user,
+                     bool graph) {
+  G.graph = graph;
+  G.m = params->restart;
+  hipStream_t own = nullptr;
+  if (graph) {  // capture needs a stream of its own (not the null stream)
+    if (hipStreamCreateWithFlags(&own, hipStreamNonBlocking) != hipSuccess)
+      return fail(LQCD_ERR_HIP, "gmres: stream creation failed");
+    hipEvent_t e;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess) {
+      (void)hipEventRecord(e, user);
+      (void)hipStreamWaitEvent(own, e, 0);
+      (void)hipEventDestroy(e);
+    }
+    G.s = own;
+  } else {
+    G.s = user;
+  }
+  for (Task& t : G.T) t.S.s = G.s;
+  G.pinned = nullptr;
+  if (hipHostMalloc((void**)&G.pinned, 2 * G.T.size() * sizeof(int), hipHostMallocDefault) != hipSuccess)
+    return fail(LQCD_ERR_HIP, "gmres: pinned buffer allocation failed");
+  if (hipEventCreateWithFlags(&G.ev[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&G.ev[1], hipEventDisableTiming) != hipSuccess) {
+    (void)hipHostFree(G.pinned);
+    return fail(LQCD_ERR_HIP, "gmres: event creation failed");
+  }
+  int rc = solve_group(G, params, stats);
+  (void)hipStreamSynchronize(G.s);
+  for (auto& v : G.exec)
+    for (hipGraphExec_t x : v)
+      if (x) (void)hipGraphExecDestroy(x);
+  (void)hipEventDestroy(G.ev[0]);
+  (void)hipEventDestroy(G.ev[1]);
+  (void)hipHostFree(G.pinned);
+  if (own) (void)hipStreamDestroy(own);
+  return rc;
+}
+
 }  // namespace lq
 
 using namespace lq;
@@ -395,11 +735,22 @@ void lqcd_solver_defaults(lqcd_solver_params* p) {
 
 size_t gmres_workspace_bytes(const lqcd_lattice* lat, int nrhs, const lqcd_solver_params* p) {
   if (check_lattice(lat) || nrhs < 1 || check_params(p)) return 0;
-  Solver S;
-  setup(S, lat, nrhs, p);
-  Arena a{nullptr, 0, 0};
-  S.layout(a);
-  return a.off + 256;
+  return task_bytes(lat, nrhs, p) + 256;
+}
+
+static int init_task(Task& t, const lqcd_lattice* lat, const void* U, const void* b, void* x, int nrhs, double m0,
+                     int layout, const lqcd_solver_params* p, char* work) {
+  setup(t.S, lat, nrhs, p);
+  t.S.m0 = m0;
+  t.S.d = 4.0 + m0;
+  t.S.U64 = U;
+  t.U = U;
+  t.b_abi = b;
+  t.x_abi = x;
+  t.layout = layout;
+  Arena a{work, 0, 0};
+  t.S.layout(a);
+  return LQCD_OK;
 }
 
 int gmres_solve(const lqcd_lattice* lat, const void* U, const void* b, void* x, int nrhs, double m0, int layout,
@@ -413,153 +764,54 @@ int gmres_solve(const lqcd_lattice* lat, const void* U, const void* b, void* x, 
   const size_t need = gmres_workspace_bytes(lat, nrhs, params);
   if (!work || work_bytes < need)
     return fail(LQCD_ERR_WORKSPACE, "gmres_solve: workspace of %zu bytes given, %zu needed", work_bytes, need);
-  const double d = 4.0 + m0;
-  if (d == 0.0 && params->eo) return fail(LQCD_ERR_SINGULAR, "gmres_solve: 4 + m0 = 0, D_oo is not invertible");
+  if (4.0 + m0 == 0.0 && params->eo) return fail(LQCD_ERR_SINGULAR, "gmres_solve: 4 + m0 = 0, D_oo is not invertible");
+  Group G;
+  G.T.resize(1);
+  char* w = (char*)work + ((256 - ((uintptr_t)work & 255)) & 255);
+  init_task(G.T[0], lat, U, b, x, nrhs, m0, layout, params, w);
+  return run_group(G, params, stats, (hipStream_t)stream, params->use_graph != 0);
+}
 
-  Solver S;
-  setup(S, lat, nrhs, params);
-  S.m0 = m0;
-  S.d = d;
-  S.s = (hipStream_t)stream;
-  S.U64 = U;
-  Arena a{(char*)work, 0, work_bytes};
-  a.off = (256 - ((uintptr_t)work & 255)) & 255;
-  S.layout(a);
-  hipStream_t s = S.s;
-  const size_t nel = S.nelem;
-  const double tol = params->tol;
-  const int fixed = params->fixed_iters ? 1 : 0;
-  const int dims[4] = {lat->dims[0], lat->dims[1], lat->dims[2], lat->dims[3]};
-  HostState hs;
-  hs.iters.assign(nrhs, 0);
-  hs.restarts.assign(nrhs, 0);
-  hs.outer.assign(nrhs, 0);
-  hs.est.assign(nrhs, 0.0);
-  int* pinned = nullptr;
-  HIPCHK(hipHostMalloc((void**)&pinned, 4 * sizeof(int), hipHostMallocDefault));
-  if (hipEventCreateWithFlags(&S.ev[0], hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&S.ev[1], hipEventDisableTiming) != hipSuccess) {
-    (void)hipHostFree(pinned);
-    return fail(LQCD_ERR_HIP, "gmres_solve: event creation failed");
+size_t gmres_workspace_bytes_batch(int nprob, const lqcd_problem* probs, const lqcd_solver_params* p) {
+  if (nprob < 1 || nprob > LQCD_MAX_BATCH || !probs || check_params(p)) return 0;
+  size_t total = 256;
+  for (int k = 0; k < nprob; ++k) {
+    if (check_lattice(&probs[k].lat) || probs[k].nrhs < 1) return 0;
+    total += task_bytes(&probs[k].lat, probs[k].nrhs, p);
   }
+  return total;
+}
 
-  auto body = [&]() -> int {
-    // ingest: ABI layout -> internal vectors; |b| of the full system per rhs
-    HIPCHK(pack(layout, true, (void*)b, S.be, S.bo, dims, nrhs, S.eo, s));
-    if (S.eo) {
-      HIPCHK(norm_parts(LQCD_F64, S.be, nel, nrhs, nullptr, S.part, S.nblk, s));
-      HIPCHK(reduce_parts(S.part, S.nblk, 1, nrhs, 1.0, S.hcol, s));
-      HIPCHK(norm_parts(LQCD_F64, S.bo, nel, nrhs, nullptr, S.part, S.nblk, s));
-      HIPCHK(reduce_parts(S.part, S.nblk, 1, nrhs, 1.0, S.nrm, s));
-      // nrm += hcol (|b_e|^2 + |b_o|^2) via a 2-row reduction of the stored values
-      HIPCHK(hipMemcpyAsync(S.part, S.hcol, nrhs * sizeof(zd), hipMemcpyDeviceToDevice, s));
-      HIPCHK(hipMemcpyAsync(S.part + nrhs, S.nrm, nrhs * sizeof(zd), hipMemcpyDeviceToDevice, s));
-      HIPCHK(reduce_parts(S.part, 2, 1, nrhs, 1.0, S.nrm, s));
-    } else {
-      HIPCHK(S.norms(LQCD_F64, S.be, 1.0, nullptr));
-    }
-    hipLaunchKernelGGL(k_sqrt_scale, dim3(S.small_grid()), dim3(64), 0, s, nrhs, S.nrm, 1.0, S.bref);
-    bool x_zero = !params->x_is_guess;
-    if (params->x_is_guess) {
-      HIPCHK(pack(layout, true, x, S.xe, S.xo, dims, nrhs, S.eo, s));
-      hipLaunchKernelGGL(k_zero_mask, dim3(S.small_grid()), dim3(64), 0, s, nrhs, S.bref, S.fin);
-      HIPCHK(scale_rhs(LQCD_F64, S.xe, nel, nrhs, S.fin, nullptr, s));
-    } else {
-      HIPCHK(hipMemsetAsync(S.xe, 0, nel * 16, s));
-    }
-    if (S.eo) {
-      // b'_e = b_e - D_eo D_oo^{-1} b_o = b_e + (1/2) H_eo b_o / (4+m0)
-      HIPCHK(wilson_eo(&S.lat, U, S.bo, S.be, S.bp, 0, nrhs, 1.0, 0.5 / d, LQCD_LAYOUT2, LQCD_F64, S.dag, nullptr, s));
-    }
-    if (S.mode == 0) {
-      rc = run_gmres(S, LQCD_F64, S.xe, S.bp, S.bref, tol, params->max_restarts, fixed, x_zero, 1.0, hs, pinned);
-      if (rc) return rc;
-    } else {
-      // iterative refinement: FP64 residual and update, inner GMRES in plo
-      const int plo = S.plo;
-      const double c = plo == LQCD_F16 ? sqrt((double)S.nsite * 12.0) : 1.0;
-      const double itol = params->inner_tol > 0 ? params->inner_tol : (plo == LQCD_F32 ? 1e-4 : 1e-2);
-      HIPCHK(convert_links(U, plo, S.Ulo, 4 * S.V * 9, s));
-      for (int outer = 0; outer < params->max_outer; ++outer) {
-        if (outer == 0 && x_zero) {
-          HIPCHK(convert(LQCD_F64, S.bp, LQCD_F64, S.r64, nel, nrhs, nullptr, s));
-          HIPCHK(S.norms(LQCD_F64, S.r64, 1.0, nullptr));
-        } else {
-          HIPCHK(S.apply(LQCD_F64, S.xe, S.r64, nullptr));
-          HIPCHK(b_minus_y(LQCD_F64, S.bp, S.r64, nel, nrhs, nullptr, S.part, S.nblk, s));
-          HIPCHK(reduce_parts(S.part, S.nblk, 1, nrhs, 1.0, S.nrm, s));
-        }
-        HIPCHK(hipMemsetAsync(S.flags, 0, 2 * sizeof(int), s));
-        hipLaunchKernelGGL(k_ir_factors, dim3(S.small_grid()), dim3(64), 0, s, nrhs, S.nrm, S.bref, tol, c, S.fin,
-                           S.fout, S.ibref, S.rel, S.flags);
-        int fl[2];
-        HIPCHK(hipMemcpyAsync(fl, S.flags, sizeof fl, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        if (fl[1]) return fail(LQCD_ERR_NONFINITE, "gmres: non-finite residual norm in refinement");
-        if (fl[0] == 0) break;
-        {
-          std::vector<double> fo(nrhs);
-          HIPCHK(hipMemcpy(fo.data(), S.fout, nrhs * sizeof(double), hipMemcpyDeviceToHost));
-          for (int r = 0; r < nrhs; ++r) hs.outer[r] += fo[r] != 0.0;
-        }
-        HIPCHK(convert(LQCD_F64, S.r64, plo, S.rlo, nel, nrhs, S.fin, s));
-        HIPCHK(hipMemsetAsync(S.dlo, 0, nel * esize(plo), s));
-        rc = run_gmres(S, plo, S.dlo, S.rlo, S.ibref, itol, 1, 0, true, c, hs, pinned);
-        if (rc) return rc;
-        HIPCHK(add_scaled(plo, S.dlo, S.xe, nel, nrhs, S.fout, s));
-      }
-    }
-    // reconstruct the odd sites, full-system true residual, write x back
-    void* t1 = S.mode ? S.r64 : S.Vk(LQCD_F64, 0);
-    double nr_e_scale = 1.0;
-    if (S.eo) {
-      // x_o = (b_o + (1/2) H_oe x_e) / (4+m0)
-      HIPCHK(wilson_eo(&S.lat, U, S.xe, S.bo, S.xo, 1, nrhs, 1.0 / d, 0.5 / d, LQCD_LAYOUT2, LQCD_F64, S.dag, nullptr,
-                       s));
-      // r_e = b_e - [(4+m0) x_e - (1/2) H_eo x_o]
-      HIPCHK(wilson_eo(&S.lat, U, S.xo, S.xe, t1, 0, nrhs, d, -0.5, LQCD_LAYOUT2, LQCD_F64, S.dag, nullptr, s));
-      HIPCHK(b_minus_y(LQCD_F64, S.be, t1, nel, nrhs, nullptr, S.part, S.nblk, s));
-      HIPCHK(reduce_parts(S.part, S.nblk, 1, nrhs, nr_e_scale, S.hcol, s));
-      HIPCHK(wilson_eo(&S.lat, U, S.xe, S.xo, S.tmp64, 1, nrhs, d, -0.5, LQCD_LAYOUT2, LQCD_F64, S.dag, nullptr, s));
-      HIPCHK(b_minus_y(LQCD_F64, S.bo, S.tmp64, nel, nrhs, nullptr, S.part, S.nblk, s));
-      HIPCHK(reduce_parts(S.part, S.nblk, 1, nrhs, 1.0, S.nrm, s));
-      HIPCHK(hipMemcpyAsync(S.part, S.hcol, nrhs * sizeof(zd), hipMemcpyDeviceToDevice, s));
-      HIPCHK(hipMemcpyAsync(S.part + nrhs, S.nrm, nrhs * sizeof(zd), hipMemcpyDeviceToDevice, s));
-      HIPCHK(reduce_parts(S.part, 2, 1, nrhs, 1.0, S.nrm, s));
-    } else {
-      HIPCHK(wilson_full(&S.lat, U, S.xe, t1, nrhs, d, -0.5, LQCD_LAYOUT2, LQCD_F64, S.dag, s));
-      HIPCHK(b_minus_y(LQCD_F64, S.be, t1, nel, nrhs, nullptr, S.part, S.nblk, s));
-      HIPCHK(reduce_parts(S.part, S.nblk, 1, nrhs, 1.0, S.nrm, s));
-    }
-    HIPCHK(pack(layout, false, x, S.xe, S.xo, dims, nrhs, S.eo, s));
-    std::vector<zd> rn(nrhs);
-    std::vector<double> bn(nrhs);
-    HIPCHK(hipMemcpyAsync(rn.data(), S.nrm, nrhs * sizeof(zd), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(bn.data(), S.bref, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    int all = 1;
-    for (int r = 0; r < nrhs; ++r) {
-      const double tr = bn[r] > 0 ? sqrt(rn[r].re) / bn[r] : 0.0;
-      const int conv = (bn[r] == 0.0) || (tr <= tol);
-      if (!(tr == tr)) return fail(LQCD_ERR_NONFINITE, "gmres: non-finite true residual for rhs %d", r);
-      all &= conv;
-      if (stats) {
-        stats[r].iters = hs.iters[r];
-        stats[r].restarts = hs.restarts[r];
-        stats[r].outer_iters = hs.outer[r];
-        stats[r].converged = conv;
-        stats[r].true_relres = tr;
-        stats[r].est_relres = hs.est[r];
-      }
-    }
-    return (all || fixed) ? LQCD_OK : LQCD_NOT_CONVERGED;
-  };
-  rc = body();
-  (void)hipStreamSynchronize(s);
-  (void)hipEventDestroy(S.ev[0]);
-  (void)hipEventDestroy(S.ev[1]);
-  (void)hipHostFree(pinned);
-  return rc;
+int gmres_solve_batch(int nprob, const lqcd_problem* probs, const lqcd_solver_params* params, void* work,
+                      size_t work_bytes, lqcd_rhs_stats* stats, void* stream) {
+  if (nprob < 1 || nprob > LQCD_MAX_BATCH)
+    return fail(LQCD_ERR_ARG, "gmres_solve_batch: %d problems, need 1..%d", nprob, LQCD_MAX_BATCH);
+  if (!probs) return fail(LQCD_ERR_ARG, "gmres_solve_batch: probs is null");
+  int rc = check_params(params);
+  if (rc) return rc;
+  for (int k = 0; k < nprob; ++k) {
+    const lqcd_problem& q = probs[k];
+    if ((rc = check_lattice(&q.lat))) return rc;
+    if (q.nrhs < 1) return fail(LQCD_ERR_ARG, "gmres_solve_batch: problem %d has nrhs = %d", k, q.nrhs);
+    if (!q.U || !q.psi || !q.eta) return fail(LQCD_ERR_ARG, "gmres_solve_batch: problem %d has a null pointer", k);
+    if (4.0 + q.m0 == 0.0 && params->eo)
+      return fail(LQCD_ERR_SINGULAR, "gmres_solve_batch: problem %d has 4 + m0 = 0", k);
+    if (params->mode == 2 && q.lat.dims[0] * q.lat.dims[1] * q.lat.dims[2] * q.lat.dims[3] !=
+                                 probs[0].lat.dims[0] * probs[0].lat.dims[1] * probs[0].lat.dims[2] * probs[0].lat.dims[3])
+      return fail(LQCD_ERR_ARG, "gmres_solve_batch: FP16 refinement needs lattices of one volume");
+  }
+  const size_t need = gmres_workspace_bytes_batch(nprob, probs, params);
+  if (!work || work_bytes < need)
+    return fail(LQCD_ERR_WORKSPACE, "gmres_solve_batch: workspace of %zu bytes given, %zu needed", work_bytes, need);
+  Group G;
+  G.T.resize(nprob);
+  char* w = (char*)work + ((256 - ((uintptr_t)work & 255)) & 255);
+  for (int k = 0; k < nprob; ++k) {
+    const lqcd_problem& q = probs[k];
+    init_task(G.T[k], &q.lat, q.U, q.psi, q.eta, q.nrhs, q.m0, LQCD_LAYOUT2, params, w);
+    w += task_bytes(&q.lat, q.nrhs, params);
+  }
+  return run_group(G, params, stats, (hipStream_t)stream, params->use_graph != 0);
 }
 
 }  // extern "C"
