@@ -84,7 +84,8 @@ int lqcd_lattice_tables(const lqcd_lattice* lat, int32_t* nbr, int32_t* eo_site)
 /* Kernel selection for the Wilson kernels (process-wide; for tuning and
  * tests).  variant 0 = automatic, 1 = one (site, rhs) per work item,
  * 2 = time-streaming pencils with the links of each step staged in LDS,
- * 3 = pencils without LDS staging.  pencil (may be NULL) = {tile Y, tile Z,
+ * 3 = pencils without LDS staging, 4 = pencils with two rhs per work item
+ * (FP32 / FP16 storage, LQCD_LAYOUT2, even nrhs; otherwise as 3).  pencil (may be NULL) = {tile Y, tile Z,
  * number of t segments} for variants 2 and 3; 0 entries are chosen automatically, values
  * that do not divide the lattice fall back to automatic.  Every choice
  * computes the same sums; results agree to rounding.  Not thread-safe
@@ -167,8 +168,9 @@ int lqcd_autotune_batch(int nprob, const lqcd_problem* probs, int prec, int reps
 /* Measured HBM ceiling (a STREAM-style probe, the paper's empirical memory
  * ceiling of Sec. V-A, eq. (4)): kind 0 = copy b = a, 1 = triad
  * a = b + s c, over n doubles per array (device buffers a, b, c of n doubles;
- * c unused for copy).  Launches `reps` times and returns the mean time per
- * launch in *ms.  Synchronises `stream`. */
+ * c unused for copy).  Tries four launch shapes (workgroups per CU, plain or
+ * non-temporal stores), each launched `reps` times, and returns the best mean
+ * time per launch in *ms.  Synchronises `stream`. */
 int lqcd_hbm_probe(int kind, double* a, double* b, const double* c, size_t n, int reps, double* ms, void* stream);
 
 /* Parameters of gmres_solve (Algorithm 2). */

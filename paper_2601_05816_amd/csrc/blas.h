@@ -32,4 +32,17 @@ hipError_t convert_links(const void* in, int pout, void* out, size_t n, hipStrea
 hipError_t pack(int layout, bool to_internal, void* abi, void* ie, void* io, const int* dims, int nrhs, int eo,
                 hipStream_t s);
 
+// 16-byte-per-lane variants for FP32 / FP16 bases (blasv.hip); the scalar
+// launchers above dispatch to them when vec_width(prec, nrhs) > 1.
+int vec_width(int prec, int nrhs);
+void set_vector_blas(int on);
+hipError_t dot_parts_v(int prec, const void* V, size_t vstride, int k0, int K, const void* w, size_t nelem, int nrhs,
+                       const int* live, void* part, unsigned nblk, hipStream_t s);
+hipError_t cgs_update_v(int prec, const void* V, size_t vstride, int K, const void* h, void* w, size_t nelem,
+                        int nrhs, const int* live, void* part, unsigned nblk, hipStream_t s);
+hipError_t scale_rhs_v(int prec, void* x, size_t nelem, int nrhs, const double* f, const int* live, unsigned nblk,
+                       hipStream_t s);
+hipError_t lincomb_v(int prec, const void* V, size_t vstride, int kmax, const void* y, const int* cnt, void* x,
+                     size_t nelem, int nrhs, double scale, unsigned nblk, hipStream_t s);
+
 }  // namespace lq

@@ -287,9 +287,14 @@ unsigned reduce_grid(size_t nelem) { return red_blocks(nelem); }
     default: return hipErrorInvalidValue;                          \
   }
 
+static int g_vec_blas = 1;
+void set_vector_blas(int on) { g_vec_blas = on ? 1 : 0; }
+
 hipError_t dot_parts(int prec, const void* V, size_t vstride, int k0, int K, const void* w, size_t nelem, int nrhs,
                      const int* live, void* part, unsigned nblk, hipStream_t s) {
   if (K < 1 || K > DOT_KB) return hipErrorInvalidValue;
+  if (g_vec_blas && vec_width(prec, nrhs) > 1)
+    return dot_parts_v(prec, V, vstride, k0, K, w, nelem, nrhs, live, part, nblk, s);
   PREC_SWITCH(prec, hipLaunchKernelGGL((k_dot_parts<PP, DOT_KB>), dim3(nblk), dim3(256), 0, s,
                                        (const store_t<PP>*)V, vstride, k0, K, (const store_t<PP>*)w, nelem, nrhs,
                                        live, (cx<double>*)part));
@@ -305,6 +310,8 @@ hipError_t norm_parts(int prec, const void* x, size_t nelem, int nrhs, const int
 
 hipError_t cgs_update(int prec, const void* V, size_t vstride, int K, const void* h, void* w, size_t nelem, int nrhs,
                       const int* live, void* part, unsigned nblk, hipStream_t s) {
+  if (g_vec_blas && vec_width(prec, nrhs) > 1)
+    return cgs_update_v(prec, V, vstride, K, h, w, nelem, nrhs, live, part, nblk, s);
   PREC_SWITCH(prec, hipLaunchKernelGGL((k_cgs_update<PP>), dim3(nblk), dim3(256), 0, s, (const store_t<PP>*)V,
                                        vstride, K, (const cx<double>*)h, (store_t<PP>*)w, nelem, nrhs, live,
                                        (cx<double>*)part));
@@ -326,6 +333,7 @@ hipError_t reduce_parts(const void* part, int nblk, int K, int nrhs, double scal
 }
 
 hipError_t scale_rhs(int prec, void* x, size_t nelem, int nrhs, const double* f, const int* live, hipStream_t s) {
+  if (g_vec_blas && vec_width(prec, nrhs) > 1) return scale_rhs_v(prec, x, nelem, nrhs, f, live, red_blocks(nelem), s);
   PREC_SWITCH(prec, hipLaunchKernelGGL((k_scale<PP>), dim3(red_blocks(nelem)), dim3(256), 0, s, (store_t<PP>*)x,
                                        nelem, nrhs, f, live));
   return hipGetLastError();
@@ -334,6 +342,8 @@ hipError_t scale_rhs(int prec, void* x, size_t nelem, int nrhs, const double* f,
 hipError_t lincomb(int prec, const void* V, size_t vstride, int kmax, const void* y, const int* cnt, int precx,
                    void* x, size_t nelem, int nrhs, double scale, hipStream_t s) {
   const unsigned nb = red_blocks(nelem);
+  if (g_vec_blas && prec == precx && vec_width(prec, nrhs) > 1)
+    return lincomb_v(prec, V, vstride, kmax, y, cnt, x, nelem, nrhs, scale, nb, s);
 #define LC(PV, PX)                                                                                                \
   hipLaunchKernelGGL((k_lincomb<PV, PX>), dim3(nb), dim3(256), 0, s, (const store_t<PV>*)V, vstride, kmax,        \
                      (const cx<double>*)y, cnt, (store_t<PX>*)x, nelem, nrhs, scale)

@@ -1,0 +1,294 @@
+// Vector-width variants of the batched BLAS-1 kernels for the low-precision
+// Krylov bases of the refinement modes: each lane moves VW consecutive rhs of
+// one row with one 16-byte access (VW = 2 for FP32, 4 for FP16 storage),
+// instead of one 8- or 4-byte access per rhs.  Needs nrhs % VW == 0 (the
+// launchers in blas.hip fall back to the scalar kernels otherwise).  Partial
+// sums per lane are FP64 for VW = 2 and FP32 for VW = 4; block and
+// cross-block sums are FP64 in a fixed order, as in blas.hip.
+#include "blas.h"
+#include "common.h"
+
+namespace lq {
+
+
+template <int P>
+struct vio;
+template <>
+struct vio<LQCD_F32> {
+  enum { VW = 2 };
+  typedef double acc_t;
+  typedef float2 store;
+  __device__ static __forceinline__ void load(const float2* p, cx<double> (&o)[2]) {
+    const f4v_t v = *(const f4v_t*)p;
+    o[0] = {v.x, v.y};
+    o[1] = {v.z, v.w};
+  }
+  __device__ static __forceinline__ void save(float2* p, const cx<double> (&o)[2]) {
+    f4v_t v = {(float)o[0].re, (float)o[0].im, (float)o[1].re, (float)o[1].im};
+    *(f4v_t*)p = v;
+  }
+};
+template <>
+struct vio<LQCD_F16> {
+  enum { VW = 4 };
+  typedef float acc_t;
+  typedef h2_t store;
+  __device__ static __forceinline__ void load(const h2_t* p, cx<double> (&o)[4]) {
+    const h8v_t v = *(const h8v_t*)p;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) o[i] = {(double)(float)v[2 * i], (double)(float)v[2 * i + 1]};
+  }
+  __device__ static __forceinline__ void save(h2_t* p, const cx<double> (&o)[4]) {
+    h8v_t v;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      v[2 * i] = (_Float16)(float)o[i].re;
+      v[2 * i + 1] = (_Float16)(float)o[i].im;
+    }
+    *(h8v_t*)p = v;
+  }
+};
+
+// Thread t owns rhs group gr = t % G (rhs gr*VW .. gr*VW+VW-1) of rows
+// row0, row0 + rstride, ... with G = nrhs / VW.
+struct vsched {
+  size_t row0, rstride;
+  int gr;
+  bool active;
+};
+__device__ __forceinline__ vsched vgrid(int G) {
+  vsched s;
+  const size_t T = (size_t)gridDim.x * blockDim.x;
+  const size_t Tp = T / G * G;
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  s.active = t < Tp;
+  s.gr = (int)(t % G);
+  s.row0 = t / G;
+  s.rstride = Tp / G;
+  return s;
+}
+
+// part[blk][k][rhs] from per-thread values val[k][v] of rhs gr*VW + v
+template <int KB, int VW, typename A>
+__device__ __forceinline__ void vblock_combine(A (&re)[KB][VW], A (&im)[KB][VW], int K, int nrhs, bool active,
+                                               cx<double>* __restrict__ part) {
+  __shared__ cx<double> sh[256];
+  const int tid = threadIdx.x, bt = blockDim.x;
+  const int G = nrhs / VW;
+  const size_t base = (size_t)blockIdx.x * K * nrhs;
+  const size_t t0 = (size_t)blockIdx.x * bt;
+  for (int k = 0; k < K; ++k) {
+#pragma unroll
+    for (int v = 0; v < VW; ++v) {
+      cx<double> x = {0.0, 0.0};
+#pragma unroll
+      for (int q = 0; q < KB; ++q)
+        if (q == k) x = {(double)re[q][v], (double)im[q][v]};
+      sh[tid] = active ? x : cx<double>{0.0, 0.0};
+      __syncthreads();
+      for (int g = tid; g < G; g += bt) {
+        const int first = (int)((g - (int)(t0 % G) + G) % G);
+        cx<double> a = {0.0, 0.0};
+        for (int i = first; i < bt; i += G) a = a + sh[i];
+        part[base + (size_t)k * nrhs + (size_t)g * VW + v] = a;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+template <int P, int KB>
+__global__ __launch_bounds__(256) void k_dot_parts_v(const typename vio<P>::store* __restrict__ V, size_t vstride,
+                                                     int k0, int K, const typename vio<P>::store* __restrict__ w,
+                                                     size_t nrow, int nrhs, const int* __restrict__ live,
+                                                     cx<double>* __restrict__ part) {
+  constexpr int VW = vio<P>::VW;
+  typedef typename vio<P>::acc_t A;
+  const int G = nrhs / VW;
+  vsched s = vgrid(G);
+  A re[KB][VW], im[KB][VW];
+#pragma unroll
+  for (int q = 0; q < KB; ++q)
+#pragma unroll
+    for (int v = 0; v < VW; ++v) re[q][v] = im[q][v] = A(0);
+  bool on = s.active;
+  if (on && live) {
+    bool any = false;
+#pragma unroll
+    for (int v = 0; v < VW; ++v) any |= live[s.gr * VW + v] != 0;
+    on = any;
+  }
+  if (on) {
+    for (size_t row = s.row0; row < nrow; row += s.rstride) {
+      const size_t e = row * nrhs + (size_t)s.gr * VW;
+      cx<double> we[VW];
+      vio<P>::load(w + e, we);
+#pragma unroll
+      for (int q = 0; q < KB; ++q)
+        if (q < K) {
+          cx<double> ve[VW];
+          vio<P>::load(V + (size_t)(k0 + q) * vstride + e, ve);
+#pragma unroll
+          for (int v = 0; v < VW; ++v) {
+            // conj(v) w
+            re[q][v] += (A)(ve[v].re * we[v].re + ve[v].im * we[v].im);
+            im[q][v] += (A)(ve[v].re * we[v].im - ve[v].im * we[v].re);
+          }
+        }
+    }
+  }
+  vblock_combine<KB, VW, A>(re, im, K, nrhs, on, part);
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_cgs_update_v(const typename vio<P>::store* __restrict__ V, size_t vstride,
+                                                      int K, const cx<double>* __restrict__ h,
+                                                      typename vio<P>::store* __restrict__ w, size_t nrow, int nrhs,
+                                                      const int* __restrict__ live, cx<double>* __restrict__ part) {
+  constexpr int VW = vio<P>::VW;
+  typedef typename vio<P>::acc_t A;
+  const int G = nrhs / VW;
+  vsched s = vgrid(G);
+  A re[1][VW], im[1][VW];
+#pragma unroll
+  for (int v = 0; v < VW; ++v) re[0][v] = im[0][v] = A(0);
+  bool on = s.active;
+  if (on && live) {
+    bool any = false;
+#pragma unroll
+    for (int v = 0; v < VW; ++v) any |= live[s.gr * VW + v] != 0;
+    on = any;
+  }
+  if (on) {
+    for (size_t row = s.row0; row < nrow; row += s.rstride) {
+      const size_t e = row * nrhs + (size_t)s.gr * VW;
+      cx<double> x[VW];
+      vio<P>::load(w + e, x);
+      for (int k = 0; k < K; ++k) {
+        cx<double> ve[VW];
+        vio<P>::load(V + (size_t)k * vstride + e, ve);
+#pragma unroll
+        for (int v = 0; v < VW; ++v) x[v] = cmadd(x[v], -h[(size_t)k * nrhs + s.gr * VW + v], ve[v]);
+      }
+      vio<P>::save(w + e, x);
+#pragma unroll
+      for (int v = 0; v < VW; ++v) re[0][v] += (A)(x[v].re * x[v].re + x[v].im * x[v].im);
+    }
+  }
+  vblock_combine<1, VW, A>(re, im, 1, nrhs, on, part);
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_scale_v(typename vio<P>::store* __restrict__ x, size_t nrow, int nrhs,
+                                                 const double* __restrict__ f, const int* __restrict__ live) {
+  constexpr int VW = vio<P>::VW;
+  const int G = nrhs / VW;
+  vsched s = vgrid(G);
+  if (!s.active) return;
+  double fs[VW];
+  bool any = false;
+#pragma unroll
+  for (int v = 0; v < VW; ++v) {
+    const int r = s.gr * VW + v;
+    const bool lv = !live || live[r];
+    fs[v] = lv ? f[r] : 1.0;
+    any |= lv;
+  }
+  if (!any) return;
+  for (size_t row = s.row0; row < nrow; row += s.rstride) {
+    const size_t e = row * nrhs + (size_t)s.gr * VW;
+    cx<double> a[VW];
+    vio<P>::load(x + e, a);
+#pragma unroll
+    for (int v = 0; v < VW; ++v) a[v] = {a[v].re * fs[v], a[v].im * fs[v]};
+    vio<P>::save(x + e, a);
+  }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_lincomb_v(const typename vio<P>::store* __restrict__ V, size_t vstride,
+                                                   int kmax, const cx<double>* __restrict__ y,
+                                                   const int* __restrict__ cnt, typename vio<P>::store* __restrict__ x,
+                                                   size_t nrow, int nrhs, double scale) {
+  constexpr int VW = vio<P>::VW;
+  const int G = nrhs / VW;
+  vsched s = vgrid(G);
+  if (!s.active) return;
+  int n[VW], nmax = 0;
+#pragma unroll
+  for (int v = 0; v < VW; ++v) {
+    const int c = cnt[s.gr * VW + v];
+    n[v] = c < kmax ? c : kmax;
+    nmax = n[v] > nmax ? n[v] : nmax;
+  }
+  if (nmax == 0) return;
+  for (size_t row = s.row0; row < nrow; row += s.rstride) {
+    const size_t e = row * nrhs + (size_t)s.gr * VW;
+    cx<double> acc[VW];
+#pragma unroll
+    for (int v = 0; v < VW; ++v) acc[v] = {0.0, 0.0};
+    for (int k = 0; k < nmax; ++k) {
+      cx<double> ve[VW];
+      vio<P>::load(V + (size_t)k * vstride + e, ve);
+#pragma unroll
+      for (int v = 0; v < VW; ++v)
+        if (k < n[v]) acc[v] = cmadd(acc[v], y[(size_t)k * nrhs + s.gr * VW + v], ve[v]);
+    }
+    cx<double> xv[VW];
+    vio<P>::load(x + e, xv);
+#pragma unroll
+    for (int v = 0; v < VW; ++v) xv[v] = {fma(scale, acc[v].re, xv[v].re), fma(scale, acc[v].im, xv[v].im)};
+    vio<P>::save(x + e, xv);
+  }
+}
+
+// ------------------------------------------------------------ launchers
+int vec_width(int prec, int nrhs) {
+  if (prec == LQCD_F32 && nrhs % 2 == 0) return 2;
+  if (prec == LQCD_F16 && nrhs % 4 == 0) return 4;
+  return 1;
+}
+
+#define VSWITCH(P, CALL)                                             \
+  switch (P) {                                                       \
+    case LQCD_F32: { constexpr int PP = LQCD_F32; CALL; } break;     \
+    case LQCD_F16: { constexpr int PP = LQCD_F16; CALL; } break;     \
+    default: return hipErrorInvalidValue;                            \
+  }
+
+hipError_t dot_parts_v(int prec, const void* V, size_t vstride, int k0, int K, const void* w, size_t nelem, int nrhs,
+                       const int* live, void* part, unsigned nblk, hipStream_t s) {
+  const size_t nrow = nelem / nrhs;
+  VSWITCH(prec, hipLaunchKernelGGL((k_dot_parts_v<PP, DOT_KB>), dim3(nblk), dim3(256), 0, s,
+                                   (const typename vio<PP>::store*)V, vstride, k0, K,
+                                   (const typename vio<PP>::store*)w, nrow, nrhs, live, (cx<double>*)part));
+  return hipGetLastError();
+}
+
+hipError_t cgs_update_v(int prec, const void* V, size_t vstride, int K, const void* h, void* w, size_t nelem,
+                        int nrhs, const int* live, void* part, unsigned nblk, hipStream_t s) {
+  const size_t nrow = nelem / nrhs;
+  VSWITCH(prec, hipLaunchKernelGGL((k_cgs_update_v<PP>), dim3(nblk), dim3(256), 0, s,
+                                   (const typename vio<PP>::store*)V, vstride, K, (const cx<double>*)h,
+                                   (typename vio<PP>::store*)w, nrow, nrhs, live, (cx<double>*)part));
+  return hipGetLastError();
+}
+
+hipError_t scale_rhs_v(int prec, void* x, size_t nelem, int nrhs, const double* f, const int* live, unsigned nblk,
+                       hipStream_t s) {
+  const size_t nrow = nelem / nrhs;
+  VSWITCH(prec, hipLaunchKernelGGL((k_scale_v<PP>), dim3(nblk), dim3(256), 0, s, (typename vio<PP>::store*)x, nrow,
+                                   nrhs, f, live));
+  return hipGetLastError();
+}
+
+hipError_t lincomb_v(int prec, const void* V, size_t vstride, int kmax, const void* y, const int* cnt, void* x,
+                     size_t nelem, int nrhs, double scale, unsigned nblk, hipStream_t s) {
+  const size_t nrow = nelem / nrhs;
+  VSWITCH(prec, hipLaunchKernelGGL((k_lincomb_v<PP>), dim3(nblk), dim3(256), 0, s,
+                                   (const typename vio<PP>::store*)V, vstride, kmax, (const cx<double>*)y, cnt,
+                                   (typename vio<PP>::store*)x, nrow, nrhs, scale));
+  return hipGetLastError();
+}
+
+}  // namespace lq

@@ -105,6 +105,69 @@ __device__ __forceinline__ void st_nt(h2_t* p, cx<float> a) {
   __builtin_nontemporal_store(v, p);
 }
 
+// NR consecutive complex numbers (consecutive rhs of one component) with
+// one vector access: FP32 x 2 = 16 B, FP16 x 2 = 8 B, FP16 x 4 = 16 B.
+typedef float f4v_t __attribute__((ext_vector_type(4)));
+typedef _Float16 h4v_t __attribute__((ext_vector_type(4)));
+typedef _Float16 h8v_t __attribute__((ext_vector_type(8)));
+
+template <int NR>
+__device__ __forceinline__ void ldn(const double2* p, cx<double>* o) {
+#pragma unroll
+  for (int r = 0; r < NR; ++r) o[r] = ld(p + r);
+}
+template <int NR>
+__device__ __forceinline__ void ldn(const float2* p, cx<float>* o) {
+  if (NR == 2) {
+    const f4v_t v = *(const f4v_t*)p;
+    o[0] = {v.x, v.y};
+    o[1] = {v.z, v.w};
+  } else {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) o[r] = ld(p + r);
+  }
+}
+template <int NR>
+__device__ __forceinline__ void ldn(const h2_t* p, cx<float>* o) {
+  if (NR == 2) {
+    const h4v_t v = *(const h4v_t*)p;
+    o[0] = {(float)v[0], (float)v[1]};
+    o[1] = {(float)v[2], (float)v[3]};
+  } else if (NR == 4) {
+    const h8v_t v = *(const h8v_t*)p;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) o[r] = {(float)v[2 * r], (float)v[2 * r + 1]};
+  } else {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) o[r] = ld(p + r);
+  }
+}
+template <int NR>
+__device__ __forceinline__ void stn(double2* p, const cx<double>* o) {
+#pragma unroll
+  for (int r = 0; r < NR; ++r) st(p + r, o[r]);
+}
+template <int NR>
+__device__ __forceinline__ void stn(float2* p, const cx<float>* o) {
+  if (NR == 2) {
+    f4v_t v = {o[0].re, o[0].im, o[1].re, o[1].im};
+    *(f4v_t*)p = v;
+  } else {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) st(p + r, o[r]);
+  }
+}
+template <int NR>
+__device__ __forceinline__ void stn(h2_t* p, const cx<float>* o) {
+  if (NR == 2) {
+    h4v_t v = {(_Float16)o[0].re, (_Float16)o[0].im, (_Float16)o[1].re, (_Float16)o[1].im};
+    *(h4v_t*)p = v;
+  } else {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) st(p + r, o[r]);
+  }
+}
+
 // ---------------------------------------------------------- block layout ---
 // Element (site, comp, rhs) of a spinor block with `nsites` sites, 12
 // components per site and nrhs right-hand sides.

@@ -96,7 +96,11 @@ static void launch_eo(const lqcd_lattice* lat, const void* U, const void* in, co
 // DAG_ = 1 selects D^dagger (hopping sign SG = -1)
 hipError_t wilson_full(const lqcd_lattice* lat, const void* U, const void* psi, void* eta, int nrhs, double diag,
                        double hopc, int layout, int prec, bool dagger, hipStream_t s) {
-  const kcfg c = choose_cfg(KIND_FULL, lat, nrhs, prec, layout);
+  kcfg c = choose_cfg(KIND_FULL, lat, nrhs, prec, layout);
+  if (c.variant == 4) {
+    if (nr_supported(prec, layout, nrhs)) return wilson_full_nr(lat, U, psi, eta, nrhs, diag, hopc, prec, dagger, c, s);
+    c.variant = 3;
+  }
   if (c.variant >= 2) return wilson_full_pencil(lat, U, psi, eta, nrhs, diag, hopc, layout, prec, dagger, c, s);
   LQ_DISPATCH(prec, layout, (dagger ? 1 : 0), launch_full, lat, U, psi, eta, nrhs, diag, hopc, s);
   return hipGetLastError();
@@ -105,7 +109,12 @@ hipError_t wilson_full(const lqcd_lattice* lat, const void* U, const void* psi, 
 hipError_t wilson_eo(const lqcd_lattice* lat, const void* U, const void* in, const void* xin, void* out, int p,
                      int nrhs, double alpha, double beta, int layout, int prec, bool dagger, const int* live,
                      hipStream_t s) {
-  const kcfg c = choose_cfg(KIND_EO, lat, nrhs, prec, layout);
+  kcfg c = choose_cfg(KIND_EO, lat, nrhs, prec, layout);
+  if (c.variant == 4) {
+    if (nr_supported(prec, layout, nrhs))
+      return wilson_eo_nr(lat, U, in, xin, out, p, nrhs, alpha, beta, prec, dagger, live, c, s);
+    c.variant = 3;
+  }
   if (c.variant >= 2)
     return wilson_eo_pencil(lat, U, in, xin, out, p, nrhs, alpha, beta, layout, prec, dagger, live, c, s);
   LQ_DISPATCH(prec, layout, (dagger ? 1 : 0), launch_eo, lat, U, in, xin, out, p, nrhs, alpha, beta, live, s);

@@ -20,7 +20,9 @@ hipError_t wilson_eo(const lqcd_lattice* lat, const void* U, const void* in, con
 
 // Kernel configuration of one apply.  variant: 1 one (site, rhs) per work
 // item, 2 time-streaming pencils with links staged in LDS, 3 pencils without
-// staging; ty, tz, nseg: pencil tile and t segments (0 = automatic).
+// staging, 4 pencils with two rhs per work item (FP32/FP16, rhs-innermost,
+// even nrhs; otherwise treated as 3); ty, tz, nseg: pencil tile and t segments
+// (0 = automatic).
 struct kcfg {
   int variant, ty, tz, nseg, nt;  // nt: non-temporal output stores (pencil variants)
 };
@@ -33,6 +35,15 @@ hipError_t wilson_full_pencil(const lqcd_lattice* lat, const void* U, const void
 hipError_t wilson_eo_pencil(const lqcd_lattice* lat, const void* U, const void* in, const void* xin, void* out,
                             int p, int nrhs, double alpha, double beta, int layout, int prec, bool dagger,
                             const int* live, const kcfg& c, hipStream_t s);
+
+// Pencil kernels with two rhs per work item (pencil_nr.hip): rhs-innermost
+// layout, FP32 / FP16 storage, even nrhs.
+bool nr_supported(int prec, int layout, int nrhs);
+hipError_t wilson_eo_nr(const lqcd_lattice* lat, const void* U, const void* in, const void* xin, void* out, int p,
+                        int nrhs, double alpha, double beta, int prec, bool dagger, const int* live, const kcfg& c,
+                        hipStream_t s);
+hipError_t wilson_full_nr(const lqcd_lattice* lat, const void* U, const void* psi, void* eta, int nrhs, double diag,
+                          double hopc, int prec, bool dagger, const kcfg& c, hipStream_t s);
 
 // Configuration for an apply (tune.hip): the process-wide forced setting if
 // any, else the autotuner's entry for these arguments, else the default.

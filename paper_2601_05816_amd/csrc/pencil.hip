@@ -17,64 +17,9 @@
 // mapping is a bijection for any tile shape; the tile shape and the number
 // of t segments only change locality.
 #include "kernels.h"
-#include "wilson.h"
+#include "pencil.h"
 
 namespace lq {
-
-struct pencil_geo {
-  int n[4];          // N0 = T, N1 = Z, N2 = Y, N3 = X
-  size_t V;
-  int TX, TY, TZ;    // column tile (in columns; TX counts compact columns for eo)
-  int NTX, NTY, NTZ; // tiles per direction
-  int nseg, Lt;      // t segments and their length
-  int bpt;           // workgroups per tile and segment
-  int ntiles;
-  int nt;            // non-temporal output stores
-};
-
-// (column coordinates, rhs, t0) of this work item, or false if idle.
-template <int LAYOUT>
-__device__ __forceinline__ bool pencil_item(const pencil_geo& pg, int nrhs, int& x, int& y, int& z, int& rhs,
-                                            int& t0) {
-  const unsigned b = blockIdx.x;
-  const unsigned k = b & 7u, i = b >> 3;
-  const unsigned u = i / pg.bpt, q = i % pg.bpt;
-  const unsigned grp = u / pg.nseg, seg = u % pg.nseg;
-  const unsigned tile = grp * 8u + k;
-  if (tile >= (unsigned)pg.ntiles) return false;
-  const unsigned CT = (unsigned)pg.TX * pg.TY * pg.TZ;
-  const unsigned tin = q * blockDim.x + threadIdx.x;
-  if (tin >= CT * (unsigned)nrhs) return false;
-  unsigned col;
-  if (LAYOUT == LQCD_RHS_OUTER) {
-    rhs = (int)(tin / CT);
-    col = tin % CT;
-  } else {
-    col = tin / nrhs;
-    rhs = (int)(tin % nrhs);
-  }
-  const int tx = tile % pg.NTX, ty = (tile / pg.NTX) % pg.NTY, tz = tile / (pg.NTX * pg.NTY);
-  x = tx * pg.TX + (int)(col % pg.TX);
-  y = ty * pg.TY + (int)((col / pg.TX) % pg.TY);
-  z = tz * pg.TZ + (int)(col / (pg.TX * pg.TY));
-  t0 = (int)seg * pg.Lt;
-  return true;
-}
-
-template <typename R>
-__device__ __forceinline__ half_spinor<R> hscale(R s, half_spinor<R> h) {
-#pragma unroll
-  for (int i = 0; i < 6; ++i) h.c[i / 3][i % 3] = scale(s, h.c[i / 3][i % 3]);
-  return h;
-}
-
-// acc += c * (hop term of direction MU with projector sign T) for a loaded
-// neighbour p and link u (ADJ: use u^dagger)
-template <int MU, int T, bool ADJ, typename S, typename R>
-__device__ __forceinline__ void add_hop(spinor<R>& acc, const spinor<R>& p, const S* __restrict__ u, R c) {
-  half_spinor<R> h = project<MU, T>(p);
-  reconstruct<MU, T>(acc, hscale(c, colour_mul<ADJ>(u, h)));
-}
 
 // ---------------------------------------------------------- full lattice
 template <int PREC, int LAYOUT, int SG>
@@ -428,59 +373,6 @@ __global__ __launch_bounds__(256) void k_wilson_eo_p(const typename prec_traits<
 }
 
 // ------------------------------------------------------------ configuration
-static int largest_divisor_at_most(int n, int cap) {
-  if (cap < 1) cap = 1;
-  for (int d = cap < n ? cap : n; d >= 1; --d)
-    if (n % d == 0) return d;
-  return 1;
-}
-
-// Tile: all of X, then as much of Y and Z as one XCD keeps resident (about
-// 16384 work items); segments: enough work items for several waves of
-// residency on the whole chip.  Entries of c that are > 0 and divide the
-// lattice override the automatic choice.
-static pencil_geo make_pencil(const lqcd_lattice* lat, int nrhs, bool eo, const kcfg& c) {
-  pencil_geo pg;
-  for (int i = 0; i < 4; ++i) pg.n[i] = lat->dims[i];
-  pg.V = (size_t)pg.n[0] * pg.n[1] * pg.n[2] * pg.n[3];
-  const int T = pg.n[0], NZ = pg.n[1], NY = pg.n[2], NX = pg.n[3];
-  pg.TX = eo ? NX / 2 : NX;
-  const int target_cols = (16384 / nrhs) > 0 ? 16384 / nrhs : 1;
-  int rest = target_cols / pg.TX;
-  if (rest < 1) rest = 1;
-  int TY = (c.ty > 0 && NY % c.ty == 0) ? c.ty : largest_divisor_at_most(NY, rest);
-  int TZ = (c.tz > 0 && NZ % c.tz == 0) ? c.tz : largest_divisor_at_most(NZ, rest / TY);
-  pg.TY = TY;
-  pg.TZ = TZ;
-  pg.NTX = 1;
-  pg.NTY = NY / TY;
-  pg.NTZ = NZ / TZ;
-  pg.ntiles = pg.NTY * pg.NTZ;
-  const size_t cols = (size_t)pg.TX * NY * NZ;
-  int nseg = 1;
-  if (c.nseg > 0 && T % c.nseg == 0) {
-    nseg = c.nseg;
-  } else {
-    const size_t want = 524288;
-    while (nseg < T && cols * (size_t)nrhs * nseg < want) {
-      int next = nseg + 1;
-      while (next < T && T % next) ++next;
-      nseg = next;
-    }
-  }
-  pg.nseg = nseg;
-  pg.Lt = T / nseg;
-  const size_t items = (size_t)pg.TX * TY * TZ * nrhs;
-  pg.bpt = (int)((items + 255) / 256);
-  pg.nt = c.nt;
-  return pg;
-}
-
-static unsigned pencil_blocks(const pencil_geo& pg) {
-  const unsigned ngroups = (unsigned)((pg.ntiles + 7) / 8);
-  return ngroups * 8u * (unsigned)pg.nseg * (unsigned)pg.bpt;
-}
-
 template <int PREC, int LAYOUT, int SG>
 static void launch_full_p(const lqcd_lattice* lat, const void* U, const void* psi, void* eta, int nrhs, double diag,
                           double hopc, const kcfg& c, hipStream_t s) {

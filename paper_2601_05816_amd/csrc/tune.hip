@@ -60,7 +60,7 @@ kcfg choose_cfg(int kind, const lqcd_lattice* lat, int nrhs, int prec, int layou
   return kDefault;
 }
 
-static std::vector<kcfg> candidates(const lqcd_lattice* lat, int layout) {
+static std::vector<kcfg> candidates(const lqcd_lattice* lat, int layout, int prec, int nrhs) {
   std::vector<kcfg> out;
   out.push_back({1, 0, 0, 0, 0});
   const int NZ = lat->dims[1], NY = lat->dims[2], T = lat->dims[0];
@@ -73,6 +73,7 @@ static std::vector<kcfg> candidates(const lqcd_lattice* lat, int layout) {
         if (sg && T % sg) continue;
         out.push_back({2, t[0], t[1], sg, nt});
         if (layout != LQCD_RHS_OUTER && t[0] == 0 && sg == 0) out.push_back({3, 0, 0, 0, nt});
+        if (nr_supported(prec, layout, nrhs)) out.push_back({4, t[0], t[1], sg, nt});
       }
     }
   return out;
@@ -85,7 +86,7 @@ using namespace lq;
 extern "C" {
 
 int lqcd_set_kernel_variant(int variant, const int32_t* pencil) {
-  if (variant < 0 || variant > 3) return fail(LQCD_ERR_ARG, "unknown kernel variant %d", variant);
+  if (variant < 0 || variant > 4) return fail(LQCD_ERR_ARG, "unknown kernel variant %d", variant);
   int p[3] = {0, 0, 0};
   if (pencil)
     for (int i = 0; i < 3; ++i) {
@@ -101,7 +102,7 @@ int lqcd_set_kernel_config(const lqcd_kernel_config* c) {
     set_forced(kcfg{0, 0, 0, 0, 0});
     return LQCD_OK;
   }
-  if (c->variant < 0 || c->variant > 3) return fail(LQCD_ERR_ARG, "unknown kernel variant %d", c->variant);
+  if (c->variant < 0 || c->variant > 4) return fail(LQCD_ERR_ARG, "unknown kernel variant %d", c->variant);
   if (c->tile_y < 0 || c->tile_z < 0 || c->segments < 0) return fail(LQCD_ERR_ARG, "negative kernel parameter");
   set_forced(kcfg{c->variant, c->tile_y, c->tile_z, c->segments, c->nontemporal ? 1 : 0});
   return LQCD_OK;
@@ -127,7 +128,7 @@ int lqcd_autotune(const lqcd_lattice* lat, const void* U, const void* psi, void*
   double best_ms = 1e300;
   kcfg best_c = kDefault;
   int err = LQCD_OK;
-  for (const kcfg& c : candidates(lat, layout)) {
+  for (const kcfg& c : candidates(lat, layout, prec, nrhs)) {
     set_forced(c);
     // one hop pass of the Schur operator (the kernel a Schur apply runs twice)
     auto run = [&]() -> hipError_t {
@@ -204,7 +205,7 @@ int lqcd_tune_load(const char* path) {
     if (sscanf(line, "%d %d %d %d %d %d %d %d : %d %d %d %d %d %lf", &k[0], &k[1], &k[2], &k[3], &k[4], &k[5], &k[6],
                &k[7], &c[0], &c[1], &c[2], &c[3], &c[4], &ms) != 14)
       continue;
-    if (c[0] < 1 || c[0] > 3) continue;
+    if (c[0] < 1 || c[0] > 4) continue;
     g_table[tkey(k[0], k[1], k[2], k[3], k[4], k[5], k[6], k[7])] = std::make_pair(kcfg{c[0], c[1], c[2], c[3], c[4]}, ms);
     ++n;
   }

@@ -62,6 +62,39 @@ __device__ __forceinline__ void reconstruct(spinor<R>& acc, const half_spinor<R>
   }
 }
 
+template <typename R>
+struct su3 {
+  cx<R> m[3][3];
+};
+
+template <typename S, typename R>
+__device__ __forceinline__ su3<R> load_link(const S* __restrict__ u) {
+  su3<R> a;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) a.m[i / 3][i % 3] = ld(u + i);
+  return a;
+}
+
+// r = U h (ADJ = false) or U^dag h (ADJ = true) for a link held in registers
+template <bool ADJ, typename R>
+__device__ __forceinline__ half_spinor<R> colour_mul_r(const su3<R>& u, const half_spinor<R>& h) {
+  half_spinor<R> r;
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      cx<R> acc = {R(0), R(0)};
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        if (ADJ) acc = cjmadd(acc, u.m[b][a], h.c[s][b]);
+        else     acc = cmadd(acc, u.m[a][b], h.c[s][b]);
+      }
+      r.c[s][a] = acc;
+    }
+  }
+  return r;
+}
+
 // r = U h (ADJ = false) or U^dag h (ADJ = true); U row-major 3x3 in memory.
 template <bool ADJ, typename S, typename R>
 __device__ __forceinline__ half_spinor<R> colour_mul(const S* __restrict__ u, const half_spinor<R>& h) {

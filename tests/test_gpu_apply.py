@@ -206,3 +206,24 @@ def test_nontemporal_stores_and_autotuned_choice(gpu_lib, kernel_variant, nt):
     got = from_layout_np(from_dev(lq.dirac_apply(Ud, pd, -0.05, layout=lq.LAYOUT2), lq.F64), lq.LAYOUT2, 4)
     assert np.all(rel_err_per_rhs(got, want) <= TOL[lq.F64])
     gpu_lib.tune_clear()
+
+
+@pytest.mark.parametrize("prec", [lq.F32, lq.F16])
+@pytest.mark.parametrize("nrhs", [2, 6, 16])
+@pytest.mark.parametrize("pencil", [(0, 0, 0), (2, 1, 3), (1, 2, 1)])
+def test_two_rhs_per_lane_kernels(gpu_lib, kernel_variant, prec, nrhs, pencil):
+    """Variant 4 (two rhs per work item, vector loads) for FP32 and FP16, full
+    and Schur applies, D and D^dagger, several tilings."""
+    if kernel_variant != 3:
+        pytest.skip("run once")
+    gpu_lib.set_kernel_variant(4, pencil)
+    dims = (6, 4, 6, 4)
+    U = rounded(syn.gauge_field(dims, "haar", config=11), prec)
+    psi = rounded(syn.spinor_block(dims, nrhs, config=11), prec)
+    for dagger in (False, True):
+        want = (dirac.apply_dw_dagger if dagger else dirac.apply_dw)(U, psi, 0.1)
+        got = _apply_gpu(U, psi, 0.1, lq.LAYOUT2, prec, dagger)
+        assert np.all(rel_err_per_rhs(got, want) <= TOL[prec])
+    psi_e = geometry.to_half(psi, dims, 0)
+    got = _apply_eo_gpu(U, psi_e, 0.1, lq.LAYOUT2, prec)
+    assert np.all(rel_err_per_rhs(got, evenodd.apply_schur(U, psi_e, 0.1)) <= TOL[prec] * 2)

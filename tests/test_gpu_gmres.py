@@ -172,3 +172,19 @@ def test_adjoint_solve(gpu_lib, eo, mode):
     x, st, rc = _solve(U, b, m0, eo=eo, mode=mode, tol=1e-10, dagger=True)
     assert rc == lq.OK
     assert np.all(rel_err_per_rhs(dirac.apply_dw_dagger(U, x, m0), b) <= 1e-10)
+
+
+@pytest.mark.parametrize("mode", ["ir-f32", "ir-f16"])
+@pytest.mark.parametrize("variant", [0, 4])
+def test_refinement_vector_paths(gpu_lib, mode, variant):
+    """nrhs divisible by four: the 16-byte-per-lane BLAS kernels of the FP32 /
+    FP16 bases and (variant 4) the two-rhs-per-lane Schur kernels."""
+    gpu_lib.set_kernel_variant(variant)
+    dims = (8, 8, 4, 8)
+    m0 = 0.05
+    U = syn.gauge_field(dims, "near_identity", config=9, eps=0.3)
+    b = syn.spinor_block(dims, 8, config=9)
+    x, st, rc = _solve(U, b, m0, restart=16, eo=True, mode=mode, tol=1e-10)
+    gpu_lib.set_kernel_variant(0)
+    assert rc == lq.OK
+    assert np.all(_true_relres(U, b, x, m0) <= 1e-10)
