@@ -33,6 +33,16 @@ CONFIG = 3
 FLOP_SITE_RHS = 1392          # 1320 projected hopping + 72 diagonal/combine
 SCHUR_FLOP_SITE_RHS = 2712    # per even site: two hopping passes + axpy
 HBM_PEAK_GBS = 8000.0
+TUNE_FILE = os.path.join(ROOT, "paper_2601_05816_amd", "tune_mi355x.txt")
+# HBM traffic of the headline kernel per launch, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (scaled by what the counters report for a plain device copy of
+# known size), keyed by kernel configuration (variant, tile_y, tile_z,
+# segments, nontemporal, wg_per_cu); reported only for the configuration the
+# counters were taken on.
+TRAFFIC = {
+    (3, 4, 4, 1, 1, 1): {"read_bytes": 16_949_914_000, "write_bytes": 6_442_458_000,
+                         "profile": "profiles/wilson_full_pencil_32x32x32x64_nrhs16_f64.md"},
+}
 
 
 def bytes_full(v, nrhs, esz):
@@ -43,6 +53,25 @@ def bytes_full(v, nrhs, esz):
 def bytes_schur_two_pass(v, nrhs, esz):
     """Two hopping passes over half lattices: links twice, in/tmp/out spinors."""
     return (2 * 36 + 60 * nrhs) * esz * (v // 2)
+
+
+def table_entry(path, kind, dims, nrhs, prec, layout):
+    """The autotuner table's configuration for (kind, dims, nrhs, prec, layout), or None."""
+    want = [kind, *dims, nrhs, prec, layout]
+    for line in open(path):
+        if line.startswith("#") or ":" not in line:
+            continue
+        k, v = line.split(":", 1)
+        try:
+            if [int(a) for a in k.split()] != want:
+                continue
+            vals = v.split()
+            c = [int(a) for a in vals[:-1]] + [0] * (6 - len(vals[:-1]))
+            return {"variant": c[0], "tile_y": c[1], "tile_z": c[2], "segments": c[3], "nontemporal": c[4],
+                    "wg_per_cu": c[5], "ms": float(vals[-1])}
+        except ValueError:
+            continue
+    return None
 
 
 def log(msg):
@@ -127,6 +156,107 @@ def gmres_section(lq, U64, psi64, nrhs):
     return out
 
 
+def batch_section(lq, syn, steps):
+    """The uneven eight-lattice batch (L = 8..24, T = 2L, eps_k = 0.2 + 0.3 k/7,
+    1..32 rhs each, m0 = -0.05): the FP32 apply of all eight lattices in one
+    persistent launch against eight separate launches, and the batched GMRES(30)
+    to a true 1e-10 (FP32 operator inside FP64 refinement, hipGraph-captured
+    Arnoldi steps) against solving the lattices one after the other."""
+    import torch
+
+    dev = torch.device("cuda:0")
+    comp = syn.batch_composition()
+    t0 = time.time()
+    probs64 = []
+    for c in comp:
+        U = syn.gauge_field(c["dims"], "near_identity", config=40 + c["index"], eps=c["eps"])
+        b = syn.spinor_block(c["dims"], c["nrhs"], config=40 + c["index"])
+        probs64.append((torch.from_numpy(U).to(dev), torch.from_numpy(np.ascontiguousarray(np.moveaxis(b, 0, -1))).to(dev),
+                        M0))
+    log(f"batch inputs generated ({time.time() - t0:.1f}s)")
+    out = {"lattices": [list(c["dims"]) for c in comp], "nrhs": [c["nrhs"] for c in comp],
+           "eps": [round(c["eps"], 4) for c in comp], "m0": M0}
+    # ------------------------------------------------ FP32 apply, one launch vs eight
+    probs32 = [(U.to(torch.complex64), b.to(torch.complex64), m0) for U, b, m0 in probs64]
+    outs = [torch.empty_like(b) for _, b, _ in probs32]
+    grid = lq.autotune_batch(probs32, outs, reps=3)
+    t_batch = timed(lambda: lq.dirac_apply_batch(probs32, outs=outs), steps, 2)
+    for U, b, m0 in probs32:
+        lq.autotune(U, b, torch.empty_like(b), m0, layout=lq.LAYOUT2, reps=2)
+    t_seq = timed(lambda: [lq.dirac_apply(U, b, m0, layout=lq.LAYOUT2, out=o) for (U, b, m0), o in zip(probs32, outs)],
+                  steps, 2)
+    nbytes = sum(bytes_full(int(np.prod(c["dims"])), c["nrhs"], 8) for c in comp)
+    out["apply_f32"] = {"one_launch_ms": round(t_batch, 4), "eight_launches_ms": round(t_seq, 4),
+                        "persistent_grid": grid, "gbs_one_launch": round(nbytes / t_batch / 1e6, 1),
+                        "gbs_eight_launches": round(nbytes / t_seq / 1e6, 1)}
+    log(f"batch apply FP32: one launch {t_batch:.3f} ms, eight launches {t_seq:.3f} ms")
+    del probs32, outs
+    torch.cuda.empty_cache()
+    # ------------------------------------------------ batched GMRES vs one solve per lattice
+    kw = dict(restart=30, eo=True, mode="ir-f32", tol=1e-10, max_restarts=400, max_outer=60)
+    torch.cuda.synchronize()
+    t = time.time()
+    xs, stats, rc = lq.gmres_solve_batch(probs64, use_graph=True, **kw)
+    torch.cuda.synchronize()
+    t_bs = time.time() - t
+    rec = {"seconds": round(t_bs, 3), "status": int(rc),
+           "converged": bool(all(st["converged"].all() for st in stats)),
+           "max_true_relres": float(max(st["true_relres"].max() for st in stats)),
+           "iters_max": [int(st["iters"].max()) for st in stats]}
+    del xs
+    torch.cuda.empty_cache()
+    torch.cuda.synchronize()
+    t = time.time()
+    seq_ok, seq_res = True, 0.0
+    for U, b, m0 in probs64:
+        x, st, rc1 = lq.gmres_solve(U, b, m0, layout=lq.LAYOUT2, use_graph=True, **kw)
+        seq_ok &= bool(st["converged"].all())
+        seq_res = max(seq_res, float(st["true_relres"].max()))
+        del x
+    torch.cuda.synchronize()
+    t_ss = time.time() - t
+    out["gmres_ir_f32"] = {"batched": rec, "one_lattice_at_a_time": {"seconds": round(t_ss, 3), "converged": seq_ok,
+                                                                       "max_true_relres": seq_res},
+                           "speedup_batched": round(t_ss / t_bs, 3), "restart": 30, "tol": 1e-10}
+    log(f"batch GMRES ir-f32: batched {t_bs:.3f} s, one at a time {t_ss:.3f} s")
+    return out
+
+
+def autograd_section(lq, syn):
+    """Differentiation at 16^3 x 32, nrhs = 8, m0 = 0.05: forward solve, then the
+    backward of L = sum_i Re<chi_i, x_i> (adjoint solve, link force, dL/dm0)."""
+    import torch
+
+    from paper_2601_05816_amd.autograd import wilson_solve
+
+    dev = torch.device("cuda:0")
+    dims, nrhs, m0 = (32, 16, 16, 16), 8, 0.05
+    U = torch.from_numpy(syn.gauge_field(dims, "near_identity", config=5, eps=EPS)).to(dev).requires_grad_(True)
+    eta = torch.from_numpy(np.ascontiguousarray(np.moveaxis(syn.spinor_block(dims, nrhs, config=5), 0, -1))).to(dev)
+    chi = torch.from_numpy(np.ascontiguousarray(np.moveaxis(syn.spinor_block(dims, nrhs, config=5, role=syn.ROLE_CHI), 0, -1))).to(dev)
+    eta.requires_grad_(True)
+    m = torch.tensor(m0, dtype=torch.float64, device=dev, requires_grad=True)
+    res = {}
+    for rep in range(2):  # the second repetition is reported (first-call set-up excluded)
+        torch.cuda.synchronize()
+        t = time.time()
+        x = wilson_solve(U, eta, m, restart=30, eo=True, tol=1e-10)
+        torch.cuda.synchronize()
+        t_fwd = time.time() - t
+        loss = (torch.conj(chi) * x).real.sum()
+        t = time.time()
+        loss.backward()
+        torch.cuda.synchronize()
+        t_bwd = time.time() - t
+        res = {"lattice": list(dims), "nrhs": nrhs, "m0": m0, "forward_solve_s": round(t_fwd, 3),
+               "backward_s": round(t_bwd, 3), "grad_U_norm": float(U.grad.norm()), "grad_m0": float(m.grad)}
+        U.grad = None
+        eta.grad = None
+        m.grad = None
+    log(f"autograd: forward {res['forward_solve_s']} s, backward {res['backward_s']} s")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,12 +268,18 @@ def main():
                     help="draw the inputs on the GPU (seeded torch generator) instead of the seeded host "
                          "recipe; for profiling runs, where values do not matter")
     ap.add_argument("--no-gmres", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the uneven eight-lattice batch")
+    ap.add_argument("--no-autograd", action="store_true", help="skip the differentiation timing")
     ap.add_argument("--gmres-nrhs", type=int, default=NRHS)
     ap.add_argument("--variant", type=int, default=0, help="Wilson kernel: 0 auto, 1 site, 2 pencil")
     ap.add_argument("--pencil", type=str, default="",
-                    help="tile Y,tile Z,t segments[,nontemporal] for the pencil kernels")
+                    help="tile Y,tile Z,t segments[,nontemporal[,workgroups per CU]] for the pencil kernels")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 2 GiB device copy (for scaling HBM byte counters)")
+    ap.add_argument("--tune-file", default=TUNE_FILE,
+                    help="kernel configurations measured by the autotuner on MI355X (used when present)")
+    ap.add_argument("--retune", action="store_true", help="ignore the tune file and autotune every apply")
+    ap.add_argument("--save-tune", default="", help="write the autotuner's table here at the end")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the multi-rhs apply and GMRES are single-device here "
@@ -158,7 +294,7 @@ def main():
     lq.load()
     if args.variant or args.pencil:
         pv = [int(v) for v in args.pencil.split(",")] if args.pencil else [0, 0, 0, 0]
-        pv += [0] * (4 - len(pv))
+        pv += [0] * (5 - len(pv))
         lq.set_kernel_config(args.variant or 2, *pv)
     dev = torch.device("cuda:0")
     v = int(np.prod(DIMS))
@@ -195,9 +331,13 @@ def main():
 
     # ---------------------------------------------------------------- headline
     tuned = None
-    if args.variant == 0 and not args.pencil:
+    use_table = args.variant == 0 and not args.pencil and not args.retune and os.path.exists(args.tune_file)
+    if use_table:
+        lq.tune_load(args.tune_file)
+        tuned = table_entry(args.tune_file, 0, DIMS, NRHS, lq.F64, lq.LAYOUT2)
+    if args.variant == 0 and not args.pencil and tuned is None:
         tuned = lq.autotune(U64, psi64, eta64, M0, layout=lq.LAYOUT2, reps=3)
-        log(f"autotuned kernel: {tuned}")
+    log(f"kernel configuration: {tuned} ({'tune file' if use_table else 'autotuned now'})")
 
     def step():
         lq.dirac_apply(U64, psi64, M0, layout=lq.LAYOUT2, out=eta64)
@@ -231,6 +371,12 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
     }
+    key = None if tuned is None else tuple(int(tuned[k]) for k in ("variant", "tile_y", "tile_z", "segments",
+                                                                    "nontemporal", "wg_per_cu"))
+    if key in TRAFFIC:
+        tr = TRAFFIC[key]
+        result["roofline"]["traffic"] = tr["read_bytes"] + tr["write_bytes"]
+        result["traffic_detail"] = dict(tr, key=list(key))
 
     if args.copy_calibration:
         n = (2 << 30) // 16
@@ -254,13 +400,13 @@ def main():
                 x = base if prec == lq.F64 else (base.to(torch.complex64) if prec == lq.F32 else to_f16(base))
                 y = torch.empty_like(x)
                 steps = max(5, args.steps // 5)
-                if args.variant == 0 and not args.pencil:
+                if args.variant == 0 and not args.pencil and not use_table:
                     lq.autotune(Up, x, y, M0, layout=lq.LAYOUT2, reps=2)
                 t_full = timed(lambda: lq.dirac_apply(Up, x, M0, layout=lq.LAYOUT2, out=y), steps, 2)
                 # a half-lattice block of the same rhs count (values do not affect timing)
                 xe = x.reshape((v,) + tuple(x.shape[4:]))[:half].contiguous()
                 ye = torch.empty_like(xe)
-                if args.variant == 0 and not args.pencil:
+                if args.variant == 0 and not args.pencil and not use_table:
                     lq.autotune(Up, xe, ye, M0, layout=lq.LAYOUT2, eo=True, reps=2)
                 t_eo = timed(lambda: lq.dirac_apply_eo(Up, xe, M0, layout=lq.LAYOUT2, out=ye), steps, 2)
                 rec = {"prec": prec_name, "nrhs": n,
@@ -282,19 +428,28 @@ def main():
     if not args.no_gmres:
         result["gmres"] = gmres_section(lq, U64, psi64, args.gmres_nrhs)
 
+    # ------------------------------------------- uneven batch, differentiation
+    if not args.no_batch:
+        result["batch"] = batch_section(lq, syn, max(5, args.steps // 5))
+    if not args.no_autograd:
+        result["autograd"] = autograd_section(lq, syn)
+
     # ------------------------------------------------------- oracle baseline
     if not args.no_cpu:
         from oracle import dirac
 
+        nb = 2
         t = time.time()
-        dirac.apply_dw(U, psi_np[:1], M0)
+        dirac.apply_dw(U, psi_np[:nb], M0)
         dt = time.time() - t
         result["cpu_baseline"] = {
-            "value": round(FLOP_SITE_RHS * v / dt / 1e9, 3), "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
-            "sample": f"one rhs of the same 32^3x64 apply (complex128 NumPy, single-threaded einsum), {dt:.1f} s",
+            "value": round(FLOP_SITE_RHS * v * nb / dt / 1e9, 3), "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+            "sample": f"{nb} of the 16 rhs of the same 32^3x64 apply (complex128 NumPy, single-threaded), {dt:.1f} s",
             "host_cpus": os.cpu_count()}
-        log(f"oracle: {dt:.1f} s for one rhs")
+        log(f"oracle: {dt:.1f} s for {nb} rhs")
 
+    if args.save_tune:
+        lq.tune_save(args.save_tune)
     print(json.dumps(result), flush=True)
 
 

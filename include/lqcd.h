@@ -85,7 +85,10 @@ int lqcd_lattice_tables(const lqcd_lattice* lat, int32_t* nbr, int32_t* eo_site)
  * tests).  variant 0 = automatic, 1 = one (site, rhs) per work item,
  * 2 = time-streaming pencils with the links of each step staged in LDS,
  * 3 = pencils without LDS staging, 4 = pencils with two rhs per work item
- * (FP32 / FP16 storage, LQCD_LAYOUT2, even nrhs; otherwise as 3).  pencil (may be NULL) = {tile Y, tile Z,
+ * (FP32 / FP16 storage, LQCD_LAYOUT2, even nrhs; otherwise as 3), 5 = pencils
+ * whose neighbour spinors and links arrive through asynchronous
+ * global-to-LDS loads, several hops in flight per wavefront (full operator,
+ * FP64, LQCD_LAYOUT2, nrhs >= 11; otherwise as 3).  pencil (may be NULL) = {tile Y, tile Z,
  * number of t segments} for variants 2 and 3; 0 entries are chosen automatically, values
  * that do not divide the lattice fall back to automatic.  Every choice
  * computes the same sums; results agree to rounding.  Not thread-safe
@@ -94,11 +97,14 @@ int lqcd_set_kernel_variant(int variant, const int32_t* pencil);
 
 /* Full kernel configuration (for tuning and tests; process-wide).
  * variant: 0 automatic (the autotuner's entry for the arguments, else the
- * default), 1, 2 or 3 as above; tile_y, tile_z, segments: pencil tile and t
+ * default), 1 to 5 as above; tile_y, tile_z, segments: pencil tile and t
  * segments (0 = automatic); nontemporal: 1 = output stores bypass L2
- * allocation.  NULL restores automatic selection.  ms is ignored. */
+ * allocation; wg_per_cu (0..8): pencil variants run at most this many
+ * workgroups per compute unit at a time (0 = no cap; the cap is imposed
+ * through the LDS request and an apply whose cap the device cannot express
+ * returns LQCD_ERR_HIP).  NULL restores automatic selection.  ms is ignored. */
 typedef struct {
-  int32_t variant, tile_y, tile_z, segments, nontemporal;
+  int32_t variant, tile_y, tile_z, segments, nontemporal, wg_per_cu;
   double ms;  /* measured time of one launch (filled by the autotuner) */
 } lqcd_kernel_config;
 int lqcd_set_kernel_config(const lqcd_kernel_config* cfg);

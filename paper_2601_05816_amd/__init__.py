@@ -58,7 +58,8 @@ MAX_BATCH = 16
 
 class KernelConfig(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("tile_y", ctypes.c_int32), ("tile_z", ctypes.c_int32),
-                ("segments", ctypes.c_int32), ("nontemporal", ctypes.c_int32), ("ms", ctypes.c_double)]
+                ("segments", ctypes.c_int32), ("nontemporal", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
+                ("ms", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -156,12 +157,12 @@ def set_kernel_variant(variant=0, pencil=None):
     _check(load().lqcd_set_kernel_variant(int(variant), arr))
 
 
-def set_kernel_config(variant=0, tile_y=0, tile_z=0, segments=0, nontemporal=0):
+def set_kernel_config(variant=0, tile_y=0, tile_z=0, segments=0, nontemporal=0, wg_per_cu=0):
     """Force a Wilson kernel configuration (variant 0 = automatic selection)."""
-    if variant == 0 and not (tile_y or tile_z or segments or nontemporal):
+    if variant == 0 and not (tile_y or tile_z or segments or nontemporal or wg_per_cu):
         _check(load().lqcd_set_kernel_config(None))
         return
-    c = KernelConfig(int(variant), int(tile_y), int(tile_z), int(segments), int(nontemporal), 0.0)
+    c = KernelConfig(int(variant), int(tile_y), int(tile_z), int(segments), int(nontemporal), int(wg_per_cu), 0.0)
     _check(load().lqcd_set_kernel_config(ctypes.byref(c)))
 
 

@@ -21,10 +21,12 @@ hipError_t wilson_eo(const lqcd_lattice* lat, const void* U, const void* in, con
 // Kernel configuration of one apply.  variant: 1 one (site, rhs) per work
 // item, 2 time-streaming pencils with links staged in LDS, 3 pencils without
 // staging, 4 pencils with two rhs per work item (FP32/FP16, rhs-innermost,
-// even nrhs; otherwise treated as 3); ty, tz, nseg: pencil tile and t segments
-// (0 = automatic).
+// even nrhs; otherwise treated as 3), 5 pencils fed by global-to-LDS loads
+// (FP64, rhs-innermost, nrhs >= 11, full operator; otherwise treated as 3); ty, tz, nseg: pencil tile and t segments
+// (0 = automatic); nt: non-temporal output stores; occ: at most this many
+// workgroups per compute unit (0 = no cap), enforced through the LDS request.
 struct kcfg {
-  int variant, ty, tz, nseg, nt;  // nt: non-temporal output stores (pencil variants)
+  int variant, ty, tz, nseg, nt, occ;
 };
 enum { KIND_FULL = 0, KIND_EO = 1 };
 
@@ -44,6 +46,12 @@ hipError_t wilson_eo_nr(const lqcd_lattice* lat, const void* U, const void* in, 
                         hipStream_t s);
 hipError_t wilson_full_nr(const lqcd_lattice* lat, const void* U, const void* psi, void* eta, int nrhs, double diag,
                           double hopc, int prec, bool dagger, const kcfg& c, hipStream_t s);
+
+// Pencil kernel fed by global-to-LDS loads (pencil_dma.hip): FP64 storage,
+// rhs-innermost layout, nrhs >= 11.
+bool dma_supported(int prec, int layout, int nrhs);
+hipError_t wilson_full_dma(const lqcd_lattice* lat, const void* U, const void* psi, void* eta, int nrhs, double diag,
+                           double hopc, int prec, bool dagger, const kcfg& c, hipStream_t s);
 
 // Configuration for an apply (tune.hip): the process-wide forced setting if
 // any, else the autotuner's entry for these arguments, else the default.

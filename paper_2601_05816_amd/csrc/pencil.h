@@ -109,6 +109,13 @@ inline pencil_geo make_pencil(const lqcd_lattice* lat, int nrhs, bool eo, const 
   return pg;
 }
 
+// Dynamic LDS bytes that cap residency at `occ` workgroups per compute unit
+// for a kernel with `static_bytes` of its own LDS: each workgroup asks for a
+// little more than 1/(occ+1) of the compute unit's LDS.  occ = 0: no cap.
+// Returns false if the cap cannot be expressed on this device (a workgroup
+// may not request that much LDS).
+bool occupancy_lds(int occ, size_t static_bytes, size_t* dyn_bytes);
+
 inline unsigned pencil_blocks(const pencil_geo& pg) {
   const unsigned ngroups = (unsigned)((pg.ntiles + 7) / 8);
   return ngroups * 8u * (unsigned)pg.nseg * (unsigned)pg.bpt;

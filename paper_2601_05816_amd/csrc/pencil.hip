@@ -373,42 +373,71 @@ __global__ __launch_bounds__(256) void k_wilson_eo_p(const typename prec_traits<
 }
 
 // ------------------------------------------------------------ configuration
-template <int PREC, int LAYOUT, int SG>
-static void launch_full_p(const lqcd_lattice* lat, const void* U, const void* psi, void* eta, int nrhs, double diag,
-                          double hopc, const kcfg& c, hipStream_t s) {
-  typedef typename prec_traits<PREC>::store S;
-  typedef typename prec_traits<PREC>::real R;
-  pencil_geo pg = make_pencil(lat, nrhs, false, c);
-  if (LAYOUT != LQCD_RHS_OUTER && c.variant == 2 && nrhs >= 4) {
-    const dim3 grid(pencil_blocks(pg)), blk(256);
-    if (nrhs >= 16)
-      hipLaunchKernelGGL((k_wilson_full_pl<PREC, LAYOUT, SG, 5>), grid, blk, 0, s, (const S*)U, (const S*)psi,
-                         (S*)eta, pg, nrhs, (R)diag, (R)hopc);
-    else if (nrhs >= 8)
-      hipLaunchKernelGGL((k_wilson_full_pl<PREC, LAYOUT, SG, 9>), grid, blk, 0, s, (const S*)U, (const S*)psi,
-                         (S*)eta, pg, nrhs, (R)diag, (R)hopc);
-    else
-      hipLaunchKernelGGL((k_wilson_full_pl<PREC, LAYOUT, SG, 17>), grid, blk, 0, s, (const S*)U, (const S*)psi,
-                         (S*)eta, pg, nrhs, (R)diag, (R)hopc);
-    return;
-  }
-  hipLaunchKernelGGL((k_wilson_full_p<PREC, LAYOUT, SG>), dim3(pencil_blocks(pg)), dim3(256), 0, s, (const S*)U,
-                     (const S*)psi, (S*)eta, pg, nrhs, (R)diag, (R)hopc);
+bool occupancy_lds(int occ, size_t static_bytes, size_t* dyn_bytes) {
+  *dyn_bytes = 0;
+  if (occ <= 0) return true;
+  int dev = 0, per_cu = 0, per_wg = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  if (hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
+      per_cu <= 0)
+    per_cu = 160 * 1024;
+  if (hipDeviceGetAttribute(&per_wg, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || per_wg <= 0)
+    per_wg = 64 * 1024;
+  // allocation granularity is 512 bytes; occ + 1 requests must overflow the CU
+  size_t want = ((size_t)per_cu / (size_t)(occ + 1) + 512) & ~(size_t)511;
+  if (want * (size_t)occ > (size_t)per_cu || want > (size_t)per_wg) return false;
+  *dyn_bytes = want > static_bytes ? want - static_bytes : 0;
+  return true;
 }
 
 template <int PREC, int LAYOUT, int SG>
-static void launch_eo_p(const lqcd_lattice* lat, const void* U, const void* in, const void* xin, void* out, int p,
-                        int nrhs, double alpha, double beta, const int* live, const kcfg& c, hipStream_t s) {
+static hipError_t launch_full_p(const lqcd_lattice* lat, const void* U, const void* psi, void* eta, int nrhs,
+                                double diag, double hopc, const kcfg& c, hipStream_t s) {
+  typedef typename prec_traits<PREC>::store S;
+  typedef typename prec_traits<PREC>::real R;
+  pencil_geo pg = make_pencil(lat, nrhs, false, c);
+  const dim3 grid(pencil_blocks(pg)), blk(256);
+  size_t dyn = 0;
+  if (LAYOUT != LQCD_RHS_OUTER && c.variant == 2 && nrhs >= 4) {
+    const int ncw = nrhs >= 16 ? 5 : (nrhs >= 8 ? 9 : 17);
+    if (!occupancy_lds(c.occ, 4 * (size_t)ncw * 63 * sizeof(S), &dyn)) return hipErrorInvalidConfiguration;
+    if (nrhs >= 16)
+      hipLaunchKernelGGL((k_wilson_full_pl<PREC, LAYOUT, SG, 5>), grid, blk, dyn, s, (const S*)U, (const S*)psi,
+                         (S*)eta, pg, nrhs, (R)diag, (R)hopc);
+    else if (nrhs >= 8)
+      hipLaunchKernelGGL((k_wilson_full_pl<PREC, LAYOUT, SG, 9>), grid, blk, dyn, s, (const S*)U, (const S*)psi,
+                         (S*)eta, pg, nrhs, (R)diag, (R)hopc);
+    else
+      hipLaunchKernelGGL((k_wilson_full_pl<PREC, LAYOUT, SG, 17>), grid, blk, dyn, s, (const S*)U, (const S*)psi,
+                         (S*)eta, pg, nrhs, (R)diag, (R)hopc);
+    return hipSuccess;
+  }
+  if (!occupancy_lds(c.occ, 0, &dyn)) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((k_wilson_full_p<PREC, LAYOUT, SG>), grid, blk, dyn, s, (const S*)U, (const S*)psi, (S*)eta,
+                     pg, nrhs, (R)diag, (R)hopc);
+  return hipSuccess;
+}
+
+template <int PREC, int LAYOUT, int SG>
+static hipError_t launch_eo_p(const lqcd_lattice* lat, const void* U, const void* in, const void* xin, void* out,
+                              int p, int nrhs, double alpha, double beta, const int* live, const kcfg& c,
+                              hipStream_t s) {
   typedef typename prec_traits<PREC>::store S;
   typedef typename prec_traits<PREC>::real R;
   pencil_geo pg = make_pencil(lat, nrhs, true, c);
-  hipLaunchKernelGGL((k_wilson_eo_p<PREC, LAYOUT, SG>), dim3(pencil_blocks(pg)), dim3(256), 0, s, (const S*)U,
+  size_t dyn = 0;
+  if (!occupancy_lds(c.occ, 0, &dyn)) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((k_wilson_eo_p<PREC, LAYOUT, SG>), dim3(pencil_blocks(pg)), dim3(256), dyn, s, (const S*)U,
                      (const S*)in, (const S*)xin, (S*)out, pg, p, nrhs, (R)alpha, (R)beta, live);
+  return hipSuccess;
 }
 
 #define LQ_KEY(p, l, d) ((p) * 100 + (l) * 10 + (d))
 #define LQ_CASE(P, L, D, FN, ...) \
-  case LQ_KEY(P, L, D): FN<P, L, (D) ? -1 : 1>(__VA_ARGS__); break;
+  case LQ_KEY(P, L, D): {                                \
+    hipError_t e_ = FN<P, L, (D) ? -1 : 1>(__VA_ARGS__);  \
+    if (e_ != hipSuccess) return e_;                     \
+  } break;
 #define LQ_CASES_L(P, D, FN, ...)                   \
   LQ_CASE(P, LQCD_RHS_OUTER, D, FN, __VA_ARGS__)    \
   LQ_CASE(P, LQCD_LAYOUT1, D, FN, __VA_ARGS__)      \

@@ -255,23 +255,29 @@ __global__ __launch_bounds__(256) void k_wilson_full_pn(const typename prec_trai
 
 // ------------------------------------------------------------- launchers
 template <int PREC, int SG, int NR>
-static void go_eo(const lqcd_lattice* lat, const void* U, const void* in, const void* xin, void* out, int p, int nrhs,
-                  double alpha, double beta, const int* live, const kcfg& c, hipStream_t s) {
+static hipError_t go_eo(const lqcd_lattice* lat, const void* U, const void* in, const void* xin, void* out, int p,
+                        int nrhs, double alpha, double beta, const int* live, const kcfg& c, hipStream_t s) {
   typedef typename prec_traits<PREC>::store S;
   typedef typename prec_traits<PREC>::real R;
   pencil_geo pg = make_pencil(lat, nrhs / NR, true, c);
-  hipLaunchKernelGGL((k_wilson_eo_pn<PREC, SG, NR>), dim3(pencil_blocks(pg)), dim3(256), 0, s, (const S*)U,
+  size_t dyn = 0;
+  if (!occupancy_lds(c.occ, 0, &dyn)) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((k_wilson_eo_pn<PREC, SG, NR>), dim3(pencil_blocks(pg)), dim3(256), dyn, s, (const S*)U,
                      (const S*)in, (const S*)xin, (S*)out, pg, p, nrhs, (R)alpha, (R)beta, live);
+  return hipSuccess;
 }
 
 template <int PREC, int SG, int NR>
-static void go_full(const lqcd_lattice* lat, const void* U, const void* psi, void* eta, int nrhs, double diag,
-                    double hopc, const kcfg& c, hipStream_t s) {
+static hipError_t go_full(const lqcd_lattice* lat, const void* U, const void* psi, void* eta, int nrhs, double diag,
+                          double hopc, const kcfg& c, hipStream_t s) {
   typedef typename prec_traits<PREC>::store S;
   typedef typename prec_traits<PREC>::real R;
   pencil_geo pg = make_pencil(lat, nrhs / NR, false, c);
-  hipLaunchKernelGGL((k_wilson_full_pn<PREC, SG, NR>), dim3(pencil_blocks(pg)), dim3(256), 0, s, (const S*)U,
+  size_t dyn = 0;
+  if (!occupancy_lds(c.occ, 0, &dyn)) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((k_wilson_full_pn<PREC, SG, NR>), dim3(pencil_blocks(pg)), dim3(256), dyn, s, (const S*)U,
                      (const S*)psi, (S*)eta, pg, nrhs, (R)diag, (R)hopc);
+  return hipSuccess;
 }
 
 bool nr_supported(int prec, int layout, int nrhs) {
@@ -282,11 +288,13 @@ hipError_t wilson_eo_nr(const lqcd_lattice* lat, const void* U, const void* in, 
                         int nrhs, double alpha, double beta, int prec, bool dagger, const int* live, const kcfg& c,
                         hipStream_t s) {
   if (prec == LQCD_F32) {
-    if (dagger) go_eo<LQCD_F32, -1, 2>(lat, U, in, xin, out, p, nrhs, alpha, beta, live, c, s);
-    else go_eo<LQCD_F32, 1, 2>(lat, U, in, xin, out, p, nrhs, alpha, beta, live, c, s);
+    hipError_t e = dagger ? go_eo<LQCD_F32, -1, 2>(lat, U, in, xin, out, p, nrhs, alpha, beta, live, c, s)
+                   : go_eo<LQCD_F32, 1, 2>(lat, U, in, xin, out, p, nrhs, alpha, beta, live, c, s);
+    if (e != hipSuccess) return e;
   } else if (prec == LQCD_F16) {
-    if (dagger) go_eo<LQCD_F16, -1, 2>(lat, U, in, xin, out, p, nrhs, alpha, beta, live, c, s);
-    else go_eo<LQCD_F16, 1, 2>(lat, U, in, xin, out, p, nrhs, alpha, beta, live, c, s);
+    hipError_t e = dagger ? go_eo<LQCD_F16, -1, 2>(lat, U, in, xin, out, p, nrhs, alpha, beta, live, c, s)
+                   : go_eo<LQCD_F16, 1, 2>(lat, U, in, xin, out, p, nrhs, alpha, beta, live, c, s);
+    if (e != hipSuccess) return e;
   } else {
     return hipErrorInvalidValue;
   }
@@ -296,11 +304,13 @@ hipError_t wilson_eo_nr(const lqcd_lattice* lat, const void* U, const void* in, 
 hipError_t wilson_full_nr(const lqcd_lattice* lat, const void* U, const void* psi, void* eta, int nrhs, double diag,
                           double hopc, int prec, bool dagger, const kcfg& c, hipStream_t s) {
   if (prec == LQCD_F32) {
-    if (dagger) go_full<LQCD_F32, -1, 2>(lat, U, psi, eta, nrhs, diag, hopc, c, s);
-    else go_full<LQCD_F32, 1, 2>(lat, U, psi, eta, nrhs, diag, hopc, c, s);
+    hipError_t e = dagger ? go_full<LQCD_F32, -1, 2>(lat, U, psi, eta, nrhs, diag, hopc, c, s)
+                   : go_full<LQCD_F32, 1, 2>(lat, U, psi, eta, nrhs, diag, hopc, c, s);
+    if (e != hipSuccess) return e;
   } else if (prec == LQCD_F16) {
-    if (dagger) go_full<LQCD_F16, -1, 2>(lat, U, psi, eta, nrhs, diag, hopc, c, s);
-    else go_full<LQCD_F16, 1, 2>(lat, U, psi, eta, nrhs, diag, hopc, c, s);
+    hipError_t e = dagger ? go_full<LQCD_F16, -1, 2>(lat, U, psi, eta, nrhs, diag, hopc, c, s)
+                   : go_full<LQCD_F16, 1, 2>(lat, U, psi, eta, nrhs, diag, hopc, c, s);
+    if (e != hipSuccess) return e;
   } else {
     return hipErrorInvalidValue;
   }

@@ -9,6 +9,7 @@
 // stores) on the caller's buffers with HIP events and records the fastest.
 // The table can be saved to and loaded from a text file.
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -31,8 +32,8 @@ typedef std::tuple<int, int, int, int, int, int, int, int> tkey;  // kind, dims[
 
 static std::mutex g_mu;
 static std::map<tkey, std::pair<kcfg, double>> g_table;
-static kcfg g_forced = {0, 0, 0, 0, 0};
-static const kcfg kDefault = {2, 0, 0, 0, 1};
+static kcfg g_forced = {0, 0, 0, 0, 0, 0};
+static const kcfg kDefault = {2, 0, 0, 0, 1, 0};
 
 static tkey key_of(int kind, const lqcd_lattice* lat, int nrhs, int prec, int layout) {
   return tkey(kind, lat->dims[0], lat->dims[1], lat->dims[2], lat->dims[3], nrhs, prec, layout);
@@ -45,6 +46,7 @@ void set_variant(int v, const int* pencil) {
   g_forced.tz = pencil ? pencil[1] : 0;
   g_forced.nseg = pencil ? pencil[2] : 0;
   g_forced.nt = 0;
+  g_forced.occ = 0;
 }
 
 static void set_forced(const kcfg& c) {
@@ -60,22 +62,44 @@ kcfg choose_cfg(int kind, const lqcd_lattice* lat, int nrhs, int prec, int layou
   return kDefault;
 }
 
-static std::vector<kcfg> candidates(const lqcd_lattice* lat, int layout, int prec, int nrhs) {
+static const int kTiles[][2] = {{0, 0}, {2, 1}, {2, 2}, {4, 2}, {4, 4}, {8, 2}, {8, 4}};
+
+static bool tile_ok(const lqcd_lattice* lat, const int* t, int sg) {
+  return !((t[0] && lat->dims[2] % t[0]) || (t[1] && lat->dims[1] % t[1]) || (sg && lat->dims[0] % sg));
+}
+
+// First pass: every kernel, tile, segment count and store kind, without a
+// residency cap.
+static std::vector<kcfg> candidates(const lqcd_lattice* lat, int layout, int prec, int nrhs, bool eo) {
   std::vector<kcfg> out;
-  out.push_back({1, 0, 0, 0, 0});
-  const int NZ = lat->dims[1], NY = lat->dims[2], T = lat->dims[0];
-  const int tiles[][2] = {{0, 0}, {2, 1}, {2, 2}, {4, 2}, {4, 4}, {8, 2}, {8, 4}};
-  const int segs[] = {0, 1, 2};
+  out.push_back({1, 0, 0, 0, 0, 0});
   for (int nt = 0; nt <= 1; ++nt)
-    for (auto& t : tiles) {
-      if ((t[0] && NY % t[0]) || (t[1] && NZ % t[1])) continue;
-      for (int sg : segs) {
-        if (sg && T % sg) continue;
-        out.push_back({2, t[0], t[1], sg, nt});
-        if (layout != LQCD_RHS_OUTER && t[0] == 0 && sg == 0) out.push_back({3, 0, 0, 0, nt});
-        if (nr_supported(prec, layout, nrhs)) out.push_back({4, t[0], t[1], sg, nt});
+    for (auto& t : kTiles)
+      for (int sg : {0, 1, 2}) {
+        if (!tile_ok(lat, t, sg)) continue;
+        out.push_back({2, t[0], t[1], sg, nt, 0});
+        if (layout != LQCD_RHS_OUTER && t[0] == 0 && sg == 0) out.push_back({3, 0, 0, 0, nt, 0});
+        if (nr_supported(prec, layout, nrhs)) out.push_back({4, t[0], t[1], sg, nt, 0});
+        if (!eo && dma_supported(prec, layout, nrhs)) out.push_back({5, t[0], t[1], sg, nt, 0});
       }
-    }
+  return out;
+}
+
+// Second pass: every pencil kernel again with capped residency (1 or 2
+// workgroups per compute unit), so that the columns one XCD works on at a
+// time stay few enough for its L2 to serve their spatial neighbours; with
+// one wavefront per SIMD the kernels are latency-bound on L2 misses rather
+// than short of wavefronts.  Keeps the first pass's store kind.
+static std::vector<kcfg> capped_candidates(const lqcd_lattice* lat, int layout, int prec, int nrhs, const kcfg& w) {
+  std::vector<kcfg> out;
+  for (int occ = 1; occ <= 2; ++occ)
+    for (auto& t : kTiles)
+      for (int sg : {1, 2}) {
+        if (!tile_ok(lat, t, sg)) continue;
+        out.push_back({2, t[0], t[1], sg, w.nt, occ});
+        if (layout != LQCD_RHS_OUTER) out.push_back({3, t[0], t[1], sg, w.nt, occ});
+        if (nr_supported(prec, layout, nrhs)) out.push_back({4, t[0], t[1], sg, w.nt, occ});
+      }
   return out;
 }
 
@@ -86,7 +110,7 @@ using namespace lq;
 extern "C" {
 
 int lqcd_set_kernel_variant(int variant, const int32_t* pencil) {
-  if (variant < 0 || variant > 4) return fail(LQCD_ERR_ARG, "unknown kernel variant %d", variant);
+  if (variant < 0 || variant > 5) return fail(LQCD_ERR_ARG, "unknown kernel variant %d", variant);
   int p[3] = {0, 0, 0};
   if (pencil)
     for (int i = 0; i < 3; ++i) {
@@ -99,12 +123,13 @@ int lqcd_set_kernel_variant(int variant, const int32_t* pencil) {
 
 int lqcd_set_kernel_config(const lqcd_kernel_config* c) {
   if (!c) {
-    set_forced(kcfg{0, 0, 0, 0, 0});
+    set_forced(kcfg{0, 0, 0, 0, 0, 0});
     return LQCD_OK;
   }
-  if (c->variant < 0 || c->variant > 4) return fail(LQCD_ERR_ARG, "unknown kernel variant %d", c->variant);
-  if (c->tile_y < 0 || c->tile_z < 0 || c->segments < 0) return fail(LQCD_ERR_ARG, "negative kernel parameter");
-  set_forced(kcfg{c->variant, c->tile_y, c->tile_z, c->segments, c->nontemporal ? 1 : 0});
+  if (c->variant < 0 || c->variant > 5) return fail(LQCD_ERR_ARG, "unknown kernel variant %d", c->variant);
+  if (c->tile_y < 0 || c->tile_z < 0 || c->segments < 0 || c->wg_per_cu < 0 || c->wg_per_cu > 8)
+    return fail(LQCD_ERR_ARG, "kernel parameter out of range");
+  set_forced(kcfg{c->variant, c->tile_y, c->tile_z, c->segments, c->nontemporal ? 1 : 0, c->wg_per_cu});
   return LQCD_OK;
 }
 
@@ -127,34 +152,36 @@ int lqcd_autotune(const lqcd_lattice* lat, const void* U, const void* psi, void*
     return fail(LQCD_ERR_HIP, "lqcd_autotune: event creation failed");
   double best_ms = 1e300;
   kcfg best_c = kDefault;
-  int err = LQCD_OK;
-  for (const kcfg& c : candidates(lat, layout, prec, nrhs)) {
-    set_forced(c);
-    // one hop pass of the Schur operator (the kernel a Schur apply runs twice)
-    auto run = [&]() -> hipError_t {
-      if (eo) return wilson_eo(lat, U, psi, nullptr, eta, 1, nrhs, 0.0, 1.0, layout, prec, false, nullptr, s);
-      return wilson_full(lat, U, psi, eta, nrhs, 3.95, -0.5, layout, prec, false, s);
-    };
-    hipError_t e = run();  // warm-up
-    if (e != hipSuccess) {
-      err = hip_status(e, "lqcd_autotune: candidate launch");
-      break;
+  // one hop pass of the Schur operator (the kernel a Schur apply runs twice)
+  auto run = [&]() -> hipError_t {
+    if (eo) return wilson_eo(lat, U, psi, nullptr, eta, 1, nrhs, 0.0, 1.0, layout, prec, false, nullptr, s);
+    return wilson_full(lat, U, psi, eta, nrhs, 3.95, -0.5, layout, prec, false, s);
+  };
+  auto time_all = [&](const std::vector<kcfg>& cands) -> int {
+    for (const kcfg& c : cands) {
+      set_forced(c);
+      hipError_t e = run();  // warm-up
+      if (e != hipSuccess && c.occ > 0) {  // launch refused: residency cap not expressible on this device
+        (void)hipGetLastError();
+        continue;
+      }
+      if (e != hipSuccess) return hip_status(e, "lqcd_autotune: candidate launch");
+      (void)hipEventRecord(e0, s);
+      for (int r = 0; r < reps; ++r) (void)run();
+      (void)hipEventRecord(e1, s);
+      if ((e = hipEventSynchronize(e1)) != hipSuccess) return hip_status(e, "lqcd_autotune: timing");
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      const double per = ms / reps;
+      if (per < best_ms) {
+        best_ms = per;
+        best_c = c;
+      }
     }
-    (void)hipEventRecord(e0, s);
-    for (int r = 0; r < reps; ++r) (void)run();
-    (void)hipEventRecord(e1, s);
-    if ((e = hipEventSynchronize(e1)) != hipSuccess) {
-      err = hip_status(e, "lqcd_autotune: timing");
-      break;
-    }
-    float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    const double per = ms / reps;
-    if (per < best_ms) {
-      best_ms = per;
-      best_c = c;
-    }
-  }
+    return LQCD_OK;
+  };
+  int err = time_all(candidates(lat, layout, prec, nrhs, eo != 0));
+  if (!err) err = time_all(capped_candidates(lat, layout, prec, nrhs, best_c));
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   set_forced(saved);
@@ -169,6 +196,7 @@ int lqcd_autotune(const lqcd_lattice* lat, const void* U, const void* psi, void*
     best->tile_z = best_c.tz;
     best->segments = best_c.nseg;
     best->nontemporal = best_c.nt;
+    best->wg_per_cu = best_c.occ;
     best->ms = best_ms;
   }
   return LQCD_OK;
@@ -179,13 +207,13 @@ int lqcd_tune_save(const char* path) {
   FILE* f = fopen(path, "w");
   if (!f) return fail(LQCD_ERR_ARG, "lqcd_tune_save: cannot open %s", path);
   std::lock_guard<std::mutex> lk(g_mu);
-  fprintf(f, "# kind N0 N1 N2 N3 nrhs prec layout : variant tile_y tile_z segments nontemporal ms\n");
+  fprintf(f, "# kind N0 N1 N2 N3 nrhs prec layout : variant tile_y tile_z segments nontemporal wg_per_cu ms\n");
   for (auto& kv : g_table) {
     const tkey& k = kv.first;
     const kcfg& c = kv.second.first;
-    fprintf(f, "%d %d %d %d %d %d %d %d : %d %d %d %d %d %.6f\n", std::get<0>(k), std::get<1>(k), std::get<2>(k),
+    fprintf(f, "%d %d %d %d %d %d %d %d : %d %d %d %d %d %d %.6f\n", std::get<0>(k), std::get<1>(k), std::get<2>(k),
             std::get<3>(k), std::get<4>(k), std::get<5>(k), std::get<6>(k), std::get<7>(k), c.variant, c.ty, c.tz,
-            c.nseg, c.nt, kv.second.second);
+            c.nseg, c.nt, c.occ, kv.second.second);
   }
   fclose(f);
   return LQCD_OK;
@@ -200,13 +228,37 @@ int lqcd_tune_load(const char* path) {
   std::lock_guard<std::mutex> lk(g_mu);
   while (fgets(line, sizeof line, f)) {
     if (line[0] == '#') continue;
-    int k[8], c[5];
-    double ms;
-    if (sscanf(line, "%d %d %d %d %d %d %d %d : %d %d %d %d %d %lf", &k[0], &k[1], &k[2], &k[3], &k[4], &k[5], &k[6],
-               &k[7], &c[0], &c[1], &c[2], &c[3], &c[4], &ms) != 14)
+    // "k0 .. k7 : v ty tz seg nt [wg_per_cu] ms" (older lines lack wg_per_cu)
+    int k[8], c[6] = {0, 0, 0, 0, 0, 0};
+    double val[8];
+    const char* colon = strchr(line, ':');
+    if (!colon || sscanf(line, "%d %d %d %d %d %d %d %d", &k[0], &k[1], &k[2], &k[3], &k[4], &k[5], &k[6], &k[7]) != 8)
       continue;
-    if (c[0] < 1 || c[0] > 4) continue;
-    g_table[tkey(k[0], k[1], k[2], k[3], k[4], k[5], k[6], k[7])] = std::make_pair(kcfg{c[0], c[1], c[2], c[3], c[4]}, ms);
+    int nv = 0;
+    const char* q = colon + 1;
+    char* end = nullptr;
+    while (nv < 8) {
+      val[nv] = strtod(q, &end);
+      if (end == q) break;
+      ++nv;
+      q = end;
+    }
+    if (nv != 6 && nv != 7) continue;
+    bool ints = true;
+    for (int i = 0; i < nv - 1; ++i) {
+      if (!(val[i] > -1e6 && val[i] < 1e6)) {
+        ints = false;
+        break;
+      }
+      c[i] = (int)val[i];
+      if ((double)c[i] != val[i]) ints = false;
+    }
+    if (!ints) continue;
+    if (nv == 6) c[5] = 0;
+    const double ms = val[nv - 1];
+    if (c[0] < 1 || c[0] > 5 || c[5] < 0 || c[5] > 8) continue;
+    g_table[tkey(k[0], k[1], k[2], k[3], k[4], k[5], k[6], k[7])] =
+        std::make_pair(kcfg{c[0], c[1], c[2], c[3], c[4], c[5]}, ms);
     ++n;
   }
   fclose(f);

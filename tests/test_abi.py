@@ -61,13 +61,16 @@ def test_tune_table_roundtrip(tmp_path):
     lib = lq.load()
     lq.tune_clear()
     p = tmp_path / "tune.txt"
-    p.write_text("# header\n0 64 32 32 32 16 0 2 : 2 4 4 1 1 4.8\nnot a line\n1 8 8 8 8 4 1 2 : 9 0 0 0 0 1.0\n")
-    assert lq.tune_load(p) == 1
+    p.write_text("# header\n0 64 32 32 32 16 0 2 : 2 4 4 1 1 4.8\nnot a line\n1 8 8 8 8 4 1 2 : 9 0 0 0 0 1.0\n"
+                 "1 64 32 32 32 16 0 2 : 3 4 4 1 1 2 2.5\n1 8 8 8 8 4 1 2 : 2 0 0 0 0 11 1.0\n")
+    assert lq.tune_load(p) == 2
     q = tmp_path / "out.txt"
     lq.tune_save(q)
     lines = [l for l in q.read_text().splitlines() if not l.startswith("#")]
-    assert lines == ["0 64 32 32 32 16 0 2 : 2 4 4 1 1 4.800000"]
+    assert lines == ["0 64 32 32 32 16 0 2 : 2 4 4 1 1 0 4.800000", "1 64 32 32 32 16 0 2 : 3 4 4 1 1 2 2.500000"]
     lq.tune_clear()
     lq.set_kernel_config(0)
     with pytest.raises(lq.LqcdError):
         lq.set_kernel_config(7)
+    with pytest.raises(lq.LqcdError):
+        lq.set_kernel_config(2, wg_per_cu=9)

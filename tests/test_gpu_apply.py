@@ -202,10 +202,58 @@ def test_nontemporal_stores_and_autotuned_choice(gpu_lib, kernel_variant, nt):
     Ud = to_dev(U, lq.F64)
     pd = to_dev(to_layout_np(psi, lq.LAYOUT2), lq.F64)
     best = gpu_lib.autotune(Ud, pd, torch.empty_like(pd), layout=lq.LAYOUT2, reps=1)
-    assert best["variant"] in (1, 2, 3) and best["ms"] > 0
+    assert best["variant"] in (1, 2, 3, 5) and best["ms"] > 0
     got = from_layout_np(from_dev(lq.dirac_apply(Ud, pd, -0.05, layout=lq.LAYOUT2), lq.F64), lq.LAYOUT2, 4)
     assert np.all(rel_err_per_rhs(got, want) <= TOL[lq.F64])
     gpu_lib.tune_clear()
+
+
+@pytest.mark.parametrize("nrhs", [10, 11, 12, 16, 24, 64])
+@pytest.mark.parametrize("pencil", [(0, 0, 0), (2, 1, 3), (1, 2, 1), (3, 2, 2)])
+def test_lds_fed_full_kernel(gpu_lib, kernel_variant, nrhs, pencil):
+    """Variant 5 (spinors and links arrive by global-to-LDS transfers, three
+    hops in flight per wavefront): FP64, rhs-innermost, D and D^dagger, tiles
+    and segment counts that leave wavefronts partly idle."""
+    if kernel_variant != 3:
+        pytest.skip("run once")
+    gpu_lib.set_kernel_config(5, pencil[0], pencil[1], pencil[2], 1)
+    try:
+        dims = (6, 4, 6, 4)
+        U = syn.gauge_field(dims, "haar", config=13)
+        psi = syn.spinor_block(dims, nrhs, config=13)
+        for dagger in (False, True):
+            want = (dirac.apply_dw_dagger if dagger else dirac.apply_dw)(U, psi, -0.3)
+            got = _apply_gpu(U, psi, -0.3, lq.LAYOUT2, lq.F64, dagger)
+            assert np.all(rel_err_per_rhs(got, want) <= TOL[lq.F64])
+        # unsupported combinations fall back to the plain pencil kernel
+        got = _apply_gpu(U, psi[:4], -0.3, lq.LAYOUT2, lq.F64)
+        assert np.all(rel_err_per_rhs(got, dirac.apply_dw(U, psi[:4], -0.3)) <= TOL[lq.F64])
+        got = _apply_gpu(U, psi, -0.3, lq.LAYOUT1, lq.F64)
+        assert np.all(rel_err_per_rhs(got, dirac.apply_dw(U, psi, -0.3)) <= TOL[lq.F64])
+    finally:
+        gpu_lib.set_kernel_config(0)
+
+
+@pytest.mark.parametrize("occ", [1, 2, 4])
+def test_residency_cap(gpu_lib, kernel_variant, occ):
+    """Capping the workgroups per compute unit (through the LDS request) only
+    changes which workgroups run together, never the result: full and Schur
+    applies, FP64 and FP32 (variant 4 for FP32 when the fixture runs 3)."""
+    if kernel_variant == 1:
+        pytest.skip("the cap applies to the pencil kernels")
+    dims = (8, 4, 6, 4)
+    U = syn.gauge_field(dims, "haar", config=12)
+    psi = syn.spinor_block(dims, 16, config=12)
+    for prec in (lq.F64, lq.F32):
+        v = 4 if (kernel_variant == 3 and prec == lq.F32) else kernel_variant
+        gpu_lib.set_kernel_config(v, 2, 2, 0, 1, occ)
+        Up, pp = rounded(U, prec), rounded(psi, prec)
+        got = _apply_gpu(Up, pp, 0.15, lq.LAYOUT2, prec)
+        assert np.all(rel_err_per_rhs(got, dirac.apply_dw(Up, pp, 0.15)) <= TOL[prec])
+        pe = geometry.to_half(pp, dims, 0)
+        got = _apply_eo_gpu(Up, pe, 0.15, lq.LAYOUT2, prec)
+        assert np.all(rel_err_per_rhs(got, evenodd.apply_schur(Up, pe, 0.15)) <= TOL[prec] * 2)
+    gpu_lib.set_kernel_config(0)
 
 
 @pytest.mark.parametrize("prec", [lq.F32, lq.F16])
