@@ -268,8 +268,6 @@ __global__ __launch_bounds__(256) void k_wilson_full_pl(const typename prec_trai
 // compact (z, y, j) columns, j = x >> 1.  Along t the output site of a
 // compact column alternates between x = 2j and 2j + 1; its +-t neighbours
 // (parity 1-p) lie in the same compact column at t +- 1 with the same x.
-// The neighbour at t+1 is the +t hop of t and the -t hop of t+2: its
-// projection is carried two steps in a small FIFO.
 template <int PREC, int LAYOUT, int SG>
 __global__ __launch_bounds__(256) void k_wilson_eo_p(const typename prec_traits<PREC>::store* __restrict__ U,
                                                      const typename prec_traits<PREC>::store* __restrict__ in,
@@ -304,15 +302,12 @@ __global__ __launch_bounds__(256) void k_wilson_eo_p(const typename prec_traits<
   const S* U3 = U + 3 * V * 9;
   const int par0 = (p + z + y) & 1;  // x parity offset at t = 0
 
-  // FIFO of projected (1 + SG gamma_0) in(t') for t' = t-1 (q0) and t (q1)
-  half_spinor<R> q0, q1;
-  {
-    const int tm = t0 > 0 ? t0 - 1 : T - 1;
-    spinor<R> pm = load_spinor<S, R>(in, blk<LAYOUT>::base((size_t)tm * H0 + hc, rhs, Vh, nrhs), cs);
-    q0 = project<0, SG>(pm);
-    spinor<R> pz = load_spinor<S, R>(in, blk<LAYOUT>::base((size_t)t0 * H0 + hc, rhs, Vh, nrhs), cs);
-    q1 = project<0, SG>(pz);
-  }
+  // One direction per phase: both neighbours and both links are loaded
+  // before either term is accumulated, so a wavefront has two hops' loads
+  // in flight.  The -t neighbour in(t-1) of the same compact column is
+  // loaded again (it was this work item's +t neighbour two steps earlier,
+  // an L2 hit) rather than carried: a carried projection costs the
+  // registers that the second hop's loads need.
   for (int it = 0; it < pg.Lt; ++it) {
     const int t = t0 + it;
     const int x = 2 * j + ((par0 + t) & 1);
@@ -322,38 +317,39 @@ __global__ __launch_bounds__(256) void k_wilson_eo_p(const typename prec_traits<
     spinor<R> acc;
 #pragma unroll
     for (int i = 0; i < 12; ++i) acc.c[i / 3][i % 3] = {R(0), R(0)};
-    // -t hop from the carried projection of in(t-1) through U_0(t-1, x)^dagger
     {
-      const int tm = t > 0 ? t - 1 : T - 1;
-      reconstruct<0, SG>(acc, colour_mul<true>(U0 + ((size_t)tm * S0 + lrow + x) * 9, q0));
+      const int tm = t > 0 ? t - 1 : T - 1, t1 = t + 1 < T ? t + 1 : 0;
+      spinor<R> pf = load_spinor<S, R>(in, blk<LAYOUT>::base((size_t)t1 * H0 + hc, rhs, Vh, nrhs), cs);
+      su3<R> uf = load_link<S, R>(U0 + site * 9);
+      spinor<R> pb = load_spinor<S, R>(in, blk<LAYOUT>::base((size_t)tm * H0 + hc, rhs, Vh, nrhs), cs);
+      su3<R> ub = load_link<S, R>(U0 + ((size_t)tm * S0 + lrow + x) * 9);
+      reconstruct<0, -SG>(acc, colour_mul_r<false>(uf, project<0, -SG>(pf)));
+      reconstruct<0, SG>(acc, colour_mul_r<true>(ub, project<0, SG>(pb)));
     }
-    // spatial hops
     {
       const int xf = x + 1 < NX ? x + 1 : 0, xb = x > 0 ? x - 1 : NX - 1;
       spinor<R> pf = load_spinor<S, R>(in, blk<LAYOUT>::base(toffh + row * NXh + (xf >> 1), rhs, Vh, nrhs), cs);
-      add_hop<3, -SG, false, S, R>(acc, pf, U3 + site * 9, R(1));
+      su3<R> uf = load_link<S, R>(U3 + site * 9);
       spinor<R> pb = load_spinor<S, R>(in, blk<LAYOUT>::base(toffh + row * NXh + (xb >> 1), rhs, Vh, nrhs), cs);
-      add_hop<3, SG, true, S, R>(acc, pb, U3 + ((size_t)t * S0 + lrow + xb) * 9, R(1));
+      su3<R> ub = load_link<S, R>(U3 + ((size_t)t * S0 + lrow + xb) * 9);
+      reconstruct<3, -SG>(acc, colour_mul_r<false>(uf, project<3, -SG>(pf)));
+      reconstruct<3, SG>(acc, colour_mul_r<true>(ub, project<3, SG>(pb)));
     }
     {
       spinor<R> pf = load_spinor<S, R>(in, blk<LAYOUT>::base(toffh + hyf, rhs, Vh, nrhs), cs);
-      add_hop<2, -SG, false, S, R>(acc, pf, U2 + site * 9, R(1));
+      su3<R> uf = load_link<S, R>(U2 + site * 9);
       spinor<R> pb = load_spinor<S, R>(in, blk<LAYOUT>::base(toffh + hyb, rhs, Vh, nrhs), cs);
-      add_hop<2, SG, true, S, R>(acc, pb, U2 + ((size_t)t * S0 + lyb + x) * 9, R(1));
+      su3<R> ub = load_link<S, R>(U2 + ((size_t)t * S0 + lyb + x) * 9);
+      reconstruct<2, -SG>(acc, colour_mul_r<false>(uf, project<2, -SG>(pf)));
+      reconstruct<2, SG>(acc, colour_mul_r<true>(ub, project<2, SG>(pb)));
     }
     {
       spinor<R> pf = load_spinor<S, R>(in, blk<LAYOUT>::base(toffh + hzf, rhs, Vh, nrhs), cs);
-      add_hop<1, -SG, false, S, R>(acc, pf, U1 + site * 9, R(1));
+      su3<R> uf = load_link<S, R>(U1 + site * 9);
       spinor<R> pb = load_spinor<S, R>(in, blk<LAYOUT>::base(toffh + hzb, rhs, Vh, nrhs), cs);
-      add_hop<1, SG, true, S, R>(acc, pb, U1 + ((size_t)t * S0 + lzb + x) * 9, R(1));
-    }
-    // +t hop: in(t+1) in the same compact column (same x)
-    {
-      const int t1 = t + 1 < T ? t + 1 : 0;
-      spinor<R> p1 = load_spinor<S, R>(in, blk<LAYOUT>::base((size_t)t1 * H0 + hc, rhs, Vh, nrhs), cs);
-      add_hop<0, -SG, false, S, R>(acc, p1, U0 + site * 9, R(1));
-      q0 = q1;
-      q1 = project<0, SG>(p1);
+      su3<R> ub = load_link<S, R>(U1 + ((size_t)t * S0 + lzb + x) * 9);
+      reconstruct<1, -SG>(acc, colour_mul_r<false>(uf, project<1, -SG>(pf)));
+      reconstruct<1, SG>(acc, colour_mul_r<true>(ub, project<1, SG>(pb)));
     }
     const size_t me = blk<LAYOUT>::base(hh, rhs, Vh, nrhs);
     if (xin) {
