@@ -179,7 +179,7 @@ def batch_section(lq, syn, steps):
     # ------------------------------------------------ FP32 apply, one launch vs eight
     probs32 = [(U.to(torch.complex64), b.to(torch.complex64), m0) for U, b, m0 in probs64]
     outs = [torch.empty_like(b) for _, b, _ in probs32]
-    grid = lq.autotune_batch(probs32, outs, reps=3)
+    batch_cfg = lq.autotune_batch(probs32, outs, reps=3)
     t_batch = timed(lambda: lq.dirac_apply_batch(probs32, outs=outs), steps, 2)
     for U, b, m0 in probs32:
         lq.autotune(U, b, torch.empty_like(b), m0, layout=lq.LAYOUT2, reps=2)
@@ -187,7 +187,7 @@ def batch_section(lq, syn, steps):
                   steps, 2)
     nbytes = sum(bytes_full(int(np.prod(c["dims"])), c["nrhs"], 8) for c in comp)
     out["apply_f32"] = {"one_launch_ms": round(t_batch, 4), "eight_launches_ms": round(t_seq, 4),
-                        "persistent_grid": grid, "gbs_one_launch": round(nbytes / t_batch / 1e6, 1),
+                        "persistent_config": batch_cfg, "gbs_one_launch": round(nbytes / t_batch / 1e6, 1),
                         "gbs_eight_launches": round(nbytes / t_seq / 1e6, 1)}
     log(f"batch apply FP32: one launch {t_batch:.3f} ms, eight launches {t_seq:.3f} ms")
     del probs32, outs

@@ -160,16 +160,32 @@ typedef struct {
  * persistent launch (the batched evaluation of Algorithm 1 over several
  * lattices of different size and rhs count).  1 <= nprob <= LQCD_MAX_BATCH;
  * all problems share the precision `prec`.  Same results as one dirac_apply
- * per problem (same per-site arithmetic). */
+ * per problem up to rounding (the same sums; the pencil kernel's order of
+ * the terms is that of the pencil variants of dirac_apply). */
 int dirac_apply_batch(int nprob, const lqcd_problem* probs, int prec, int flags, void* stream);
 
-/* Grid size of the persistent batch kernel (0 = four workgroups per CU). */
+/* Grid size of the batch launch: 0 = the kernel's default (one (site, rhs)
+ * per item: four persistent workgroups per CU; pencils: one workgroup per
+ * work unit, longest units first); > 0 = a persistent grid of that many
+ * workgroups (the pencil kernel rounds it down to a multiple of 8). */
 int lqcd_set_batch_grid(int blocks);
 
-/* Autotuner for the persistent batch kernel: times grid sizes of 1, 2, 4, 8
- * and 16 workgroups per CU on these problems (eta overwritten), keeps the
- * fastest (lqcd_set_batch_grid) and returns it in best_grid (may be NULL). */
-int lqcd_autotune_batch(int nprob, const lqcd_problem* probs, int prec, int reps, int* best_grid, void* stream);
+/* Kernel of the batch launch (process-wide): 0 automatic (2 for the full
+ * operator, 1 for the odd-even passes of gmres_solve_batch, the faster of
+ * the two for each on MI355X), 1 one (site, rhs) per work item, 2
+ * time-streaming pencils with each
+ * lattice's autotuned tile and segment count (two rhs per work item for
+ * FP32 / FP16 blocks with even nrhs).  Returns LQCD_ERR_ARG for other values. */
+int lqcd_set_batch_kernel(int kind);
+
+/* Autotuner for the batch launch: times both kernels with their default
+ * grid and persistent grids of 1, 2, 4, 8 and 16 workgroups per CU (eta
+ * overwritten), keeps the fastest grid (lqcd_set_batch_grid) and kernel
+ * (lqcd_set_batch_kernel: 1 if the one-site kernel wins, else the automatic
+ * choice) and returns the winner in best_kernel, best_grid (either may be
+ * NULL). */
+int lqcd_autotune_batch(int nprob, const lqcd_problem* probs, int prec, int reps, int* best_kernel, int* best_grid,
+                        void* stream);
 
 /* Measured HBM ceiling (a STREAM-style probe, the paper's empirical memory
  * ceiling of Sec. V-A, eq. (4)): kind 0 = copy b = a, 1 = triad

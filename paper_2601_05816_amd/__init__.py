@@ -99,7 +99,10 @@ def load():
     lib.lqcd_tune_load.restype = i32
     lib.lqcd_tune_clear.argtypes = []
     lib.lqcd_tune_clear.restype = None
-    lib.lqcd_autotune_batch.argtypes = [i32, ctypes.POINTER(Problem), i32, i32, ctypes.POINTER(ctypes.c_int), vp]
+    lib.lqcd_autotune_batch.argtypes = [i32, ctypes.POINTER(Problem), i32, i32, ctypes.POINTER(ctypes.c_int),
+                                        ctypes.POINTER(ctypes.c_int), vp]
+    lib.lqcd_set_batch_kernel.argtypes = [i32]
+    lib.lqcd_set_batch_kernel.restype = i32
     lib.lqcd_autotune_batch.restype = i32
     lib.lqcd_hbm_probe.argtypes = [i32, vp, vp, vp, ctypes.c_size_t, i32, ctypes.POINTER(ctypes.c_double), vp]
     lib.lqcd_hbm_probe.restype = i32
@@ -379,8 +382,15 @@ def autotune(U, psi, eta, m0=0.0, layout=LAYOUT2, eo=False, reps=3):
     return best.as_dict()
 
 
+def set_batch_kernel(kind=0):
+    """Kernel of the persistent batch launch: 0 automatic, 1 one (site, rhs) per
+    work item, 2 time-streaming pencils."""
+    _check(load().lqcd_set_batch_kernel(int(kind)))
+
+
 def autotune_batch(problems, outs, reps=3):
-    """Pick the persistent grid size for dirac_apply_batch on these problems."""
+    """Pick the kernel and persistent grid size for dirac_apply_batch on these
+    problems; returns {"kernel": k, "grid": g}."""
     prec = _prec_of(problems[0][1])
     arr = (Problem * len(problems))()
     for k, ((U, psi, m0), eta) in enumerate(zip(problems, outs)):
@@ -389,9 +399,10 @@ def autotune_batch(problems, outs, reps=3):
         arr[k].lat = _lattice(dims)
         arr[k].U, arr[k].psi, arr[k].eta = U.data_ptr(), psi.data_ptr(), eta.data_ptr()
         arr[k].nrhs, arr[k].m0 = nrhs, float(m0)
-    g = ctypes.c_int(0)
-    _check(load().lqcd_autotune_batch(len(problems), arr, prec, int(reps), ctypes.byref(g), _stream()))
-    return g.value
+    kind, g = ctypes.c_int(0), ctypes.c_int(0)
+    _check(load().lqcd_autotune_batch(len(problems), arr, prec, int(reps), ctypes.byref(kind), ctypes.byref(g),
+                                      _stream()))
+    return {"kernel": kind.value, "grid": g.value}
 
 
 def hbm_probe(a, b, c=None, kind="triad", reps=5):

@@ -2,6 +2,7 @@
 #pragma once
 
 #include "common.h"
+#include "pencil.h"
 #include "site.h"
 
 namespace lq {
@@ -20,6 +21,8 @@ struct batch_prob {
   int parity;
   double alpha, beta;
   unsigned long long unit0;  // first work unit (filled by wilson_batch)
+  pencil_geo pg;             // pencil decomposition (pencil batch kernel; filled by wilson_batch)
+  int nr;                    // rhs per work item of the pencil body (1 or 2)
 };
 
 struct batch_desc {
@@ -31,5 +34,10 @@ struct batch_desc {
 geo4 make_geo4(const lqcd_lattice* lat);
 hipError_t wilson_batch(batch_desc& d, int prec, bool dagger, hipStream_t s);
 void set_batch_grid(int blocks);
+// Kernel of the batch launch: 0 automatic (pencils for full-lattice
+// applies, one (site, rhs) per work item for odd-even passes), 1 one
+// (site, rhs) per work item, 2 time-streaming pencils.
+void set_batch_kernel(int kind);
+int batch_kernel();
 
 }  // namespace lq

@@ -1,14 +1,25 @@
 // Uneven batches: several independent lattices, each with its own gauge
 // field, rhs count and mass, in ONE persistent launch.
 //
-// The work of every problem is cut into units of 256 (site, rhs) items; the
-// units of all problems form one list (problem k owns units
-// [unit0_k, unit0_k + units_k)).  A fixed grid of workgroups sized to the
-// chip's residency walks the list with a stride of the grid size, so a batch
-// of lattices from 8^3 x 16 to 24^3 x 48 with 1..32 rhs each keeps every CU
-// busy without one launch per lattice.  The per-item arithmetic is the
-// one-site body of dslash.hip (rhs-innermost layout).
+// The work of every problem is cut into units of 256 work items; the units
+// of all problems form one list (problem k owns units [unit0_k, unit0_k +
+// units_k)).  A fixed grid of workgroups sized to the chip's residency walks
+// the list with a stride of the grid size, so a batch of lattices from
+// 8^3 x 16 to 24^3 x 48 with 1..32 rhs each keeps every CU busy without one
+// launch per lattice.  Two kernels: a unit is either 256 (site, rhs) items
+// with the one-site body of dslash.hip, or one workgroup of the problem's
+// time-streaming pencil grid (pencil_kernels.h) with the tile, segment
+// count and store kind the autotuner recorded for that lattice, two rhs per
+// work item for FP32 / FP16 blocks with an even rhs count.  Pencil units
+// differ in length between lattices, so by default the pencil launch has one
+// workgroup per unit (the dispatcher balances them) with the longest units
+// first; a set grid size makes it persistent.  Pencil units of a problem
+// start at a multiple of 8 and a persistent grid is a multiple of 8, so a
+// unit keeps the XCD its pencil grid position assumes.
+#include <algorithm>
+
 #include "batch.h"
+#include "pencil_kernels.h"
 #include "wilson.h"
 
 namespace lq {
@@ -40,9 +51,41 @@ __global__ __launch_bounds__(256) void k_wilson_batch(batch_desc d) {
   }
 }
 
+template <int PREC, int SG>
+__global__ __launch_bounds__(256) void k_wilson_batch_p(batch_desc d) {
+  typedef typename prec_traits<PREC>::store S;
+  typedef typename prec_traits<PREC>::real R;
+  for (unsigned long long u = blockIdx.x; u < d.total_units; u += gridDim.x) {
+    int k = 0;
+    while (k + 1 < d.n && u >= d.p[k + 1].unit0) ++k;
+    const batch_prob& pb = d.p[k];
+    const unsigned b = (unsigned)(u - pb.unit0);
+    const S* U = (const S*)pb.U;
+    const S* in = (const S*)pb.in;
+    S* out = (S*)pb.out;
+    if (pb.parity < 0) {
+      if (PREC != LQCD_F64 && pb.nr == 2)
+        wilson_full_pn_body<PREC, SG, (PREC == LQCD_F64 ? 1 : 2)>(U, in, out, pb.pg, pb.nrhs, (R)pb.alpha,
+                                                                   (R)pb.beta, b);
+      else
+        wilson_full_p_body<PREC, LQCD_LAYOUT2, SG>(U, in, out, pb.pg, pb.nrhs, (R)pb.alpha, (R)pb.beta, b);
+    } else {
+      if (PREC != LQCD_F64 && pb.nr == 2)
+        wilson_eo_pn_body<PREC, SG, (PREC == LQCD_F64 ? 1 : 2)>(U, in, (const S*)pb.xin, out, pb.pg, pb.parity,
+                                                                 pb.nrhs, (R)pb.alpha, (R)pb.beta, pb.live, b);
+      else
+        wilson_eo_p_body<PREC, LQCD_LAYOUT2, SG>(U, in, (const S*)pb.xin, out, pb.pg, pb.parity, pb.nrhs,
+                                                 (R)pb.alpha, (R)pb.beta, pb.live, b);
+    }
+  }
+}
+
 static int g_batch_grid = 0;  // persistent grid size (0 = residency of the chip)
+static int g_batch_kind = 0;
 
 void set_batch_grid(int blocks) { g_batch_grid = blocks > 0 ? blocks : 0; }
+void set_batch_kernel(int kind) { g_batch_kind = kind; }
+int batch_kernel() { return g_batch_kind; }
 
 unsigned batch_grid_default() {
   static unsigned cached = 0;
@@ -55,27 +98,64 @@ unsigned batch_grid_default() {
   return cached;
 }
 
-hipError_t wilson_batch(batch_desc& d, int prec, bool dagger, hipStream_t s) {
+hipError_t wilson_batch(batch_desc& din, int prec, bool dagger, hipStream_t s) {
+  // automatic choice (measured on MI355X with the eight-lattice batch): the
+  // pencil kernel for full-lattice applies, the one-site kernel for the
+  // odd-even passes of the lock-step solver
+  const bool pencil = g_batch_kind == 2 || (g_batch_kind == 0 && din.n > 0 && din.p[0].parity < 0);
+  batch_desc d = din;  // the launch's copy: problems may be reordered below
   unsigned long long units = 0;
+  if (pencil) {
+    for (int k = 0; k < d.n; ++k) {
+      batch_prob& pb = d.p[k];
+      lqcd_lattice lat;
+      for (int i = 0; i < 4; ++i) lat.dims[i] = pb.g.n[i];
+      // tile, segments and store kind of the autotuner's entry for this lattice
+      const bool eo = pb.parity >= 0;
+      const kcfg c = choose_cfg(eo ? KIND_EO : KIND_FULL, &lat, pb.nrhs, prec, LQCD_LAYOUT2);
+      pb.nr = (prec != LQCD_F64 && pb.nrhs % 2 == 0) ? 2 : 1;
+      pb.pg = make_pencil(&lat, pb.nrhs / pb.nr, eo, c);
+    }
+    // longest units (most time steps per workgroup) first, so that the
+    // dispatcher does not end the launch on a few long workgroups
+    std::stable_sort(d.p, d.p + d.n, [](const batch_prob& a, const batch_prob& b) { return a.pg.Lt > b.pg.Lt; });
+  }
   for (int k = 0; k < d.n; ++k) {
-    const size_t nsite = d.p[k].parity < 0 ? d.p[k].g.V : d.p[k].g.V / 2;
-    d.p[k].unit0 = units;
-    units += (nsite * (size_t)d.p[k].nrhs + 255) / 256;
+    batch_prob& pb = d.p[k];
+    pb.unit0 = units;
+    if (pencil) {
+      units += pencil_blocks(pb.pg);  // a multiple of 8
+    } else {
+      const size_t nsite = pb.parity >= 0 ? pb.g.V / 2 : pb.g.V;
+      units += (nsite * (size_t)pb.nrhs + 255) / 256;
+    }
   }
   d.total_units = units;
   if (units == 0) return hipSuccess;
-  unsigned grid = g_batch_grid ? (unsigned)g_batch_grid : batch_grid_default();
+  // pencils: one workgroup per unit unless a persistent grid is set (a
+  // multiple of 8, so that every unit keeps the XCD its position assumes);
+  // one (site, rhs) per item: persistent, four workgroups per CU by default
+  unsigned grid;
+  if (pencil) grid = g_batch_grid ? (g_batch_grid < 8 ? 8u : (unsigned)g_batch_grid & ~7u) : (unsigned)units;
+  else grid = g_batch_grid ? (unsigned)g_batch_grid : batch_grid_default();
   if (grid > units) grid = (unsigned)units;
-#define BL(P, SGN) hipLaunchKernelGGL((k_wilson_batch<P, SGN>), dim3(grid), dim3(256), 0, s, d)
-  switch (prec * 2 + (dagger ? 1 : 0)) {
-    case LQCD_F64 * 2: BL(LQCD_F64, 1); break;
-    case LQCD_F64 * 2 + 1: BL(LQCD_F64, -1); break;
-    case LQCD_F32 * 2: BL(LQCD_F32, 1); break;
-    case LQCD_F32 * 2 + 1: BL(LQCD_F32, -1); break;
-    case LQCD_F16 * 2: BL(LQCD_F16, 1); break;
-    case LQCD_F16 * 2 + 1: BL(LQCD_F16, -1); break;
-    default: return hipErrorInvalidValue;
+#define BL(K, P, SGN) hipLaunchKernelGGL((K<P, SGN>), dim3(grid), dim3(256), 0, s, d)
+#define BL_ALL(K)                                         \
+  switch (prec * 2 + (dagger ? 1 : 0)) {                  \
+    case LQCD_F64 * 2: BL(K, LQCD_F64, 1); break;         \
+    case LQCD_F64 * 2 + 1: BL(K, LQCD_F64, -1); break;    \
+    case LQCD_F32 * 2: BL(K, LQCD_F32, 1); break;         \
+    case LQCD_F32 * 2 + 1: BL(K, LQCD_F32, -1); break;    \
+    case LQCD_F16 * 2: BL(K, LQCD_F16, 1); break;         \
+    case LQCD_F16 * 2 + 1: BL(K, LQCD_F16, -1); break;    \
+    default: return hipErrorInvalidValue;                 \
   }
+  if (pencil) {
+    BL_ALL(k_wilson_batch_p)
+  } else {
+    BL_ALL(k_wilson_batch)
+  }
+#undef BL_ALL
 #undef BL
   return hipGetLastError();
 }
@@ -127,6 +207,12 @@ int dirac_apply_batch(int nprob, const lqcd_problem* probs, int prec, int flags,
 int lqcd_set_batch_grid(int blocks) {
   if (blocks < 0) return fail(LQCD_ERR_ARG, "negative grid size");
   set_batch_grid(blocks);
+  return LQCD_OK;
+}
+
+int lqcd_set_batch_kernel(int kind) {
+  if (kind < 0 || kind > 2) return fail(LQCD_ERR_ARG, "unknown batch kernel %d", kind);
+  set_batch_kernel(kind);
   return LQCD_OK;
 }
 

@@ -17,11 +17,11 @@ struct pencil_geo {
   int nt;            // non-temporal output stores
 };
 
-// (column coordinates, rhs, t0) of this work item, or false if idle.
+// (column coordinates, rhs, t0) of work item threadIdx.x of block b of the
+// pencil grid, or false if idle.
 template <int LAYOUT>
 __device__ __forceinline__ bool pencil_item(const pencil_geo& pg, int nrhs, int& x, int& y, int& z, int& rhs,
-                                            int& t0) {
-  const unsigned b = blockIdx.x;
+                                            int& t0, unsigned b) {
   const unsigned k = b & 7u, i = b >> 3;
   const unsigned u = i / pg.bpt, q = i % pg.bpt;
   const unsigned grp = u / pg.nseg, seg = u % pg.nseg;

@@ -17,11 +17,11 @@
 // mapping is a bijection for any tile shape; the tile shape and the number
 // of t segments only change locality.
 #include "kernels.h"
-#include "pencil.h"
+#include "pencil_kernels.h"
 
 namespace lq {
 
-// ---------------------------------------------------------- full lattice
+// k_wilson_full_p: one launch over the pencil grid of one lattice (body in pencil_kernels.h).
 template <int PREC, int LAYOUT, int SG>
 __global__ __launch_bounds__(256) void k_wilson_full_p(const typename prec_traits<PREC>::store* __restrict__ U,
                                                        const typename prec_traits<PREC>::store* __restrict__ psi,
@@ -29,88 +29,7 @@ __global__ __launch_bounds__(256) void k_wilson_full_p(const typename prec_trait
                                                        pencil_geo pg, int nrhs,
                                                        typename prec_traits<PREC>::real diag,
                                                        typename prec_traits<PREC>::real hopc) {
-  typedef typename prec_traits<PREC>::store S;
-  typedef typename prec_traits<PREC>::real R;
-  int x, y, z, rhs, t0;
-  if (!pencil_item<LAYOUT>(pg, nrhs, x, y, z, rhs, t0)) return;
-  const int T = pg.n[0], NZ = pg.n[1], NY = pg.n[2], NX = pg.n[3];
-  const size_t V = pg.V, S0 = (size_t)NZ * NY * NX;
-  const int cs = blk<LAYOUT>::cstride(nrhs);
-  // column bases (site number at t = 0) of this column and its spatial neighbours
-  const size_t c0 = ((size_t)z * NY + y) * NX + x;
-  const size_t cxf = c0 - x + (x + 1 < NX ? x + 1 : 0), cxb = c0 - x + (x > 0 ? x - 1 : NX - 1);
-  const size_t cyf = c0 + (size_t)((y + 1 < NY ? y + 1 : 0) - y) * NX;
-  const size_t cyb = c0 + (size_t)((y > 0 ? y - 1 : NY - 1) - y) * NX;
-  const size_t czf = c0 + (size_t)((z + 1 < NZ ? z + 1 : 0) - z) * NY * NX;
-  const size_t czb = c0 + (size_t)((z > 0 ? z - 1 : NZ - 1) - z) * NY * NX;
-  const S* U0 = U;
-  const S* U1 = U + 1 * V * 9;
-  const S* U2 = U + 2 * V * 9;
-  const S* U3 = U + 3 * V * 9;
-
-  // prologue: the -t hop of site t0 and the projected centre of t0
-  spinor<R> acc;
-  half_spinor<R> hplus;
-  {
-    const int tm = t0 > 0 ? t0 - 1 : T - 1;
-    const size_t sm = (size_t)tm * S0 + c0;
-    spinor<R> pm = load_spinor<S, R>(psi, blk<LAYOUT>::base(sm, rhs, V, nrhs), cs);
-#pragma unroll
-    for (int i = 0; i < 12; ++i) acc.c[i / 3][i % 3] = {R(0), R(0)};
-    add_hop<0, SG, true, S, R>(acc, pm, U0 + sm * 9, hopc);
-    const size_t s0 = (size_t)t0 * S0 + c0;
-    spinor<R> p0 = load_spinor<S, R>(psi, blk<LAYOUT>::base(s0, rhs, V, nrhs), cs);
-#pragma unroll
-    for (int i = 0; i < 12; ++i) {
-      cx<R> a = acc.c[i / 3][i % 3], b = p0.c[i / 3][i % 3];
-      acc.c[i / 3][i % 3] = {fma(diag, b.re, a.re), fma(diag, b.im, a.im)};
-    }
-    hplus = project<0, SG>(p0);
-  }
-  for (int it = 0; it < pg.Lt; ++it) {
-    const int t = t0 + it;
-    const size_t toff = (size_t)t * S0;
-    const size_t site = toff + c0;
-    // spatial hops (directions 3 = x, 2 = y, 1 = z)
-    {
-      spinor<R> p = load_spinor<S, R>(psi, blk<LAYOUT>::base(toff + cxf, rhs, V, nrhs), cs);
-      add_hop<3, -SG, false, S, R>(acc, p, U3 + site * 9, hopc);
-    }
-    {
-      spinor<R> p = load_spinor<S, R>(psi, blk<LAYOUT>::base(toff + cxb, rhs, V, nrhs), cs);
-      add_hop<3, SG, true, S, R>(acc, p, U3 + (toff + cxb) * 9, hopc);
-    }
-    {
-      spinor<R> p = load_spinor<S, R>(psi, blk<LAYOUT>::base(toff + cyf, rhs, V, nrhs), cs);
-      add_hop<2, -SG, false, S, R>(acc, p, U2 + site * 9, hopc);
-    }
-    {
-      spinor<R> p = load_spinor<S, R>(psi, blk<LAYOUT>::base(toff + cyb, rhs, V, nrhs), cs);
-      add_hop<2, SG, true, S, R>(acc, p, U2 + (toff + cyb) * 9, hopc);
-    }
-    {
-      spinor<R> p = load_spinor<S, R>(psi, blk<LAYOUT>::base(toff + czf, rhs, V, nrhs), cs);
-      add_hop<1, -SG, false, S, R>(acc, p, U1 + site * 9, hopc);
-    }
-    {
-      spinor<R> p = load_spinor<S, R>(psi, blk<LAYOUT>::base(toff + czb, rhs, V, nrhs), cs);
-      add_hop<1, SG, true, S, R>(acc, p, U1 + (toff + czb) * 9, hopc);
-    }
-    // time direction: psi(t+1) gives the +t hop of t, and the centre and the
-    // -t hop (through U_0(t)^dagger and the carried projection of psi(t)) of t+1
-    const int t1 = t + 1 < T ? t + 1 : 0;
-    const size_t s1 = (size_t)t1 * S0 + c0;
-    spinor<R> p1 = load_spinor<S, R>(psi, blk<LAYOUT>::base(s1, rhs, V, nrhs), cs);
-    add_hop<0, -SG, false, S, R>(acc, p1, U0 + site * 9, hopc);
-    if (pg.nt) store_spinor_nt<S, R>(eta, blk<LAYOUT>::base(site, rhs, V, nrhs), cs, acc);
-    else store_spinor<S, R>(eta, blk<LAYOUT>::base(site, rhs, V, nrhs), cs, acc);
-    if (it + 1 < pg.Lt) {
-#pragma unroll
-      for (int i = 0; i < 12; ++i) acc.c[i / 3][i % 3] = scale(diag, p1.c[i / 3][i % 3]);
-      reconstruct<0, SG>(acc, hscale(hopc, colour_mul<true>(U0 + site * 9, hplus)));
-      hplus = project<0, SG>(p1);
-    }
-  }
+  wilson_full_p_body<PREC, LAYOUT, SG>(U, psi, eta, pg, nrhs, diag, hopc, blockIdx.x);
 }
 
 // ------------------------------------------- full lattice, links via LDS
@@ -263,11 +182,7 @@ __global__ __launch_bounds__(256) void k_wilson_full_pl(const typename prec_trai
   }
 }
 
-// --------------------------------------------------------- odd-even hop
-// out(h) = alpha xin(h) + beta hop(in)(h) on parity p; columns are the
-// compact (z, y, j) columns, j = x >> 1.  Along t the output site of a
-// compact column alternates between x = 2j and 2j + 1; its +-t neighbours
-// (parity 1-p) lie in the same compact column at t +- 1 with the same x.
+// k_wilson_eo_p: one launch over the pencil grid of one lattice (body in pencil_kernels.h).
 template <int PREC, int LAYOUT, int SG>
 __global__ __launch_bounds__(256) void k_wilson_eo_p(const typename prec_traits<PREC>::store* __restrict__ U,
                                                      const typename prec_traits<PREC>::store* __restrict__ in,
@@ -277,95 +192,7 @@ __global__ __launch_bounds__(256) void k_wilson_eo_p(const typename prec_traits<
                                                      typename prec_traits<PREC>::real alpha,
                                                      typename prec_traits<PREC>::real beta,
                                                      const int* __restrict__ live) {
-  typedef typename prec_traits<PREC>::store S;
-  typedef typename prec_traits<PREC>::real R;
-  int j, y, z, rhs, t0;
-  if (!pencil_item<LAYOUT>(pg, nrhs, j, y, z, rhs, t0)) return;
-  if (live && !live[rhs]) return;
-  const int T = pg.n[0], NZ = pg.n[1], NY = pg.n[2], NX = pg.n[3];
-  const int NXh = NX >> 1;
-  const size_t V = pg.V, Vh = V / 2;
-  const size_t S0 = (size_t)NZ * NY * NX, H0 = S0 / 2;  // site / compact strides of one time slice
-  const int cs = blk<LAYOUT>::cstride(nrhs);
-  const size_t row = (size_t)z * NY + y;                   // (z, y) row
-  const size_t hc = row * NXh + j;                         // compact column base at t = 0
-  const size_t hyf = ((size_t)z * NY + (y + 1 < NY ? y + 1 : 0)) * NXh + j;
-  const size_t hyb = ((size_t)z * NY + (y > 0 ? y - 1 : NY - 1)) * NXh + j;
-  const size_t hzf = ((size_t)(z + 1 < NZ ? z + 1 : 0) * NY + y) * NXh + j;
-  const size_t hzb = ((size_t)(z > 0 ? z - 1 : NZ - 1) * NY + y) * NXh + j;
-  const size_t lyb = ((size_t)z * NY + (y > 0 ? y - 1 : NY - 1)) * NX;  // site bases (x added later)
-  const size_t lzb = ((size_t)(z > 0 ? z - 1 : NZ - 1) * NY + y) * NX;
-  const size_t lrow = row * NX;
-  const S* U0 = U;
-  const S* U1 = U + 1 * V * 9;
-  const S* U2 = U + 2 * V * 9;
-  const S* U3 = U + 3 * V * 9;
-  const int par0 = (p + z + y) & 1;  // x parity offset at t = 0
-
-  // One direction per phase: both neighbours and both links are loaded
-  // before either term is accumulated, so a wavefront has two hops' loads
-  // in flight.  The -t neighbour in(t-1) of the same compact column is
-  // loaded again (it was this work item's +t neighbour two steps earlier,
-  // an L2 hit) rather than carried: a carried projection costs the
-  // registers that the second hop's loads need.
-  for (int it = 0; it < pg.Lt; ++it) {
-    const int t = t0 + it;
-    const int x = 2 * j + ((par0 + t) & 1);
-    const size_t site = (size_t)t * S0 + lrow + x;
-    const size_t hh = (size_t)t * H0 + hc;
-    const size_t toffh = (size_t)t * H0;
-    spinor<R> acc;
-#pragma unroll
-    for (int i = 0; i < 12; ++i) acc.c[i / 3][i % 3] = {R(0), R(0)};
-    {
-      const int tm = t > 0 ? t - 1 : T - 1, t1 = t + 1 < T ? t + 1 : 0;
-      spinor<R> pf = load_spinor<S, R>(in, blk<LAYOUT>::base((size_t)t1 * H0 + hc, rhs, Vh, nrhs), cs);
-      su3<R> uf = load_link<S, R>(U0 + site * 9);
-      spinor<R> pb = load_spinor<S, R>(in, blk<LAYOUT>::base((size_t)tm * H0 + hc, rhs, Vh, nrhs), cs);
-      su3<R> ub = load_link<S, R>(U0 + ((size_t)tm * S0 + lrow + x) * 9);
-      reconstruct<0, -SG>(acc, colour_mul_r<false>(uf, project<0, -SG>(pf)));
-      reconstruct<0, SG>(acc, colour_mul_r<true>(ub, project<0, SG>(pb)));
-    }
-    {
-      const int xf = x + 1 < NX ? x + 1 : 0, xb = x > 0 ? x - 1 : NX - 1;
-      spinor<R> pf = load_spinor<S, R>(in, blk<LAYOUT>::base(toffh + row * NXh + (xf >> 1), rhs, Vh, nrhs), cs);
-      su3<R> uf = load_link<S, R>(U3 + site * 9);
-      spinor<R> pb = load_spinor<S, R>(in, blk<LAYOUT>::base(toffh + row * NXh + (xb >> 1), rhs, Vh, nrhs), cs);
-      su3<R> ub = load_link<S, R>(U3 + ((size_t)t * S0 + lrow + xb) * 9);
-      reconstruct<3, -SG>(acc, colour_mul_r<false>(uf, project<3, -SG>(pf)));
-      reconstruct<3, SG>(acc, colour_mul_r<true>(ub, project<3, SG>(pb)));
-    }
-    {
-      spinor<R> pf = load_spinor<S, R>(in, blk<LAYOUT>::base(toffh + hyf, rhs, Vh, nrhs), cs);
-      su3<R> uf = load_link<S, R>(U2 + site * 9);
-      spinor<R> pb = load_spinor<S, R>(in, blk<LAYOUT>::base(toffh + hyb, rhs, Vh, nrhs), cs);
-      su3<R> ub = load_link<S, R>(U2 + ((size_t)t * S0 + lyb + x) * 9);
-      reconstruct<2, -SG>(acc, colour_mul_r<false>(uf, project<2, -SG>(pf)));
-      reconstruct<2, SG>(acc, colour_mul_r<true>(ub, project<2, SG>(pb)));
-    }
-    {
-      spinor<R> pf = load_spinor<S, R>(in, blk<LAYOUT>::base(toffh + hzf, rhs, Vh, nrhs), cs);
-      su3<R> uf = load_link<S, R>(U1 + site * 9);
-      spinor<R> pb = load_spinor<S, R>(in, blk<LAYOUT>::base(toffh + hzb, rhs, Vh, nrhs), cs);
-      su3<R> ub = load_link<S, R>(U1 + ((size_t)t * S0 + lzb + x) * 9);
-      reconstruct<1, -SG>(acc, colour_mul_r<false>(uf, project<1, -SG>(pf)));
-      reconstruct<1, SG>(acc, colour_mul_r<true>(ub, project<1, SG>(pb)));
-    }
-    const size_t me = blk<LAYOUT>::base(hh, rhs, Vh, nrhs);
-    if (xin) {
-      spinor<R> xv = load_spinor<S, R>(xin, me, cs);
-#pragma unroll
-      for (int i = 0; i < 12; ++i) {
-        cx<R> a = acc.c[i / 3][i % 3], b = xv.c[i / 3][i % 3];
-        acc.c[i / 3][i % 3] = {fma(beta, a.re, alpha * b.re), fma(beta, a.im, alpha * b.im)};
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < 12; ++i) acc.c[i / 3][i % 3] = scale(beta, acc.c[i / 3][i % 3]);
-    }
-    if (pg.nt) store_spinor_nt<S, R>(out, me, cs, acc);
-    else store_spinor<S, R>(out, me, cs, acc);
-  }
+  wilson_eo_p_body<PREC, LAYOUT, SG>(U, in, xin, out, pg, p, nrhs, alpha, beta, live, blockIdx.x);
 }
 
 // ------------------------------------------------------------ configuration

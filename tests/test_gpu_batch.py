@@ -19,9 +19,13 @@ def _l2(block):
 
 @pytest.mark.parametrize("prec", [lq.F64, lq.F32, lq.F16])
 @pytest.mark.parametrize("grid", [0, 1, 7])
-def test_uneven_batch_small(gpu_lib, prec, grid):
-    """Small lattices of different shapes and rhs counts; the persistent grid
-    size (including a single workgroup) does not change the result."""
+@pytest.mark.parametrize("kind", [1, 2])
+def test_uneven_batch_small(gpu_lib, prec, grid, kind):
+    """Small lattices of different shapes and rhs counts (odd and even, so the
+    pencil kernel mixes one and two rhs per work item); neither the kernel nor
+    the persistent grid size (including a single workgroup, or the eight the
+    pencil kernel rounds up to) changes the result."""
+    gpu_lib.set_batch_kernel(kind)
     gpu_lib.set_batch_grid(grid)
     cases = [((4, 4, 4, 4), 1, 0.1), ((8, 4, 4, 4), 5, -0.05), ((4, 6, 2, 8), 3, 0.3), ((2, 2, 2, 2), 2, 0.0),
              ((6, 4, 4, 2), 7, -0.2)]
@@ -33,6 +37,7 @@ def test_uneven_batch_small(gpu_lib, prec, grid):
         wants.append(dirac.apply_dw(U, psi, m0))
     outs = lq.dirac_apply_batch(probs)
     gpu_lib.set_batch_grid(0)
+    gpu_lib.set_batch_kernel(0)
     from helpers import from_dev
     for out, want in zip(outs, wants):
         got = np.moveaxis(from_dev(out, prec), -1, 0)
@@ -55,14 +60,23 @@ def test_batch_composition_matches_single_applies(gpu_lib):
     gpu_lib.set_kernel_variant(1)
     singles = [lq.dirac_apply(U, psi, m0) for U, psi, m0 in probs]
     gpu_lib.set_kernel_variant(0)
+    gpu_lib.set_batch_kernel(1)
     outs = lq.dirac_apply_batch(probs)
     for a, b in zip(outs, singles):
         assert torch.equal(a, b)
+    # the pencil kernel sums the same terms in the pencil order
+    gpu_lib.set_batch_kernel(2)
+    outs = lq.dirac_apply_batch(probs)
+    gpu_lib.set_batch_kernel(0)
+    for a, b in zip(outs, singles):
+        d = torch.linalg.vector_norm((a - b).reshape(-1, a.shape[-1]), dim=0)
+        assert torch.all(d <= 1e-6 * torch.linalg.vector_norm(b.reshape(-1, b.shape[-1]), dim=0))
 
 
 @pytest.mark.parametrize("mode", ["f64", "ir-f32"])
 @pytest.mark.parametrize("graph", [False, True])
-def test_batched_solve_uneven(gpu_lib, mode, graph):
+@pytest.mark.parametrize("kind", [1, 2])
+def test_batched_solve_uneven(gpu_lib, mode, graph, kind):
     """Four lattices of different shapes, masses and rhs counts solved in one
     lock-step GMRES (persistent batched applies); every solution passes the
     oracle's residual check."""
@@ -75,7 +89,11 @@ def test_batched_solve_uneven(gpu_lib, mode, graph):
         b = syn.spinor_block(dims, n, config=60 + k)
         probs.append((torch.from_numpy(U).to("cuda"), torch.from_numpy(_l2(b)).to("cuda"), m0))
         host.append((U, b, m0))
-    xs, stats, rc = lq.gmres_solve_batch(probs, restart=12, eo=True, mode=mode, tol=1e-10, use_graph=graph)
+    gpu_lib.set_batch_kernel(kind)
+    try:
+        xs, stats, rc = lq.gmres_solve_batch(probs, restart=12, eo=True, mode=mode, tol=1e-10, use_graph=graph)
+    finally:
+        gpu_lib.set_batch_kernel(0)
     assert rc == lq.OK
     for x, st, (U, b, m0) in zip(xs, stats, host):
         xh = np.moveaxis(x.cpu().numpy(), -1, 0)
@@ -98,3 +116,28 @@ def test_graph_replays_match_eager(gpu_lib):
         outs.append((x.clone(), st["iters"].copy()))
     assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][0], outs[2][0])
     assert np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_batched_solve_fp16_needs_one_volume(gpu_lib):
+    """FP16 refinement of a batch needs lattices of one volume (documented
+    argument error, raised before any launch)."""
+    import torch
+
+    probs = []
+    for k, dims in enumerate([(4, 4, 4, 4), (8, 4, 4, 4)]):
+        U = torch.from_numpy(syn.gauge_field(dims, "near_identity", config=80 + k)).to("cuda")
+        b = torch.from_numpy(_l2(syn.spinor_block(dims, 2, config=80 + k))).to("cuda")
+        probs.append((U, b, 0.1))
+    with pytest.raises(lq.LqcdError, match="one volume"):
+        lq.gmres_solve_batch(probs, restart=8, eo=True, mode="ir-f16")
+    # equal volumes (different shapes) are accepted
+    probs2 = []
+    for k, dims in enumerate([(8, 4, 4, 4), (4, 8, 4, 4)]):
+        U = syn.gauge_field(dims, "near_identity", config=82 + k)
+        b = syn.spinor_block(dims, 2, config=82 + k)
+        probs2.append((torch.from_numpy(U).to("cuda"), torch.from_numpy(_l2(b)).to("cuda"), 0.1, U, b))
+    xs, stats, rc = lq.gmres_solve_batch([p[:3] for p in probs2], restart=8, eo=True, mode="ir-f16", tol=1e-10)
+    assert rc == lq.OK
+    for x, (_, _, m0, U, b) in zip(xs, probs2):
+        xh = np.moveaxis(x.cpu().numpy(), -1, 0)
+        assert np.all(rel_err_per_rhs(dirac.apply_dw(U, xh, m0), b) <= 1e-10)
