@@ -16,7 +16,7 @@ Conventions (all arrays are numpy complex128, C order):
 * random streams: ``numpy.random.default_rng([config, role, index])`` with
   role 0 = gauge field, 1 = source spinors, 2 = projection spinors (chi),
   3 = gauge transformation, 4 = batch composition draws, 5 = plane-wave
-  polarisations.  Every rhs has its own stream, so any subset of right-hand
+  polarisations, 6 = clover field.  Every rhs has its own stream, so any subset of right-hand
   sides can be regenerated on its own.
 """
 from __future__ import annotations
@@ -29,6 +29,7 @@ ROLE_CHI = 2
 ROLE_GAUGE_TRANSFORM = 3
 ROLE_BATCH = 4
 ROLE_PLANE_WAVE = 5
+ROLE_CLOVER = 6
 
 # Gell-Mann matrices lambda_1..lambda_8 (standard normalisation tr(l_a l_b) = 2 delta_ab).
 _GELL_MANN = np.zeros((8, 3, 3), dtype=np.complex128)
@@ -159,3 +160,21 @@ def batch_composition(config: int = 4):
         nrhs = int(rng(config, ROLE_BATCH, k).integers(1, 33))
         out.append(dict(dims=(2 * L, L, L, L), eps=0.2 + 0.3 * k / 7, nrhs=nrhs, index=k))
     return out
+
+
+def clover_field(dims, config: int, scale: float = 0.2, index: int = 0) -> np.ndarray:
+    """Synthetic clover field, packed (N0, N1, N2, N3, 42) complex128: per site
+    two Hermitian 6x6 blocks H = scale (Z + Z^dagger) / (2 sqrt 6) with Z a
+    complex Gaussian 6x6 (stream (config, 6, index)), stored as each block's
+    6 diagonal entries (real) then its 15 entries above the diagonal in
+    row-major order.  Spectral radius about 2 scale, so (4 + m0) - C stays
+    well away from singular for scale <= 0.5 and m0 > -1."""
+    v = volume(dims)
+    z = _complex_normal(rng(config, ROLE_CLOVER, index), (v, 2, 6, 6))
+    h = scale * (z + np.conj(np.swapaxes(z, -1, -2))) / (2.0 * np.sqrt(6.0))
+    out = np.zeros((v, 42), dtype=np.complex128)
+    iu = np.triu_indices(6, 1)
+    for b in range(2):
+        out[:, 21 * b:21 * b + 6] = np.real(np.diagonal(h[:, b], axis1=-2, axis2=-1))
+        out[:, 21 * b + 6:21 * b + 21] = h[:, b][:, iu[0], iu[1]]
+    return out.reshape(tuple(dims) + (42,))
