@@ -141,6 +141,37 @@ int dirac_apply(const lqcd_lattice* lat, const void* U, const void* psi, void* e
 int dirac_apply_eo(const lqcd_lattice* lat, const void* U, const void* psi_e, void* eta_e,
                    int nrhs, double m0, int layout, int prec, int flags, void* stream);
 
+/* ---- the clover-improved operator D = D_W - C (Sec. III-A.1) ---- */
+
+/* Clover field C: [V][42] complex in the precision `prec` (same storage as
+ * U), device pointer, caller-owned.  Per site two Hermitian 6x6 blocks
+ * (Sec. III-A.1: "block-diagonal, each block Hermitian, 42 numbers"): block b
+ * acts on spins (2b, 2b+1) x colour with index 3 s + c inside the block, and
+ * is stored as its 6 diagonal entries (only the real parts are read) followed
+ * by the 15 entries above the diagonal row by row ((0,1), (0,2), ..., (4,5)).
+ *
+ * eta = D psi = D_W psi - C psi (Algorithm 1, line 1 with C), or with
+ * flags = LQCD_DAGGER eta = D^dagger psi = D_W^dagger psi - C psi (C is
+ * Hermitian).  Arguments, layouts and errors as dirac_apply. */
+int dirac_apply_clover(const lqcd_lattice* lat, const void* U, const void* C, const void* psi, void* eta, int nrhs,
+                       double m0, int layout, int prec, int flags, void* stream);
+
+/* Cinv[x] = ((4 + m0) I - C(x))^{-1} for every site, in the same packed
+ * storage (the inverse of a Hermitian block is Hermitian): the site-local
+ * inverse D_oo^{-1} of the odd-even Schur complement.  Computed in FP64 and
+ * stored in `prec`.  C, Cinv: device [V][42], caller-owned, distinct.
+ * Synchronises `stream`; returns LQCD_ERR_SINGULAR if a block has a pivot
+ * below 1e-13 (4 + m0) in magnitude (Cinv is then unspecified). */
+int clover_inverse(const lqcd_lattice* lat, const void* C, void* Cinv, double m0, int prec, void* stream);
+
+/* eta_e = S psi_e with S = D_ee - D_eo D_oo^{-1} D_oe (Sec. III-A.2 with the
+ * clover term): D_ee = (4 + m0) - C on even sites, D_oo^{-1} = Cinv (from
+ * clover_inverse with the same m0) on odd sites.  flags = LQCD_DAGGER gives
+ * S^dagger.  psi_e, eta_e: even half-lattice blocks as dirac_apply_eo.  Uses
+ * a temporary odd block allocated with hipMallocAsync on `stream`. */
+int dirac_apply_eo_clover(const lqcd_lattice* lat, const void* U, const void* C, const void* Cinv, const void* psi_e,
+                          void* eta_e, int nrhs, double m0, int layout, int prec, int flags, void* stream);
+
 /* ---- uneven batches of independent lattices ---- */
 #define LQCD_MAX_BATCH 16
 
@@ -190,9 +221,12 @@ int lqcd_autotune_batch(int nprob, const lqcd_problem* probs, int prec, int reps
 /* Measured HBM ceiling (a STREAM-style probe, the paper's empirical memory
  * ceiling of Sec. V-A, eq. (4)): kind 0 = copy b = a, 1 = triad
  * a = b + s c, over n doubles per array (device buffers a, b, c of n doubles;
- * c unused for copy).  Tries four launch shapes (workgroups per CU, plain or
- * non-temporal stores), each launched `reps` times, and returns the best mean
- * time per launch in *ms.  Synchronises `stream`. */
+ * c unused for copy).  Tries five launch shapes (persistent grids of 8 or 16
+ * workgroups per CU with plain or non-temporal stores, and one workgroup per
+ * contiguous chunk with non-temporal loads and stores), each launched `reps`
+ * times, and returns the best mean time per launch in *ms.  Synchronises
+ * `stream`.  The grid of the chunked shape is n / 2048 workgroups, so n may
+ * not exceed 2^42. */
 int lqcd_hbm_probe(int kind, double* a, double* b, const double* c, size_t n, int reps, double* ms, void* stream);
 
 /* Parameters of gmres_solve (Algorithm 2). */
@@ -241,6 +275,17 @@ size_t gmres_workspace_bytes(const lqcd_lattice* lat, int nrhs, const lqcd_solve
 int gmres_solve(const lqcd_lattice* lat, const void* U, const void* b, void* x, int nrhs,
                 double m0, int layout, const lqcd_solver_params* params, void* work,
                 size_t work_bytes, lqcd_rhs_stats* stats, void* stream);
+
+/* gmres_solve for the clover-improved operator D = D_W - C (C as for
+ * dirac_apply_clover, FP64, device [V][42], caller-owned).  With eo the
+ * Schur complement uses D_oo^{-1} = ((4+m0) - C_o)^{-1}, computed in the
+ * workspace (LQCD_ERR_SINGULAR if singular); the refinement modes convert
+ * C and D_oo^{-1} to the working precision.  Workspace from
+ * gmres_workspace_bytes_clover; everything else as gmres_solve. */
+size_t gmres_workspace_bytes_clover(const lqcd_lattice* lat, int nrhs, const lqcd_solver_params* p);
+int gmres_solve_clover(const lqcd_lattice* lat, const void* U, const void* C, const void* b, void* x, int nrhs,
+                       double m0, int layout, const lqcd_solver_params* params, void* work, size_t work_bytes,
+                       lqcd_rhs_stats* stats, void* stream);
 
 /* Batched solves over independent lattices (uneven sizes and rhs counts):
  * problem k solves D_k x_k = b_k with b = probs[k].psi and x = probs[k].eta

@@ -84,6 +84,12 @@ def load():
     lib.lqcd_lattice_tables.argtypes = [lp, vp, vp]
     lib.dirac_apply.argtypes = [lp, vp, vp, vp, i32, dbl, i32, i32, i32, vp]
     lib.dirac_apply_eo.argtypes = [lp, vp, vp, vp, i32, dbl, i32, i32, i32, vp]
+    lib.dirac_apply_clover.argtypes = [lp, vp, vp, vp, vp, i32, dbl, i32, i32, i32, vp]
+    lib.dirac_apply_clover.restype = i32
+    lib.clover_inverse.argtypes = [lp, vp, vp, dbl, i32, vp]
+    lib.clover_inverse.restype = i32
+    lib.dirac_apply_eo_clover.argtypes = [lp, vp, vp, vp, vp, vp, i32, dbl, i32, i32, i32, vp]
+    lib.dirac_apply_eo_clover.restype = i32
     lib.lqcd_set_kernel_variant.argtypes = [i32, vp]
     lib.dirac_apply_batch.argtypes = [i32, ctypes.POINTER(Problem), i32, i32, vp]
     lib.dirac_apply_batch.restype = i32
@@ -116,6 +122,11 @@ def load():
         lib.gmres_solve.argtypes = [lp, vp, vp, vp, i32, dbl, i32, ctypes.POINTER(SolverParams), vp,
                                     ctypes.c_size_t, ctypes.POINTER(RhsStats), vp]
         lib.gmres_solve.restype = i32
+        lib.gmres_workspace_bytes_clover.argtypes = [lp, i32, ctypes.POINTER(SolverParams)]
+        lib.gmres_workspace_bytes_clover.restype = ctypes.c_size_t
+        lib.gmres_solve_clover.argtypes = [lp, vp, vp, vp, vp, i32, dbl, i32, ctypes.POINTER(SolverParams), vp,
+                                           ctypes.c_size_t, ctypes.POINTER(RhsStats), vp]
+        lib.gmres_solve_clover.restype = i32
         lib.gmres_workspace_bytes_batch.argtypes = [i32, ctypes.POINTER(Problem), ctypes.POINTER(SolverParams)]
         lib.gmres_workspace_bytes_batch.restype = ctypes.c_size_t
         lib.gmres_solve_batch.argtypes = [i32, ctypes.POINTER(Problem), ctypes.POINTER(SolverParams), vp,
@@ -266,6 +277,68 @@ def dirac_apply_eo(U, psi_e, m0, layout=LAYOUT2, dagger=False, out=None):
     return out
 
 
+# ---------------------------------------------------------------- clover
+def _check_clover(C, dims, prec):
+    if _prec_of(C) != prec:
+        raise TypeError("the clover field must have the precision of U")
+    want = tuple(dims) + (42,) + ((2,) if prec == F16 else ())
+    if tuple(C.shape) != want:
+        raise ValueError(f"clover field shape {tuple(C.shape)}, expected {want}")
+
+
+def dirac_apply_clover(U, C, psi, m0, layout=LAYOUT2, dagger=False, out=None):
+    """eta = (D_W - C) psi (or its adjoint) with a packed clover field C
+    [N0, N1, N2, N3, 42] (two Hermitian 6x6 blocks per site)."""
+    import torch
+
+    prec = _prec_of(psi)
+    if _prec_of(U) != prec:
+        raise TypeError("U and psi must have the same precision")
+    dims = _dims_of_links(U, prec)
+    _check_clover(C, dims, prec)
+    nrhs, _ = _nrhs_of(psi, prec, layout, 4)
+    out = torch.empty_like(psi) if out is None else out
+    _check_device(U, C, psi, out)
+    _check(load().dirac_apply_clover(ctypes.byref(_lattice(dims)), U.data_ptr(), C.data_ptr(), psi.data_ptr(),
+                                     out.data_ptr(), nrhs, float(m0), layout, prec, DAGGER if dagger else 0, _stream()))
+    return out
+
+
+def clover_inverse(C, m0, dims):
+    """Packed ((4 + m0) - C(x))^{-1} for every site (same shape and precision as C)."""
+    import torch
+
+    prec = _prec_of(C)
+    _check_clover(C, dims, prec)
+    out = torch.empty_like(C)
+    _check_device(C, out)
+    _check(load().clover_inverse(ctypes.byref(_lattice(dims)), C.data_ptr(), out.data_ptr(), float(m0), prec,
+                                 _stream()))
+    return out
+
+
+def dirac_apply_eo_clover(U, C, Cinv, psi_e, m0, layout=LAYOUT2, dagger=False, out=None):
+    """eta_e = S psi_e with the clover term: S = D_ee - D_eo D_oo^-1 D_oe, Cinv
+    from clover_inverse(C, m0)."""
+    import torch
+
+    prec = _prec_of(psi_e)
+    if _prec_of(U) != prec:
+        raise TypeError("U and psi_e must have the same precision")
+    dims = _dims_of_links(U, prec)
+    _check_clover(C, dims, prec)
+    _check_clover(Cinv, dims, prec)
+    nrhs, sdims = _nrhs_of(psi_e, prec, layout, 1)
+    if int(sdims[0]) * 2 != int(np.prod(dims)):
+        raise ValueError(f"half-lattice block has {sdims[0]} sites, lattice {dims} needs {int(np.prod(dims)) // 2}")
+    out = torch.empty_like(psi_e) if out is None else out
+    _check_device(U, C, Cinv, psi_e, out)
+    _check(load().dirac_apply_eo_clover(ctypes.byref(_lattice(dims)), U.data_ptr(), C.data_ptr(), Cinv.data_ptr(),
+                                        psi_e.data_ptr(), out.data_ptr(), nrhs, float(m0), layout, prec,
+                                        DAGGER if dagger else 0, _stream()))
+    return out
+
+
 # ---------------------------------------------------------------- solver
 MODES = {"f64": 0, "ir-f32": 1, "ir-f16": 2}
 
@@ -310,6 +383,34 @@ def gmres_solve(U, b, m0, layout=LAYOUT2, x0=None, work=None, **kw):
     st = (RhsStats * nrhs)()
     rc = _check(load().gmres_solve(ctypes.byref(_lattice(dims)), U.data_ptr(), b.data_ptr(), x.data_ptr(), nrhs,
                                    float(m0), layout, ctypes.byref(p), work.data_ptr(), work.numel(), st, _stream()))
+    stats = {k: np.array([getattr(s, k) for s in st]) for k, _ in RhsStats._fields_}
+    return x, stats, rc
+
+
+def gmres_solve_clover(U, C, b, m0, layout=LAYOUT2, x0=None, work=None, **kw):
+    """x = (D_W - C)^-1 b per rhs (FP64 U, clover field C [N0..N3, 42] and b);
+    same keywords and return value as gmres_solve."""
+    import torch
+
+    if U.dtype != torch.complex128 or b.dtype != torch.complex128:
+        raise TypeError("gmres_solve_clover takes complex128 U, C and b")
+    dims = _dims_of_links(U, F64)
+    _check_clover(C, dims, F64)
+    nrhs, sdims = _nrhs_of(b, F64, layout, 4)
+    if tuple(sdims) != tuple(dims):
+        raise ValueError(f"source lattice {sdims} does not match gauge lattice {dims}")
+    p = solver_params(x_is_guess=x0 is not None, **kw)
+    x = x0.clone() if x0 is not None else torch.empty_like(b)
+    need = int(load().gmres_workspace_bytes_clover(ctypes.byref(_lattice(dims)), nrhs, ctypes.byref(p)))
+    if need == 0:
+        raise ValueError("invalid solver arguments")
+    if work is None or work.numel() < need:
+        work = torch.empty(need, dtype=torch.uint8, device=b.device)
+    _check_device(U, C, b, x, work)
+    st = (RhsStats * nrhs)()
+    rc = _check(load().gmres_solve_clover(ctypes.byref(_lattice(dims)), U.data_ptr(), C.data_ptr(), b.data_ptr(),
+                                          x.data_ptr(), nrhs, float(m0), layout, ctypes.byref(p), work.data_ptr(),
+                                          work.numel(), st, _stream()))
     stats = {k: np.array([getattr(s, k) for s in st]) for k, _ in RhsStats._fields_}
     return x, stats, rc
 

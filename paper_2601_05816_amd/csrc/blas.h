@@ -18,6 +18,8 @@ hipError_t norm_parts(int prec, const void* x, size_t nelem, int nrhs, const int
                       hipStream_t s);
 hipError_t cgs_update(int prec, const void* V, size_t vstride, int K, const void* h, void* w, size_t nelem, int nrhs,
                       const int* live, void* part, unsigned nblk, hipStream_t s);
+// number of partial-sum blocks cgs_update leaves in `part` (reduce that many)
+unsigned cgs_update_parts(int prec, size_t nelem, int nrhs, unsigned nblk);
 hipError_t b_minus_y(int prec, const void* b, void* y, size_t nelem, int nrhs, const int* live, void* part,
                      unsigned nblk, hipStream_t s);
 hipError_t reduce_parts(const void* part, int nblk, int K, int nrhs, double scale, void* out, hipStream_t s);

@@ -133,6 +133,67 @@ __global__ __launch_bounds__(256) void k_cgs_update(const store_t<P>* __restrict
   block_combine<1>(acc, 1, nrhs, on, part);
 }
 
+// Chunked, non-persistent forms of the two kernels above that write a
+// vector: block b owns the contiguous elements [b CH, (b+1) CH) with
+// CH = SB x iters, SB = the largest multiple of nrhs not above the block
+// size, so thread t < SB keeps rhs t % nrhs.  With one block per chunk the
+// dispatcher keeps the blocks in flight on neighbouring addresses, which
+// measured 15 % more read+write bandwidth on MI355X than a persistent
+// grid-stride loop.
+__device__ __forceinline__ void chunk_combine(cx<double> v, int nrhs, int sb, bool on,
+                                              cx<double>* __restrict__ part) {
+  __shared__ cx<double> sh[256];
+  const int tid = threadIdx.x;
+  sh[tid] = on ? v : cx<double>{0.0, 0.0};
+  __syncthreads();
+  for (int r = tid; r < nrhs; r += blockDim.x) {
+    cx<double> a = {0.0, 0.0};
+    for (int i = r; i < sb; i += nrhs) a = a + sh[i];
+    part[(size_t)blockIdx.x * nrhs + r] = a;
+  }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_cgs_update_c(const store_t<P>* __restrict__ V, size_t vstride, int K,
+                                                      const cx<double>* __restrict__ h, store_t<P>* __restrict__ w,
+                                                      size_t nelem, int nrhs, int iters,
+                                                      const int* __restrict__ live, cx<double>* __restrict__ part) {
+  const int sb = (int)(blockDim.x / nrhs) * nrhs;
+  const int tid = threadIdx.x;
+  const int rhs = tid % nrhs;
+  const bool on = tid < sb && (!live || live[rhs]);
+  cx<double> acc = {0.0, 0.0};
+  if (on) {
+    const size_t e0 = (size_t)blockIdx.x * sb * iters + tid;
+    for (int i = 0; i < iters; ++i) {
+      const size_t e = e0 + (size_t)i * sb;
+      if (e >= nelem) break;
+      cx<double> v = ldd<P>(w + e);
+      for (int k = 0; k < K; ++k) v = cmadd(v, -h[(size_t)k * nrhs + rhs], ldd<P>(V + (size_t)k * vstride + e));
+      std_<P>(w + e, v);
+      acc.re = fma(v.re, v.re, fma(v.im, v.im, acc.re));
+    }
+  }
+  chunk_combine(acc, nrhs, sb, on, part);
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_scale_c(store_t<P>* __restrict__ x, size_t nelem, int nrhs, int iters,
+                                                 const double* __restrict__ s, const int* __restrict__ live) {
+  const int sb = (int)(blockDim.x / nrhs) * nrhs;
+  const int tid = threadIdx.x;
+  const int rhs = tid % nrhs;
+  if (tid >= sb || (live && !live[rhs])) return;
+  const double f = s[rhs];
+  const size_t e0 = (size_t)blockIdx.x * sb * iters + tid;
+  for (int i = 0; i < iters; ++i) {
+    const size_t e = e0 + (size_t)i * sb;
+    if (e >= nelem) break;
+    cx<double> v = ldd<P>(x + e);
+    std_<P>(x + e, cx<double>{v.re * f, v.im * f});
+  }
+}
+
 // y = b - y ; part = |y|^2 per block
 template <int P>
 __global__ __launch_bounds__(256) void k_bmy(const store_t<P>* __restrict__ b, store_t<P>* __restrict__ y,
@@ -308,10 +369,36 @@ hipError_t norm_parts(int prec, const void* x, size_t nelem, int nrhs, const int
   return hipGetLastError();
 }
 
+// Chunk length (in multiples of the block's rhs-aligned width) of the
+// chunked kernels: at least 16, and few enough blocks that their partial
+// sums fit the nblk x DOT_KB x nrhs part buffer.
+static int chunk_iters(size_t nelem, int nrhs, unsigned nblk) {
+  const size_t sb = (size_t)(256 / nrhs) * nrhs;
+  const size_t cap = (size_t)nblk * DOT_KB;  // partial rows available
+  size_t it = 16;
+  while ((nelem + sb * it - 1) / (sb * it) > cap) it *= 2;
+  return (int)it;
+}
+
+unsigned cgs_update_parts(int prec, size_t nelem, int nrhs, unsigned nblk) {
+  if ((g_vec_blas && vec_width(prec, nrhs) > 1) || nrhs > 256) return nblk;
+  const size_t sb = (size_t)(256 / nrhs) * nrhs;
+  const size_t ch = sb * (size_t)chunk_iters(nelem, nrhs, nblk);
+  return (unsigned)((nelem + ch - 1) / ch);
+}
+
 hipError_t cgs_update(int prec, const void* V, size_t vstride, int K, const void* h, void* w, size_t nelem, int nrhs,
                       const int* live, void* part, unsigned nblk, hipStream_t s) {
   if (g_vec_blas && vec_width(prec, nrhs) > 1)
     return cgs_update_v(prec, V, vstride, K, h, w, nelem, nrhs, live, part, nblk, s);
+  if (nrhs <= 256) {
+    const int it = chunk_iters(nelem, nrhs, nblk);
+    const unsigned nb = cgs_update_parts(prec, nelem, nrhs, nblk);
+    PREC_SWITCH(prec, hipLaunchKernelGGL((k_cgs_update_c<PP>), dim3(nb), dim3(256), 0, s, (const store_t<PP>*)V,
+                                         vstride, K, (const cx<double>*)h, (store_t<PP>*)w, nelem, nrhs, it, live,
+                                         (cx<double>*)part));
+    return hipGetLastError();
+  }
   PREC_SWITCH(prec, hipLaunchKernelGGL((k_cgs_update<PP>), dim3(nblk), dim3(256), 0, s, (const store_t<PP>*)V,
                                        vstride, K, (const cx<double>*)h, (store_t<PP>*)w, nelem, nrhs, live,
                                        (cx<double>*)part));
@@ -334,6 +421,12 @@ hipError_t reduce_parts(const void* part, int nblk, int K, int nrhs, double scal
 
 hipError_t scale_rhs(int prec, void* x, size_t nelem, int nrhs, const double* f, const int* live, hipStream_t s) {
   if (g_vec_blas && vec_width(prec, nrhs) > 1) return scale_rhs_v(prec, x, nelem, nrhs, f, live, red_blocks(nelem), s);
+  if (nrhs <= 256) {
+    const size_t ch = (size_t)(256 / nrhs) * nrhs * 16;
+    PREC_SWITCH(prec, hipLaunchKernelGGL((k_scale_c<PP>), dim3((unsigned)((nelem + ch - 1) / ch)), dim3(256), 0, s,
+                                         (store_t<PP>*)x, nelem, nrhs, 16, f, live));
+    return hipGetLastError();
+  }
   PREC_SWITCH(prec, hipLaunchKernelGGL((k_scale<PP>), dim3(red_blocks(nelem)), dim3(256), 0, s, (store_t<PP>*)x,
                                        nelem, nrhs, f, live));
   return hipGetLastError();

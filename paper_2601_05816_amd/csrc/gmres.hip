@@ -188,6 +188,11 @@ struct Solver {
   // device buffers
   const void* U64;
   void* Ulo;
+  // clover term (D = D_W - C): caller's FP64 field, the site-local inverse
+  // of D_oo (eo) and working-precision copies (refinement modes)
+  bool clov = false;
+  const void* C64 = nullptr;
+  void *Ci64 = nullptr, *Clo = nullptr, *Cilo = nullptr;
   void *xe, *xo, *be, *bo, *bp;   // FP64 internal vectors (xo, bo only with eo)
   void* r64;                      // FP64 residual (refinement modes)
   void* tmp64;                    // FP64 odd temporary (eo)
@@ -214,6 +219,9 @@ struct Solver {
     rlo = mode ? a.take(nelem * esize(pw)) : nullptr;
     dlo = mode ? a.take(nelem * esize(pw)) : nullptr;
     Ulo = mode ? a.take(4 * V * 9 * esize(pw)) : nullptr;
+    Ci64 = (clov && eo) ? a.take(V * 42 * 16) : nullptr;
+    Clo = (clov && mode) ? a.take(V * 42 * esize(pw)) : nullptr;
+    Cilo = (clov && eo && mode) ? a.take(V * 42 * esize(pw)) : nullptr;
     part = (zd*)a.take((size_t)nblk * DOT_KB * nrhs * sizeof(zd));
     hcol = (zd*)a.take((size_t)(m + 1) * nrhs * sizeof(zd));
     nrm = (zd*)a.take((size_t)nrhs * sizeof(zd));
@@ -242,6 +250,15 @@ struct Solver {
   // out = A in, in the working precision `prec` (A = S with eo, else D)
   hipError_t apply(int prec, const void* in, void* out, const int* lv) {
     const void* U = prec == LQCD_F64 ? U64 : Ulo;
+    if (clov) {  // pass 1 tmp_o = D_oo^{-1} H_oe in; pass 2 out = (d - C_e) in - H_eo tmp_o / 4
+      const void* Cp = prec == LQCD_F64 ? C64 : Clo;
+      if (!eo) return wilson_full_clover(&lat, U, Cp, in, out, nrhs, d, -0.5, LQCD_LAYOUT2, prec, dag, s);
+      void* t = prec == LQCD_F64 ? tmp64 : tmplo;
+      hipError_t e = wilson_eo_clover(&lat, U, in, nullptr, t, 1, nrhs, 0.0, 1.0, LQCD_LAYOUT2, prec, dag, lv, nullptr,
+                                      prec == LQCD_F64 ? Ci64 : Cilo, s);
+      if (e != hipSuccess) return e;
+      return wilson_eo_clover(&lat, U, t, in, out, 0, nrhs, d, -0.25, LQCD_LAYOUT2, prec, dag, lv, Cp, nullptr, s);
+    }
     if (eo) {
       void* t = prec == LQCD_F64 ? tmp64 : tmplo;
       hipError_t e = wilson_eo(&lat, U, in, nullptr, t, 1, nrhs, 0.0, 1.0, LQCD_LAYOUT2, prec, dag, lv, s);
@@ -366,7 +383,9 @@ static hipError_t arnoldi_step(Group& G, int prec, int j, double sc, double tol,
     }
     if ((e = cgs_update(prec, S.basis, nel, j + 1, S.hcol, w, nel, S.nrhs, S.live, S.part, S.nblk, s)) != hipSuccess)
       return e;
-    if ((e = reduce_parts(S.part, S.nblk, 1, S.nrhs, sc, S.nrm, s)) != hipSuccess) return e;
+    if ((e = reduce_parts(S.part, (int)cgs_update_parts(prec, nel, S.nrhs, S.nblk), 1, S.nrhs, sc, S.nrm, s)) !=
+        hipSuccess)
+      return e;
     hipLaunchKernelGGL(k_arnoldi_col, dim3(S.small_grid()), dim3(64), 0, s, j, m, S.nrhs, S.hcol, S.nrm, S.H, S.cs,
                        S.sn, S.g, t.bref, tol, fixed, S.live, S.steps, S.est, S.scl);
     if ((e = scale_rhs(prec, w, nel, S.nrhs, S.scl, S.live, s)) != hipSuccess) return e;
@@ -500,8 +519,9 @@ static int check_params(const lqcd_solver_params* p) {
   return LQCD_OK;
 }
 
-static void setup(Solver& S, const lqcd_lattice* lat, int nrhs, const lqcd_solver_params* p) {
+static void setup(Solver& S, const lqcd_lattice* lat, int nrhs, const lqcd_solver_params* p, bool clov = false) {
   S.lat = *lat;
+  S.clov = clov;
   S.V = (size_t)lat->dims[0] * lat->dims[1] * lat->dims[2] * lat->dims[3];
   S.eo = p->eo ? 1 : 0;
   S.nsite = S.eo ? S.V / 2 : S.V;
@@ -514,9 +534,9 @@ static void setup(Solver& S, const lqcd_lattice* lat, int nrhs, const lqcd_solve
   S.nblk = reduce_grid(S.nelem);
 }
 
-static size_t task_bytes(const lqcd_lattice* lat, int nrhs, const lqcd_solver_params* p) {
+static size_t task_bytes(const lqcd_lattice* lat, int nrhs, const lqcd_solver_params* p, bool clov = false) {
   Solver S;
-  setup(S, lat, nrhs, p);
+  setup(S, lat, nrhs, p, clov);
   Arena a{nullptr, 0, 0};
   S.layout(a);
   return (a.off + 511) & ~(size_t)255;
@@ -565,9 +585,22 @@ static int solve_group(Group& G, const lqcd_solver_params* params, lqcd_rhs_stat
     } else {
       HIPCHK(hipMemsetAsync(S.xe, 0, S.nelem * 16, s));
     }
-    if (S.eo)  // b'_e = b_e - D_eo D_oo^{-1} b_o = b_e + (1/2) H_eo b_o / (4+m0)
+    if (S.clov && S.eo) {  // D_oo^{-1} = ((4+m0) - C_o)^{-1}, site by site
+      HIPCHK(hipMemsetAsync(S.flags, 0, 2 * sizeof(int), s));
+      HIPCHK(clover_invert(&S.lat, S.C64, S.Ci64, S.d, LQCD_F64, S.flags, s));
+      int sing = 0;
+      HIPCHK(hipMemcpyAsync(&sing, S.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      if (sing) return fail(LQCD_ERR_SINGULAR, "gmres: (4 + m0) - C(x) is singular on some odd site");
+    }
+    if (S.eo && S.clov) {  // b'_e = b_e + (1/2) H_eo D_oo^{-1} b_o
+      HIPCHK(clover_site_mul(&S.lat, S.Ci64, S.bo, S.tmp64, 1, S.nrhs, 1.0, LQCD_LAYOUT2, LQCD_F64, s));
+      HIPCHK(wilson_eo(&S.lat, t.U, S.tmp64, S.be, S.bp, 0, S.nrhs, 1.0, 0.5, LQCD_LAYOUT2, LQCD_F64, S.dag, nullptr,
+                       s));
+    } else if (S.eo) {  // b'_e = b_e - D_eo D_oo^{-1} b_o = b_e + (1/2) H_eo b_o / (4+m0)
       HIPCHK(wilson_eo(&S.lat, t.U, S.bo, S.be, S.bp, 0, S.nrhs, 1.0, 0.5 / S.d, LQCD_LAYOUT2, LQCD_F64, S.dag,
                        nullptr, s));
+    }
   }
   if (mode == 0) {
     for (Task& t : G.T) {
@@ -581,7 +614,11 @@ static int solve_group(Group& G, const lqcd_solver_params* params, lqcd_rhs_stat
     // iterative refinement: FP64 residual and update, inner GMRES in plo
     const int plo = G.T[0].S.plo;
     const double itol = params->inner_tol > 0 ? params->inner_tol : (plo == LQCD_F32 ? 1e-4 : 1e-2);
-    for (Task& t : G.T) HIPCHK(convert_links(t.U, plo, t.S.Ulo, 4 * t.S.V * 9, s));
+    for (Task& t : G.T) {
+      HIPCHK(convert_links(t.U, plo, t.S.Ulo, 4 * t.S.V * 9, s));
+      if (t.S.clov) HIPCHK(convert_links(t.S.C64, plo, t.S.Clo, t.S.V * 42, s));
+      if (t.S.clov && t.S.eo) HIPCHK(convert_links(t.S.Ci64, plo, t.S.Cilo, t.S.V * 42, s));
+    }
     for (int outer = 0; outer < params->max_outer; ++outer) {
       if (outer == 0 && x_zero) {
         for (Task& t : G.T) {
@@ -641,7 +678,22 @@ static int solve_group(Group& G, const lqcd_solver_params* params, lqcd_rhs_stat
     const double d = S.d;
     const int dims[4] = {S.lat.dims[0], S.lat.dims[1], S.lat.dims[2], S.lat.dims[3]};
     void* t1 = S.mode ? S.r64 : S.Vk(LQCD_F64, 0);
-    if (S.eo) {
+    if (S.eo && S.clov) {
+      // x_o = D_oo^{-1} (b_o + (1/2) H_oe x_e); r = b - D x with D_pp = (4+m0) - C_p
+      HIPCHK(wilson_eo_clover(&S.lat, t.U, S.xe, S.bo, S.xo, 1, S.nrhs, 1.0, 0.5, LQCD_LAYOUT2, LQCD_F64, S.dag,
+                              nullptr, nullptr, S.Ci64, s));
+      HIPCHK(wilson_eo_clover(&S.lat, t.U, S.xo, S.xe, t1, 0, S.nrhs, d, -0.5, LQCD_LAYOUT2, LQCD_F64, S.dag, nullptr,
+                              S.C64, nullptr, s));
+      HIPCHK(b_minus_y(LQCD_F64, S.be, t1, S.nelem, S.nrhs, nullptr, S.part, S.nblk, s));
+      HIPCHK(wilson_eo_clover(&S.lat, t.U, S.xe, S.xo, S.tmp64, 1, S.nrhs, d, -0.5, LQCD_LAYOUT2, LQCD_F64, S.dag,
+                              nullptr, S.C64, nullptr, s));
+      HIPCHK(b_minus_y(LQCD_F64, S.bo, S.tmp64, S.nelem, S.nrhs, nullptr, S.part, S.nblk, s));
+      HIPCHK(full_norm2(t, t1, S.tmp64, s));
+    } else if (S.clov) {
+      HIPCHK(wilson_full_clover(&S.lat, t.U, S.C64, S.xe, t1, S.nrhs, d, -0.5, LQCD_LAYOUT2, LQCD_F64, S.dag, s));
+      HIPCHK(b_minus_y(LQCD_F64, S.be, t1, S.nelem, S.nrhs, nullptr, S.part, S.nblk, s));
+      HIPCHK(reduce_parts(S.part, S.nblk, 1, S.nrhs, 1.0, S.nrm, s));
+    } else if (S.eo) {
       // x_o = (b_o + (1/2) H_oe x_e) / (4+m0)
       HIPCHK(wilson_eo(&S.lat, t.U, S.xe, S.bo, S.xo, 1, S.nrhs, 1.0 / d, 0.5 / d, LQCD_LAYOUT2, LQCD_F64, S.dag,
                        nullptr, s));
@@ -739,8 +791,9 @@ size_t gmres_workspace_bytes(const lqcd_lattice* lat, int nrhs, const lqcd_solve
 }
 
 static int init_task(Task& t, const lqcd_lattice* lat, const void* U, const void* b, void* x, int nrhs, double m0,
-                     int layout, const lqcd_solver_params* p, char* work) {
-  setup(t.S, lat, nrhs, p);
+                     int layout, const lqcd_solver_params* p, char* work, const void* C = nullptr) {
+  setup(t.S, lat, nrhs, p, C != nullptr);
+  t.S.C64 = C;
   t.S.m0 = m0;
   t.S.d = 4.0 + m0;
   t.S.U64 = U;
@@ -769,6 +822,29 @@ int gmres_solve(const lqcd_lattice* lat, const void* U, const void* b, void* x, 
   G.T.resize(1);
   char* w = (char*)work + ((256 - ((uintptr_t)work & 255)) & 255);
   init_task(G.T[0], lat, U, b, x, nrhs, m0, layout, params, w);
+  return run_group(G, params, stats, (hipStream_t)stream, params->use_graph != 0);
+}
+
+size_t gmres_workspace_bytes_clover(const lqcd_lattice* lat, int nrhs, const lqcd_solver_params* p) {
+  if (check_lattice(lat) || nrhs < 1 || check_params(p)) return 0;
+  return task_bytes(lat, nrhs, p, true) + 256;
+}
+
+int gmres_solve_clover(const lqcd_lattice* lat, const void* U, const void* C, const void* b, void* x, int nrhs,
+                       double m0, int layout, const lqcd_solver_params* params, void* work, size_t work_bytes,
+                       lqcd_rhs_stats* stats, void* stream) {
+  int rc = check_lattice(lat);
+  if (rc) return rc;
+  if ((rc = check_block(nrhs, layout, LQCD_F64))) return rc;
+  if ((rc = check_params(params))) return rc;
+  if (!U || !C || !b || !x) return fail(LQCD_ERR_ARG, "gmres_solve_clover: null array pointer");
+  const size_t need = gmres_workspace_bytes_clover(lat, nrhs, params);
+  if (!work || work_bytes < need)
+    return fail(LQCD_ERR_WORKSPACE, "gmres_solve_clover: workspace of %zu bytes given, %zu needed", work_bytes, need);
+  Group G;
+  G.T.resize(1);
+  char* w = (char*)work + ((256 - ((uintptr_t)work & 255)) & 255);
+  init_task(G.T[0], lat, U, b, x, nrhs, m0, layout, params, w, C);
   return run_group(G, params, stats, (hipStream_t)stream, params->use_graph != 0);
 }
 

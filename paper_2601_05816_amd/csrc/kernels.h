@@ -53,6 +53,21 @@ bool dma_supported(int prec, int layout, int nrhs);
 hipError_t wilson_full_dma(const lqcd_lattice* lat, const void* U, const void* psi, void* eta, int nrhs, double diag,
                            double hopc, int prec, bool dagger, const kcfg& c, hipStream_t s);
 
+// The clover-improved operator (clover.hip): one (site, rhs) per work item.
+// Full: eta = diag psi - C psi + hopc hop(psi).  Odd-even half (out on
+// parity p, in on 1-p): out = Cout [alpha xin - Cx xin + beta hop(in)], Cx and
+// Cout per-site packed 42-entry fields (either may be null).
+hipError_t wilson_full_clover(const lqcd_lattice* lat, const void* U, const void* C, const void* psi, void* eta,
+                              int nrhs, double diag, double hopc, int layout, int prec, bool dagger, hipStream_t s);
+hipError_t wilson_eo_clover(const lqcd_lattice* lat, const void* U, const void* in, const void* xin, void* out, int p,
+                            int nrhs, double alpha, double beta, int layout, int prec, bool dagger, const int* live,
+                            const void* Cx, const void* Cout, hipStream_t s);
+// out = alpha Cm in on the parity-p half lattice (a site-local block multiply)
+hipError_t clover_site_mul(const lqcd_lattice* lat, const void* Cm, const void* in, void* out, int p, int nrhs,
+                           double alpha, int layout, int prec, hipStream_t s);
+hipError_t clover_invert(const lqcd_lattice* lat, const void* C, void* Cinv, double d, int prec, int* dflag,
+                         hipStream_t s);
+
 // Configuration for an apply (tune.hip): the process-wide forced setting if
 // any, else the autotuner's entry for these arguments, else the default.
 kcfg choose_cfg(int kind, const lqcd_lattice* lat, int nrhs, int prec, int layout);

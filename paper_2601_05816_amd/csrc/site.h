@@ -2,6 +2,7 @@
 // kernels (dslash.hip) and the persistent batch kernel (batch.hip).
 #pragma once
 
+#include "clover.h"
 #include "wilson.h"
 
 namespace lq {
@@ -18,13 +19,15 @@ inline geo4 make_geo(const lqcd_lattice* lat) {
   return g;
 }
 
-// eta(site, rhs) = diag psi + hopc hop(psi) at one site and rhs
-template <int PREC, int LAYOUT, int SG>
+// eta(site, rhs) = diag psi + hopc hop(psi) at one site and rhs, minus
+// C(site) psi(site) when CL (clover field C: 42 packed entries per site)
+template <int PREC, int LAYOUT, int SG, bool CL = false>
 __device__ __forceinline__ void wilson_full_site(const typename prec_traits<PREC>::store* __restrict__ U,
                                                  const typename prec_traits<PREC>::store* __restrict__ psi,
                                                  typename prec_traits<PREC>::store* __restrict__ eta,
                                                  const geo4& g, int nrhs, typename prec_traits<PREC>::real diag,
-                                                 typename prec_traits<PREC>::real hopc, size_t site, int rhs) {
+                                                 typename prec_traits<PREC>::real hopc, size_t site, int rhs,
+                                                 const typename prec_traits<PREC>::store* __restrict__ C = nullptr) {
   typedef typename prec_traits<PREC>::store S;
   typedef typename prec_traits<PREC>::real R;
   const size_t V = g.V;
@@ -62,20 +65,29 @@ __device__ __forceinline__ void wilson_full_site(const typename prec_traits<PREC
     cx<R> a = acc.c[i / 3][i % 3], b = p.c[i / 3][i % 3];
     acc.c[i / 3][i % 3] = {fma(hopc, a.re, diag * b.re), fma(hopc, a.im, diag * b.im)};
   }
+  if (CL) {
+    const spinor<R> cp = clover_mul<S, R>(C + site * 42, p);
+#pragma unroll
+    for (int i = 0; i < 12; ++i) acc.c[i / 3][i % 3] = acc.c[i / 3][i % 3] - cp.c[i / 3][i % 3];
+  }
   store_spinor<S, R>(eta, me, cs, acc);
 }
 
 // --------------------------------------------------------- odd-even hop
 // out(h) = alpha * xin(h) + beta * hop(in)(h) for one parity-p site h (compact
 // index) and rhs, where `in` is a parity (1-p) compact block; xin may be
-// null (alpha ignored).
-template <int PREC, int LAYOUT, int SG>
+// null (alpha ignored).  When CL, with per-site packed 42-entry fields
+// indexed by site number (either may be null):
+//   out(h) = Cout(x) [alpha xin(h) - Cx(x) xin(h) + beta hop(in)(h)].
+template <int PREC, int LAYOUT, int SG, bool CL = false>
 __device__ __forceinline__ void wilson_eo_site(const typename prec_traits<PREC>::store* __restrict__ U,
                                                const typename prec_traits<PREC>::store* __restrict__ in,
                                                const typename prec_traits<PREC>::store* __restrict__ xin,
                                                typename prec_traits<PREC>::store* __restrict__ out, const geo4& g,
                                                int p, int nrhs, typename prec_traits<PREC>::real alpha,
-                                               typename prec_traits<PREC>::real beta, size_t h, int rhs) {
+                                               typename prec_traits<PREC>::real beta, size_t h, int rhs,
+                                               const typename prec_traits<PREC>::store* __restrict__ Cx = nullptr,
+                                               const typename prec_traits<PREC>::store* __restrict__ Cout = nullptr) {
   typedef typename prec_traits<PREC>::store S;
   typedef typename prec_traits<PREC>::real R;
   const size_t V = g.V, Vh = V / 2;
@@ -127,10 +139,16 @@ __device__ __forceinline__ void wilson_eo_site(const typename prec_traits<PREC>:
       cx<R> a = acc.c[i / 3][i % 3], b = x.c[i / 3][i % 3];
       acc.c[i / 3][i % 3] = {fma(beta, a.re, alpha * b.re), fma(beta, a.im, alpha * b.im)};
     }
+    if (CL && Cx) {
+      const spinor<R> cx_ = clover_mul<S, R>(Cx + site * 42, x);
+#pragma unroll
+      for (int i = 0; i < 12; ++i) acc.c[i / 3][i % 3] = acc.c[i / 3][i % 3] - cx_.c[i / 3][i % 3];
+    }
   } else {
 #pragma unroll
     for (int i = 0; i < 12; ++i) acc.c[i / 3][i % 3] = scale(beta, acc.c[i / 3][i % 3]);
   }
+  if (CL && Cout) acc = clover_mul<S, R>(Cout + site * 42, acc);
   store_spinor<S, R>(out, me, cs, acc);
 }
 

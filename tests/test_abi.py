@@ -74,3 +74,8 @@ def test_tune_table_roundtrip(tmp_path):
         lq.set_kernel_config(7)
     with pytest.raises(lq.LqcdError):
         lq.set_kernel_config(2, wg_per_cu=9)
+    with pytest.raises(lq.LqcdError):
+        lq.set_batch_kernel(3)
+    lq.set_batch_kernel(0)
+    with pytest.raises(lq.LqcdError):
+        lq.set_batch_grid(-1)

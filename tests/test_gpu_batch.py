@@ -20,7 +20,8 @@ def _l2(block):
 @pytest.mark.parametrize("prec", [lq.F64, lq.F32, lq.F16])
 @pytest.mark.parametrize("grid", [0, 1, 7])
 @pytest.mark.parametrize("kind", [1, 2])
-def test_uneven_batch_small(gpu_lib, prec, grid, kind):
+@pytest.mark.parametrize("dagger", [False, True])
+def test_uneven_batch_small(gpu_lib, prec, grid, kind, dagger):
     """Small lattices of different shapes and rhs counts (odd and even, so the
     pencil kernel mixes one and two rhs per work item); neither the kernel nor
     the persistent grid size (including a single workgroup, or the eight the
@@ -34,8 +35,8 @@ def test_uneven_batch_small(gpu_lib, prec, grid, kind):
         U = rounded(syn.gauge_field(dims, "near_identity", config=50 + k, eps=0.2 + 0.3 * k / 7), prec)
         psi = rounded(syn.spinor_block(dims, n, config=50 + k), prec)
         probs.append((to_dev(U, prec), to_dev(_l2(psi), prec), m0))
-        wants.append(dirac.apply_dw(U, psi, m0))
-    outs = lq.dirac_apply_batch(probs)
+        wants.append((dirac.apply_dw_dagger if dagger else dirac.apply_dw)(U, psi, m0))
+    outs = lq.dirac_apply_batch(probs, dagger=dagger)
     gpu_lib.set_batch_grid(0)
     gpu_lib.set_batch_kernel(0)
     from helpers import from_dev
