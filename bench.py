@@ -40,7 +40,7 @@ TUNE_FILE = os.path.join(ROOT, "paper_2601_05816_amd", "tune_mi355x.txt")
 # segments, nontemporal, wg_per_cu); reported only for the configuration the
 # counters were taken on.
 TRAFFIC = {
-    (3, 4, 4, 1, 1, 1): {"read_bytes": 16_949_914_000, "write_bytes": 6_442_458_000,
+    (3, 4, 4, 1, 1, 1): {"read_bytes": 16_760_687_000, "write_bytes": 6_442_452_000,
                          "profile": "profiles/wilson_full_pencil_32x32x32x64_nrhs16_f64.md"},
 }
 
@@ -160,6 +160,57 @@ def gmres_section(lq, U64, psi64, nrhs):
     return out
 
 
+def clover_section(lq, syn, U64, psi64, steps):
+    """The clover-improved operator D = D_W - C on the headline workload
+    (synthetic clover field, two Hermitian 6x6 blocks per site, scale 0.2):
+    full and Schur applies in FP64 and odd-even GMRES(30) to a true 1e-10,
+    FP64 against FP32 refinement."""
+    import torch
+
+    dev = U64.device
+    v = int(np.prod(DIMS))
+    t0 = time.time()
+    C = torch.from_numpy(syn.clover_field(DIMS, config=CONFIG, scale=0.2)).to(dev)
+    log(f"clover field generated ({time.time() - t0:.1f}s)")
+    out = {"lattice": list(DIMS), "nrhs": NRHS, "m0": M0, "clover_scale": 0.2}
+    eta = torch.empty_like(psi64)
+    t_full = timed(lambda: lq.dirac_apply_clover(U64, C, psi64, M0, layout=lq.LAYOUT2, out=eta), steps, 2)
+    nb = (36 + 42 + 24 * NRHS) * 16 * v  # links, clover field, in, out
+    Ci = lq.clover_inverse(C, M0, DIMS)
+    xe = psi64.reshape((v,) + tuple(psi64.shape[4:]))[: v // 2].contiguous()
+    ye = torch.empty_like(xe)
+    t_eo = timed(lambda: lq.dirac_apply_eo_clover(U64, C, Ci, xe, M0, layout=lq.LAYOUT2, out=ye), steps, 2)
+    out["apply_f64"] = {"full_ms": round(t_full, 4), "full_gbs": round(nb / t_full / 1e6, 1),
+                        # + 528 flop per site and rhs: two Hermitian 6x6 block products and the subtraction
+                        "full_gflops": round((FLOP_SITE_RHS + 528) * v * NRHS / t_full / 1e6, 1),
+                        "schur_ms": round(t_eo, 4), "kernel": "one (site, rhs) per work item"}
+    log(f"clover apply FP64 nrhs={NRHS}: full {t_full:.3f} ms ({nb / t_full / 1e6:.0f} GB/s), Schur {t_eo:.3f} ms")
+    del eta, ye, xe, Ci
+    torch.cuda.empty_cache()
+    b = psi64[..., :NRHS].contiguous()
+    sol = {}
+    for mode in ("f64", "ir-f32"):
+        torch.cuda.synchronize()
+        t = time.time()
+        x, st, rc = lq.gmres_solve_clover(U64, C, b, M0, layout=lq.LAYOUT2, restart=30, eo=True, mode=mode,
+                                          tol=1e-10, max_restarts=400, max_outer=60)
+        torch.cuda.synchronize()
+        dt = time.time() - t
+        rec = {"seconds": round(dt, 3), "status": int(rc), "converged": bool(st["converged"].all()),
+               "max_true_relres": float(st["true_relres"].max()), "iters_max": int(st["iters"].max())}
+        if mode != "f64":
+            d = (x - sol["f64"]).reshape(-1, NRHS)
+            rel = torch.linalg.vector_norm(d, dim=0) / torch.linalg.vector_norm(sol["f64"].reshape(-1, NRHS), dim=0)
+            rec["max_rel_diff_vs_f64"] = float(rel.max())
+        sol[mode] = x
+        out["gmres_" + mode.replace("-", "_")] = rec
+        log(f"clover GMRES {mode}: {json.dumps(rec)}")
+    out["speedup_ir_f32"] = round(out["gmres_f64"]["seconds"] / out["gmres_ir_f32"]["seconds"], 3)
+    del sol, C
+    torch.cuda.empty_cache()
+    return out
+
+
 def batch_section(lq, syn, steps):
     """The uneven eight-lattice batch (L = 8..24, T = 2L, eps_k = 0.2 + 0.3 k/7,
     1..32 rhs each, m0 = -0.05): the FP32 apply of all eight lattices in one
@@ -261,6 +312,54 @@ def autograd_section(lq, syn):
     return res
 
 
+def profile_only(args):
+    """One workload under a profiler: GPU-drawn inputs (timing does not depend
+    on the values), the kernel configurations of the tune file, `--steps`
+    launches after `--warmup`; prints one JSON line of launch times."""
+    import torch
+
+    import paper_2601_05816_amd as lq
+
+    lq.load()
+    if os.path.exists(args.tune_file):
+        lq.tune_load(args.tune_file)
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev).manual_seed(CONFIG)
+    v = int(np.prod(DIMS))
+    U = torch.randn((4,) + DIMS + (3, 3), dtype=torch.complex128, device=dev, generator=g)
+    out = {"mode": args.only, "lattice": list(DIMS), "steps": args.steps, "warmup": args.warmup}
+    if args.only == "sweep-f64":
+        pts = []
+        for n in (1, 4, 8, 16, 32, 64):  # dispatches: warmup + steps launches per point, in this order
+            psi = torch.randn(DIMS + (4, 3, n), dtype=torch.complex128, device=dev, generator=g)
+            eta = torch.empty_like(psi)
+            ms = timed(lambda: lq.dirac_apply(U, psi, M0, layout=lq.LAYOUT2, out=eta), args.steps, args.warmup)
+            pts.append({"nrhs": n, "ms": round(ms, 4)})
+            log(f"nrhs {n}: {ms:.4f} ms")
+            del psi, eta
+        out["points"] = pts
+    elif args.only == "schur-f64":
+        xe = torch.randn((v // 2, 4, 3, NRHS), dtype=torch.complex128, device=dev, generator=g)
+        ye = torch.empty_like(xe)
+        ms = timed(lambda: lq.dirac_apply_eo(U, xe, M0, layout=lq.LAYOUT2, out=ye), args.steps, args.warmup)
+        out.update(nrhs=NRHS, schur_ms=round(ms, 4))
+    else:  # the paper's fixed protocol: 100 iterations = 10 restarts of 10, odd-even, FP64
+        U.mul_(0.3)
+        b = torch.randn(DIMS + (4, 3, NRHS), dtype=torch.complex128, device=dev, generator=g)
+        kw = dict(restart=10, max_restarts=10, eo=True, fixed_iters=True)
+        work = torch.empty(lq.gmres_workspace_bytes(DIMS, NRHS, lq.solver_params(**kw)), dtype=torch.uint8,
+                           device=dev)
+        out["seconds"] = []
+        for i in range(args.warmup + args.steps):
+            torch.cuda.synchronize()
+            t = time.time()
+            lq.gmres_solve(U, b, M0, layout=lq.LAYOUT2, work=work, **kw)
+            torch.cuda.synchronize()
+            out["seconds"].append(round(time.time() - t, 3))
+            log(f"fixed 100 iterations ({'warmup' if i < args.warmup else 'timed'}): {out['seconds'][-1]} s")
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -273,6 +372,7 @@ def main():
                          "recipe; for profiling runs, where values do not matter")
     ap.add_argument("--no-gmres", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven eight-lattice batch")
+    ap.add_argument("--no-clover", action="store_true", help="skip the clover-improved operator")
     ap.add_argument("--no-autograd", action="store_true", help="skip the differentiation timing")
     ap.add_argument("--gmres-nrhs", type=int, default=NRHS)
     ap.add_argument("--variant", type=int, default=0, help="Wilson kernel: 0 auto, 1 site, 2 pencil")
@@ -284,7 +384,14 @@ def main():
                     help="kernel configurations measured by the autotuner on MI355X (used when present)")
     ap.add_argument("--retune", action="store_true", help="ignore the tune file and autotune every apply")
     ap.add_argument("--save-tune", default="", help="write the autotuner's table here at the end")
+    ap.add_argument("--only", choices=["sweep-f64", "schur-f64", "gmres-fixed"], default="",
+                    help="profiling mode: run one workload only (GPU-drawn inputs, tune file), print its times")
     args = ap.parse_args()
+    if args.only:
+        if args.gpus != 1:
+            sys.exit(2)
+        profile_only(args)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the multi-rhs apply and GMRES are single-device here "
               "(rhs or lattice sharding across GPUs is not built)", file=sys.stderr)
@@ -432,7 +539,9 @@ def main():
     if not args.no_gmres:
         result["gmres"] = gmres_section(lq, U64, psi64, args.gmres_nrhs)
 
-    # ------------------------------------------- uneven batch, differentiation
+    # ------------------------------- clover term, uneven batch, differentiation
+    if not args.no_clover:
+        result["clover"] = clover_section(lq, syn, U64, psi64, max(5, args.steps // 5))
     if not args.no_batch:
         result["batch"] = batch_section(lq, syn, max(5, args.steps // 5))
     if not args.no_autograd:

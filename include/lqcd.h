@@ -150,7 +150,7 @@ int dirac_apply_eo(const lqcd_lattice* lat, const void* U, const void* psi_e, vo
  * is stored as its 6 diagonal entries (only the real parts are read) followed
  * by the 15 entries above the diagonal row by row ((0,1), (0,2), ..., (4,5)).
  *
- * eta = D psi = D_W psi - C psi (Algorithm 1, line 1 with C), or with
+ * eta = D psi = D_W psi - C psi (Algorithm 1 with C), or with
  * flags = LQCD_DAGGER eta = D^dagger psi = D_W^dagger psi - C psi (C is
  * Hermitian).  Arguments, layouts and errors as dirac_apply. */
 int dirac_apply_clover(const lqcd_lattice* lat, const void* U, const void* C, const void* psi, void* eta, int nrhs,

@@ -1,5 +1,5 @@
 // Batched BLAS-1 on rhs-innermost vectors for the Arnoldi process of
-// Algorithm 2 (lines 2-4 and the final update).
+// Algorithm 2 (the Arnoldi step and the final update of x).
 //
 // Every vector is [nrow][nrhs] complex with nrow = 12 x (number of sites), so
 // element e = row * nrhs + rhs.  Reductions are per rhs ("batched dot

@@ -1,5 +1,5 @@
 // The improved operator D = D_W - C with a clover field (Sec. III-A.1, the
-// equation after eq. (1); Algorithm 1 line 1 applies C with the diagonal):
+// equation after eq. (1); Algorithm 1 applies C together with the diagonal):
 // the full apply, the site-local inverse of D_oo = (4 + m0) - C_o, and the
 // odd-even Schur complement S = D_ee - D_eo D_oo^{-1} D_oe with a
 // site-dependent D_oo.  One (site, rhs) per work item, the body of site.h

@@ -3,7 +3,7 @@
 // FP16-storage inner solver.
 //
 // Every rhs runs its own GMRES(m) in lock-step with the others (batched, not
-// block Krylov).  One Arnoldi step for all rhs (Algorithm 2, lines 4-5):
+// block Krylov).  One Arnoldi step for all rhs (Algorithm 2):
 //   w = A v_j                      Wilson kernels on the whole block
 //   h_kj = <v_k, w>, k <= j        classical Gram-Schmidt: all dots of the step
 //                                  in passes of DOT_KB vectors over w
@@ -12,8 +12,8 @@
 //   v_{j+1} = w / |w|
 // A rhs whose relnorm falls below tol (or whose Krylov space closes) stops
 // taking steps (its lanes are masked) while the others continue; the cycle
-// ends when none is left ("max over rhs" exit, line 6).  At the end of a cycle
-// each rhs solves its small triangular system and updates x (line 9).  The
+// ends when none is left (the "max over rhs" exit of Algorithm 2).  At the end of a cycle
+// each rhs solves its small triangular system and updates x.  The
 // next cycle starts from the true residual b - A x.
 #include <math.h>
 #include <string.h>

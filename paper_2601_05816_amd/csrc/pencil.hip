@@ -3,8 +3,8 @@
 // A work item owns one spatial column (z, y, x) and one rhs and walks a
 // segment of t values.  The +t neighbour loaded for site t is the centre of
 // site t+1 and the -t neighbour of site t+2, so each spinor along t is read
-// once and its three uses (Algorithm 1: the diagonal term of line 1 and the
-// two time-direction hops of lines 7 and 9) are served from registers; only
+// once and its three uses (Algorithm 1: the diagonal term and the two
+// time-direction hops) are served from registers; only
 // the six spatial neighbours go through the caches.  The time link U_0(x) is
 // shared between the +t hop of site t and the -t hop of site t+1.
 //

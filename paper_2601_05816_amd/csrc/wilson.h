@@ -3,7 +3,7 @@
 // For one output site x and one rhs the kernels accumulate
 //   hop(x) = sum_mu [ (1 - s gamma_mu) U_mu(x) psi(x+mu) + (1 + s gamma_mu) U_mu(x-mu)^dag psi(x-mu) ]
 // with s = +1 for D and s = -1 for D^dagger (the adjoint of each hopping term
-// flips the sign of gamma_mu), the quantity summed in Algorithm 1, lines 7 and 9.
+// flips the sign of gamma_mu), the quantity summed over directions in Algorithm 1.
 // Each term is evaluated on a half spinor, as Sec. III-A.1 describes for the
 // projected vectors lambda_mu and chi_mu: with psi = (u; d) in upper/lower
 // spin pairs and gamma_mu = [[0, B], [B^dag, 0]],
