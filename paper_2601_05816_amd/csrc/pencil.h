@@ -24,7 +24,8 @@ __device__ __forceinline__ bool pencil_item(const pencil_geo& pg, int nrhs, int&
                                             int& t0, unsigned b) {
   const unsigned k = b & 7u, i = b >> 3;
   const unsigned u = i / pg.bpt, q = i % pg.bpt;
-  const unsigned grp = u / pg.nseg, seg = u % pg.nseg;
+  const unsigned ngrp = (unsigned)(pg.ntiles + 7) / 8u;
+  const unsigned seg = u / ngrp, grp = u % ngrp;  // segment-major: tile groups of one t segment run back to back
   const unsigned tile = grp * 8u + k;
   if (tile >= (unsigned)pg.ntiles) return false;
   const unsigned CT = (unsigned)pg.TX * pg.TY * pg.TZ;

@@ -13,9 +13,12 @@
 // group" at the same position of the dispatch order therefore work on eight
 // adjacent tiles at the same time, so that a tile's spatial halo is the
 // interior of a tile that another XCD reads in the same time step.  Within
-// an XCD the tile's workgroups cover the tile's columns and rhs.  The
-// mapping is a bijection for any tile shape; the tile shape and the number
-// of t segments only change locality.
+// an XCD the tile's workgroups cover the tile's columns and rhs.  With
+// several t segments the order is segment-major: all tile groups of segment
+// 0, then of segment 1, ..., so a tile group's z halo at the same t range was
+// read by the previous group shortly before (an Infinity Cache hit rather
+// than an HBM read).  The mapping is a bijection for any tile shape; the tile
+// shape and the number of t segments only change locality.
 #include "kernels.h"
 #include "pencil_kernels.h"
 
@@ -34,10 +37,13 @@ __global__ __launch_bounds__(256) void k_wilson_full_p(const typename prec_trait
 
 // ------------------------------------------- full lattice, links via LDS
 // Same pencil walk; the links of a time step are fetched once per wavefront
-// with coalesced loads into a wave-private LDS slice and read from there by
-// all lanes of a column (the rhs that share the column), instead of one
-// vector-memory load per lane.  Rhs-fastest layouts only; NCW bounds the
-// number of columns one wavefront touches (64 / nrhs + 1).
+// with coalesced loads (one complex number per lane and load) into a
+// wave-private LDS slice and read from there by all lanes of a column (the
+// rhs that share the column), instead of one vector-memory load per lane and
+// link element.  The slices are double-buffered and the loads of step t+1 are
+// issued before step t is computed, so their latency overlaps the step.
+// Rhs-fastest layouts only; NCW bounds the number of columns one wavefront
+// touches (64 / nrhs + 1).
 // Link slots per column and step: 0 U_0(x), 1..3 U_mu(x) (mu = 1 z, 2 y, 3 x),
 // 4..6 U_mu(x - mu).
 template <int PREC, int LAYOUT, int SG, int NCW>
@@ -49,11 +55,14 @@ __global__ __launch_bounds__(256) void k_wilson_full_pl(const typename prec_trai
                                                         typename prec_traits<PREC>::real hopc) {
   typedef typename prec_traits<PREC>::store S;
   typedef typename prec_traits<PREC>::real R;
-  __shared__ S lds_all[4][NCW * 63];
+  constexpr int NEL = NCW * 63;            // link elements of a wavefront and step
+  constexpr int NE = (NEL + 63) / 64;      // per lane
+  __shared__ S lds_all[4][2][NEL];
   const unsigned b = blockIdx.x;
   const unsigned k8 = b & 7u, ib = b >> 3;
   const unsigned u = ib / pg.bpt, q = ib % pg.bpt;
-  const unsigned grp = u / pg.nseg, seg = u % pg.nseg;
+  const unsigned ngrp = (unsigned)(pg.ntiles + 7) / 8u;
+  const unsigned seg = u / ngrp, grp = u % ngrp;  // segment-major: tile groups of one t segment run back to back
   const unsigned tile = grp * 8u + k8;
   if (tile >= (unsigned)pg.ntiles) return;  // whole workgroup idle
   const unsigned CT = (unsigned)pg.TX * pg.TY * pg.TZ;
@@ -69,7 +78,6 @@ __global__ __launch_bounds__(256) void k_wilson_full_pl(const typename prec_trai
   const unsigned col = active ? tin / nrhs : colw0;
   const int rhs = (int)(tin % nrhs);
   const int cl = (int)(col - colw0);
-  S* lds = lds_all[wave];
 
   const int T = pg.n[0], NZ = pg.n[1], NY = pg.n[2], NX = pg.n[3];
   const int tx = tile % pg.NTX, ty = (tile / pg.NTX) % pg.NTY, tz = tile / (pg.NTX * pg.NTY);
@@ -91,11 +99,15 @@ __global__ __launch_bounds__(256) void k_wilson_full_pl(const typename prec_trai
   const size_t czb = c0 + (size_t)((z > 0 ? z - 1 : NZ - 1) - z) * NY * NX;
   const S* U0 = U;
 
-  // stage the 7 links of every column of this wavefront at time t
-  auto stage = [&](int t) {
-    const size_t toff = (size_t)t * S0;
-    const int nel = ncw * 63;
-    for (int e = (int)lane; e < nel; e += 64) {
+  // this lane's link elements: source offset at t = 0 and LDS slot, computed once
+  size_t goff[NE];
+  int lidx[NE];
+#pragma unroll
+  for (int k = 0; k < NE; ++k) {
+    const int e = (int)lane + 64 * k;
+    lidx[k] = -1;
+    goff[k] = 0;
+    if (e < ncw * 63) {
       const int slot = e / (9 * ncw);
       const int rem = e - slot * 9 * ncw;
       const int c = rem / 9, kk = rem - c * 9;
@@ -109,16 +121,30 @@ __global__ __launch_bounds__(256) void k_wilson_full_pl(const typename prec_trai
         else if (mu == 2) sc += (size_t)((yy > 0 ? yy - 1 : NY - 1) - yy) * NX;
         else sc += (size_t)((xx > 0 ? xx - 1 : NX - 1) - xx);
       }
-      lds[(c * 7 + slot) * 9 + kk] = U[((size_t)mu * V + toff + sc) * 9 + kk];
+      goff[k] = ((size_t)mu * V + sc) * 9 + kk;
+      lidx[k] = (c * 7 + slot) * 9 + kk;
     }
+  }
+  S lr[NE];
+  auto fetch = [&](int t) {
+    const size_t toff9 = (size_t)t * S0 * 9;
+#pragma unroll
+    for (int k = 0; k < NE; ++k)
+      if (lidx[k] >= 0) lr[k] = U[goff[k] + toff9];
+  };
+  auto put = [&](int buf) {
+    S* lds = lds_all[wave][buf];
+#pragma unroll
+    for (int k = 0; k < NE; ++k)
+      if (lidx[k] >= 0) lds[lidx[k]] = lr[k];
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   };
-  const S* L = lds + cl * 7 * 9;
 
   spinor<R> acc;
   half_spinor<R> hplus;
+  fetch(t0);
   {
     const int tm = t0 > 0 ? t0 - 1 : T - 1;
     const size_t sm = (size_t)tm * S0 + c0;
@@ -135,11 +161,13 @@ __global__ __launch_bounds__(256) void k_wilson_full_pl(const typename prec_trai
     }
     hplus = project<0, SG>(p0);
   }
+  put(0);
   for (int it = 0; it < pg.Lt; ++it) {
     const int t = t0 + it;
     const size_t toff = (size_t)t * S0;
     const size_t site = toff + c0;
-    stage(t);
+    const S* L = lds_all[wave][it & 1] + cl * 7 * 9;
+    if (it + 1 < pg.Lt) fetch(t + 1);
     {
       spinor<R> p = load_spinor<S, R>(psi, blk<LAYOUT>::base(toff + cxf, rhs, V, nrhs), cs);
       add_hop<3, -SG, false, S, R>(acc, p, L + 3 * 9, hopc);
@@ -177,8 +205,8 @@ __global__ __launch_bounds__(256) void k_wilson_full_pl(const typename prec_trai
       for (int i = 0; i < 12; ++i) acc.c[i / 3][i % 3] = scale(diag, p1.c[i / 3][i % 3]);
       reconstruct<0, SG>(acc, hscale(hopc, colour_mul<true>(L, hplus)));
       hplus = project<0, SG>(p1);
+      put((it + 1) & 1);
     }
-    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -223,7 +251,7 @@ static hipError_t launch_full_p(const lqcd_lattice* lat, const void* U, const vo
   size_t dyn = 0;
   if (LAYOUT != LQCD_RHS_OUTER && c.variant == 2 && nrhs >= 4) {
     const int ncw = nrhs >= 16 ? 5 : (nrhs >= 8 ? 9 : 17);
-    if (!occupancy_lds(c.occ, 4 * (size_t)ncw * 63 * sizeof(S), &dyn)) return hipErrorInvalidConfiguration;
+    if (!occupancy_lds(c.occ, 8 * (size_t)ncw * 63 * sizeof(S), &dyn)) return hipErrorInvalidConfiguration;
     if (nrhs >= 16)
       hipLaunchKernelGGL((k_wilson_full_pl<PREC, LAYOUT, SG, 5>), grid, blk, dyn, s, (const S*)U, (const S*)psi,
                          (S*)eta, pg, nrhs, (R)diag, (R)hopc);

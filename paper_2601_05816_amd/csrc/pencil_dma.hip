@@ -151,7 +151,8 @@ __global__ __launch_bounds__(256) void k_wilson_full_dma(const double2* __restri
   const unsigned b = blockIdx.x;
   const unsigned k8 = b & 7u, ib = b >> 3;
   const unsigned u = ib / pg.bpt, q = ib % pg.bpt;
-  const unsigned grp = u / pg.nseg, seg = u % pg.nseg;
+  const unsigned ngrp = (unsigned)(pg.ntiles + 7) / 8u;
+  const unsigned seg = u / ngrp, grp = u % ngrp;  // segment-major: tile groups of one t segment run back to back
   const unsigned tile = grp * 8u + k8;
   if (tile >= (unsigned)pg.ntiles) return;  // whole workgroup idle
   const unsigned CT = (unsigned)pg.TX * pg.TY * pg.TZ;
