@@ -40,7 +40,7 @@ TUNE_FILE = os.path.join(ROOT, "paper_2601_05816_amd", "tune_mi355x.txt")
 # segments, nontemporal, wg_per_cu); reported only for the configuration the
 # counters were taken on.
 TRAFFIC = {
-    (3, 4, 4, 1, 1, 1): {"read_bytes": 16_760_687_000, "write_bytes": 6_442_452_000,
+    (3, 4, 4, 1, 1, 1): {"read_bytes": 16_797_550_000, "write_bytes": 6_442_461_000,
                          "profile": "profiles/wilson_full_pencil_32x32x32x64_nrhs16_f64.md"},
 }
 
@@ -51,8 +51,11 @@ def bytes_full(v, nrhs, esz):
 
 
 def bytes_schur_two_pass(v, nrhs, esz):
-    """Two hopping passes over half lattices: links twice, in/tmp/out spinors."""
-    return (2 * 36 + 60 * nrhs) * esz * (v // 2)
+    """Two hopping passes over half lattices.  Each pass reads every link once
+    (8 links of 9 entries per output site = 72 per even site) and its input
+    half spinor block and writes its output; the second also reads the axpy
+    input: per even site 2 x 72 links + (12 + 12) + (12 + 12 + 12) nrhs."""
+    return (2 * 72 + 60 * nrhs) * esz * (v // 2)
 
 
 def table_entry(path, kind, dims, nrhs, prec, layout):
