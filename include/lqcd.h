@@ -299,6 +299,30 @@ size_t gmres_workspace_bytes_batch(int nprob, const lqcd_problem* probs, const l
 int gmres_solve_batch(int nprob, const lqcd_problem* probs, const lqcd_solver_params* params, void* work,
                       size_t work_bytes, lqcd_rhs_stats* stats, void* stream);
 
+/* Block GMRES: all rhs of the block expand ONE block Krylov subspace
+ * K_k(A, R0) = span{R0, A R0, ..., A^{k-1} R0} of the residual block R0 (the
+ * block Krylov space of Sec. II that the paper contrasts with its batched
+ * solver), and every rhs minimises its residual over that shared space.
+ * Restarted block GMRES(m): thin QR of the residual block (Cholesky QR), per
+ * step the block apply W = A V_j, block classical Gram-Schmidt
+ * H_ij = V_i^H W, W -= V_i H_ij (tall-skinny products on the FP64 matrix
+ * cores), Cholesky QR W = V_{j+1} H_{j+1,j}, and the block Hessenberg
+ * least-squares problem by complex Givens rotations on the device.  A cycle
+ * ends after `restart` steps, when every rhs is below tol, or when the new
+ * block is numerically rank deficient; rhs already converged at a restart
+ * are left out of the next cycle.
+ * Arguments as gmres_solve, with 1 <= nrhs <= LQCD_BLOCK_MAX_RHS, mode 0
+ * (FP64) and use_graph 0 only (LQCD_ERR_ARG otherwise); eo, dagger,
+ * fixed_iters, x_is_guess, tol and max_restarts as there.  stats[i].iters
+ * counts the block steps during which rhs i was active.  Workspace from
+ * block_gmres_workspace_bytes (0 for invalid arguments).  Synchronises
+ * `stream` once per block step and at every restart. */
+#define LQCD_BLOCK_MAX_RHS 16
+size_t block_gmres_workspace_bytes(const lqcd_lattice* lat, int nrhs, const lqcd_solver_params* p);
+int block_gmres_solve(const lqcd_lattice* lat, const void* U, const void* b, void* x, int nrhs, double m0,
+                      int layout, const lqcd_solver_params* params, void* work, size_t work_bytes,
+                      lqcd_rhs_stats* stats, void* stream);
+
 /* Gradient of a real loss with respect to the links through y = D psi
  * (differentiation of the Sec. III-A.1 operator): with dL = Re <g, dy> and
  * gradients of complex entries taken as dL/dRe + i dL/dIm,

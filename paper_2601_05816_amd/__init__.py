@@ -132,6 +132,11 @@ def load():
         lib.gmres_solve_batch.argtypes = [i32, ctypes.POINTER(Problem), ctypes.POINTER(SolverParams), vp,
                                           ctypes.c_size_t, ctypes.POINTER(RhsStats), vp]
         lib.gmres_solve_batch.restype = i32
+        lib.block_gmres_workspace_bytes.argtypes = [lp, i32, ctypes.POINTER(SolverParams)]
+        lib.block_gmres_workspace_bytes.restype = ctypes.c_size_t
+        lib.block_gmres_solve.argtypes = [lp, vp, vp, vp, i32, dbl, i32, ctypes.POINTER(SolverParams), vp,
+                                          ctypes.c_size_t, ctypes.POINTER(RhsStats), vp]
+        lib.block_gmres_solve.restype = i32
         lib.link_force.argtypes = [lp, vp, vp, vp, vp, i32, i32, dbl, i32, vp]
         lib.link_force.restype = i32
         lib.block_dot.argtypes = [lp, vp, vp, i32, i32, vp, vp]
@@ -383,6 +388,39 @@ def gmres_solve(U, b, m0, layout=LAYOUT2, x0=None, work=None, **kw):
     st = (RhsStats * nrhs)()
     rc = _check(load().gmres_solve(ctypes.byref(_lattice(dims)), U.data_ptr(), b.data_ptr(), x.data_ptr(), nrhs,
                                    float(m0), layout, ctypes.byref(p), work.data_ptr(), work.numel(), st, _stream()))
+    stats = {k: np.array([getattr(s, k) for s in st]) for k, _ in RhsStats._fields_}
+    return x, stats, rc
+
+
+BLOCK_MAX_RHS = 16
+
+
+def block_gmres_workspace_bytes(dims, nrhs, params):
+    return int(load().block_gmres_workspace_bytes(ctypes.byref(_lattice(dims)), int(nrhs), ctypes.byref(params)))
+
+
+def block_gmres_solve(U, b, m0, layout=LAYOUT2, x0=None, work=None, **kw):
+    """x = D^-1 b with block GMRES: all rhs of b (at most BLOCK_MAX_RHS) share
+    one block Krylov space.  Same keywords (mode must be "f64", no graphs) and
+    return value as gmres_solve; stats["iters"] counts block steps."""
+    import torch
+
+    if U.dtype != torch.complex128 or b.dtype != torch.complex128:
+        raise TypeError("block_gmres_solve takes complex128 U and b")
+    dims = _dims_of_links(U, F64)
+    nrhs, sdims = _nrhs_of(b, F64, layout, 4)
+    if tuple(sdims) != tuple(dims):
+        raise ValueError(f"source lattice {sdims} does not match gauge lattice {dims}")
+    p = solver_params(x_is_guess=x0 is not None, **kw)
+    x = x0.clone() if x0 is not None else torch.empty_like(b)
+    need = block_gmres_workspace_bytes(dims, nrhs, p)
+    if work is None or work.numel() < need:
+        work = torch.empty(max(need, 1), dtype=torch.uint8, device=b.device)
+    _check_device(U, b, x, work)
+    st = (RhsStats * nrhs)()
+    rc = _check(load().block_gmres_solve(ctypes.byref(_lattice(dims)), U.data_ptr(), b.data_ptr(), x.data_ptr(),
+                                         nrhs, float(m0), layout, ctypes.byref(p), work.data_ptr(), work.numel(), st,
+                                         _stream()))
     stats = {k: np.array([getattr(s, k) for s in st]) for k, _ in RhsStats._fields_}
     return x, stats, rc
 

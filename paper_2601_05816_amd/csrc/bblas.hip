@@ -1,0 +1,170 @@
+// Tall-skinny block kernels of block GMRES on rhs-innermost FP64 blocks
+// [nrows][b] (b <= 16 right-hand sides per row): the block Gram products
+// H_k = V_k^H W and the block combinations out = alpha Y + beta sum_k V_k C_k
+// with b x b coefficient blocks C_k.  These are dense contractions (K =
+// nrows for the Gram products, K = b for the combinations), so they run on
+// the FP64 matrix cores: v_mfma_f64_16x16x4f64 with a complex product split
+// into four real products.  Operand layouts of that instruction (lane l of a
+// wavefront): A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k, and D[i][j]
+// in lane j + 16 (i % 4), element i / 4 (checked on the device).
+#include <hip/hip_runtime.h>
+
+#include "blas.h"
+#include "common.h"
+
+namespace lq {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef cx<double> zd;
+
+__device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// parts[p][k][i b + j] = sum over the rows of part p of conj(V_k[row][i]) W[row][j]
+// for k < K; p = 4 * block + wave.  A wavefront takes four rows per step:
+// lane l loads element (row0 + l / 16, l % 16) of V_k and of W, i.e. the A
+// operand V_k^T (i = column of V, k = row) and the B operand W.
+template <int KB>
+__global__ __launch_bounds__(256) void k_bgram(const zd* __restrict__ V, size_t vstride, int K,
+                                               const zd* __restrict__ W, size_t nrows, int b, size_t rows_per_blk,
+                                               zd* __restrict__ parts) {
+  const int l = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = l & 15, kq = l >> 4;
+  const size_t r0 = (size_t)blockIdx.x * rows_per_blk;
+  const size_t r1 = r0 + rows_per_blk < nrows ? r0 + rows_per_blk : nrows;
+  d4 hr[KB], hi[KB];
+#pragma unroll
+  for (int k = 0; k < KB; ++k) {
+    hr[k] = d4{0.0, 0.0, 0.0, 0.0};
+    hi[k] = d4{0.0, 0.0, 0.0, 0.0};
+  }
+  for (size_t q = r0 + 4 * (size_t)wave; q < r1; q += 16) {
+    const size_t row = q + kq;
+    const bool ok = row < r1 && col < b;
+    const zd w = ok ? W[row * b + col] : zd{0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      if (k < K) {
+        const zd v = ok ? V[(size_t)k * vstride + row * b + col] : zd{0.0, 0.0};
+        // conj(v) w = (vr wr + vi wi) + i (vr wi - vi wr)
+        hr[k] = mfma(v.re, w.re, hr[k]);
+        hr[k] = mfma(v.im, w.im, hr[k]);
+        hi[k] = mfma(v.re, w.im, hi[k]);
+        hi[k] = mfma(-v.im, w.re, hi[k]);
+      }
+    }
+  }
+  const size_t bb = (size_t)b * b;
+  zd* out = parts + ((size_t)blockIdx.x * 4 + wave) * K * bb;
+#pragma unroll
+  for (int k = 0; k < KB; ++k) {
+    if (k < K) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = kq + 4 * v;
+        if (i < b && col < b) out[(size_t)k * bb + (size_t)i * b + col] = zd{hr[k][v], hi[k][v]};
+      }
+    }
+  }
+}
+
+// out[row][c] = alpha Y[row][c] + beta sum_k sum_r V_k[row][r] C_k[r][c]
+// (Y is not read when alpha = 0; out may alias Y or V_0: every wavefront
+// reads its 16-row tile completely before it writes it).  A wavefront works
+// on 16 rows: the tile of V_k is staged in LDS (coalesced loads) and read
+// back as the A operand (i = row, k = r), the coefficients are the B
+// operand (k = r, j = c).
+template <int KB>
+__global__ __launch_bounds__(256) void k_bgemm(zd* out, const zd* Y, double alpha, double beta, const zd* V,
+                                               size_t vstride, int K, const zd* __restrict__ C, size_t nrows, int b) {
+  __shared__ zd tile[4][256];
+  const int l = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = l & 15, kq = l >> 4;
+  const size_t bb = (size_t)b * b;
+  zd cb[KB][4];  // C_k[r0 + kq][col] for r0 = 0, 4, 8, 12
+#pragma unroll
+  for (int k = 0; k < KB; ++k)
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int r = 4 * s + kq;
+      cb[k][s] = (k < K && r < b && col < b) ? C[(size_t)k * bb + (size_t)r * b + col] : zd{0.0, 0.0};
+    }
+  zd* sh = tile[wave];
+  const size_t ntiles = (nrows + 15) / 16;
+  for (size_t t = (size_t)blockIdx.x * 4 + wave; t < ntiles; t += (size_t)gridDim.x * 4) {
+    const size_t t0 = t * 16;
+    const size_t lim = (nrows - t0 < 16 ? nrows - t0 : 16) * (size_t)b;
+    d4 dr = {0.0, 0.0, 0.0, 0.0}, di = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      if (k < K) {
+        const zd* src = V + (size_t)k * vstride + t0 * b;
+        for (int e = l; e < 16 * b; e += 64) sh[e] = (size_t)e < lim ? src[e] : zd{0.0, 0.0};
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int r = 4 * s + kq;
+          if (4 * s < b) {  // uniform: skip steps past the last coefficient row
+            const zd a = r < b ? sh[col * b + r] : zd{0.0, 0.0};
+            const zd c = cb[k][s];
+            // a c = (ar cr - ai ci) + i (ar ci + ai cr)
+            dr = mfma(a.re, c.re, dr);
+            dr = mfma(-a.im, c.im, dr);
+            di = mfma(a.re, c.im, di);
+            di = mfma(a.im, c.re, di);
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const size_t row = t0 + kq + 4 * v;
+      if (row < nrows && col < b) {
+        const size_t e = row * b + col;
+        zd o = {beta * dr[v], beta * di[v]};
+        if (alpha != 0.0) {
+          const zd y = Y[e];
+          o.re += alpha * y.re;
+          o.im += alpha * y.im;
+        }
+        out[e] = o;
+      }
+    }
+  }
+}
+
+unsigned bgram_blocks(size_t nrows) {
+  size_t n = (nrows + 255) / 256;
+  if (n > 1024) n = 1024;
+  return n < 1 ? 1u : (unsigned)n;
+}
+
+hipError_t bgram_parts(const void* V, size_t vstride, int K, const void* W, size_t nrows, int b, void* parts,
+                       unsigned nblk, hipStream_t s) {
+  if (b < 1 || b > 16 || K < 1 || K > BG_KB) return hipErrorInvalidValue;
+  size_t rpb = (nrows + nblk - 1) / nblk;
+  rpb = (rpb + 15) & ~(size_t)15;
+  hipLaunchKernelGGL((k_bgram<BG_KB>), dim3(nblk), dim3(256), 0, s, (const zd*)V, vstride, K, (const zd*)W, nrows, b,
+                     rpb, (zd*)parts);
+  return hipGetLastError();
+}
+
+hipError_t bgemm(void* out, const void* Y, double alpha, double beta, const void* V, size_t vstride, int K,
+                 const void* C, size_t nrows, int b, hipStream_t s) {
+  if (b < 1 || b > 16 || K < 0 || K > BG_KB) return hipErrorInvalidValue;
+  const size_t ntiles = (nrows + 15) / 16;
+  size_t grid = (ntiles + 3) / 4;
+  if (grid > 2048) grid = 2048;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL((k_bgemm<BG_KB>), dim3((unsigned)grid), dim3(256), 0, s, (zd*)out, (const zd*)Y, alpha, beta,
+                     (const zd*)V, vstride, K, (const zd*)C, nrows, b);
+  return hipGetLastError();
+}
+
+}  // namespace lq

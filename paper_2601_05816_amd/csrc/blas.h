@@ -34,6 +34,18 @@ hipError_t convert_links(const void* in, int pout, void* out, size_t n, hipStrea
 hipError_t pack(int layout, bool to_internal, void* abi, void* ie, void* io, const int* dims, int nrhs, int eo,
                 hipStream_t s);
 
+// Block kernels of block GMRES (bblas.hip), FP64 blocks [nrows][b], b <= 16,
+// on the FP64 matrix cores.  bgram_parts writes 4 * nblk partial sums of the
+// K Gram blocks V_k^H W (K <= BG_KB, each b x b, row-major) for
+// reduce_parts(parts, 4 * nblk, K, b * b, ...); nblk = bgram_blocks(nrows).
+// bgemm: out = alpha Y + beta sum_k V_k C_k, K <= BG_KB coefficient blocks.
+constexpr int BG_KB = 4;
+unsigned bgram_blocks(size_t nrows);
+hipError_t bgram_parts(const void* V, size_t vstride, int K, const void* W, size_t nrows, int b, void* parts,
+                       unsigned nblk, hipStream_t s);
+hipError_t bgemm(void* out, const void* Y, double alpha, double beta, const void* V, size_t vstride, int K,
+                 const void* C, size_t nrows, int b, hipStream_t s);
+
 // 16-byte-per-lane variants for FP32 / FP16 bases (blasv.hip); the scalar
 // launchers above dispatch to them when vec_width(prec, nrhs) > 1.
 int vec_width(int prec, int nrhs);

@@ -163,6 +163,208 @@ __global__ void k_zero_mask(int nrhs, const double* __restrict__ bref, double* _
   if (r < nrhs) f[r] = bref[r] > 0.0 ? 1.0 : 0.0;
 }
 
+
+// ------------------------------------------------------------ block GMRES
+// All rhs of one lattice expand one block Krylov space K_k(A, R0) (Sec. II);
+// a block of b <= 16 rhs is an nrows x b matrix (the rhs-innermost layout).
+// Columns that have converged at the start of a cycle are zeroed and carried
+// as identity pivots, which decouples them exactly (their least-squares
+// coefficients are zero), so the block shrinks without repacking.
+
+// Cycle start: active columns (|r_q| > tol |b_q|; with a fixed iteration
+// count every nonzero source) and factors 1 / 0 that zero the others.
+__global__ void k_bstart(int b, const zd* __restrict__ nrm, const double* __restrict__ bref, double tol, int fixed,
+                         int* __restrict__ act, double* __restrict__ f, int* __restrict__ flags) {
+  if (threadIdx.x || blockIdx.x) return;
+  int n = 0, bad = 0;
+  for (int q = 0; q < b; ++q) {
+    const double r = sqrt(nrm[q].re);
+    if (!isfinite(r)) bad = 1;
+    const bool a = isfinite(r) && bref[q] > 0.0 && r > 0.0 && (fixed || r > tol * bref[q]);
+    act[q] = a ? 1 : 0;
+    f[q] = a ? 1.0 : 0.0;
+    n += a;
+  }
+  flags[0] = n;
+  flags[1] = bad;
+}
+
+// G = R^H R for the Gram block G of the active columns (R upper triangular,
+// unit rows and columns for the inactive ones) and Rinv = R^-1.  A pivot at
+// or below 1e-24 of the largest diagonal entry of G (a diagonal entry of R
+// at or below 1e-12 of the largest column norm) marks the block numerically
+// rank deficient: *bad = 1, that pivot's row is left zero and Rinv unset.
+__global__ void k_bchol(int b, const int* __restrict__ act, const zd* __restrict__ G, zd* __restrict__ R,
+                        zd* __restrict__ Rinv, int* __restrict__ bad) {
+  if (threadIdx.x || blockIdx.x) return;
+  double gmax = 0.0;
+  for (int q = 0; q < b; ++q)
+    if (act[q] && G[q * b + q].re > gmax) gmax = G[q * b + q].re;
+  for (int i = 0; i < b * b; ++i) R[i] = {0.0, 0.0};
+  int deficient = 0;
+  for (int q = 0; q < b; ++q) {
+    if (!act[q]) {
+      R[q * b + q] = {1.0, 0.0};
+      continue;
+    }
+    double d = G[q * b + q].re;
+    for (int p = 0; p < q; ++p) d -= R[p * b + q].re * R[p * b + q].re + R[p * b + q].im * R[p * b + q].im;
+    if (!(d > 1e-24 * gmax)) {
+      deficient = 1;
+      R[q * b + q] = {d > 0.0 ? sqrt(d) : 0.0, 0.0};
+      continue;
+    }
+    const double rq = sqrt(d);
+    R[q * b + q] = {rq, 0.0};
+    for (int c = q + 1; c < b; ++c) {
+      if (!act[c]) continue;
+      zd z = G[q * b + c];
+      for (int p = 0; p < q; ++p) {  // z -= conj(R[p][q]) R[p][c]
+        const zd u = R[p * b + q], v = R[p * b + c];
+        z.re -= u.re * v.re + u.im * v.im;
+        z.im -= u.re * v.im - u.im * v.re;
+      }
+      R[q * b + c] = {z.re / rq, z.im / rq};
+    }
+  }
+  *bad = deficient;
+  if (deficient) return;
+  for (int i = 0; i < b * b; ++i) Rinv[i] = {0.0, 0.0};
+  for (int c = 0; c < b; ++c) {  // column c of R^-1 by back substitution
+    const double dc = R[c * b + c].re;
+    Rinv[c * b + c] = {1.0 / dc, 0.0};
+    for (int i = c - 1; i >= 0; --i) {
+      zd z = {0.0, 0.0};
+      for (int k = i + 1; k <= c; ++k) {
+        const zd u = R[i * b + k], v = Rinv[k * b + c];
+        z.re += u.re * v.re - u.im * v.im;
+        z.im += u.re * v.im + u.im * v.re;
+      }
+      const double di = R[i * b + i].re;
+      Rinv[i * b + c] = {-z.re / di, -z.im / di};
+    }
+  }
+}
+
+// rotated right-hand side of the cycle's least-squares problem: [S; 0]
+__global__ void k_binit(int m, int b, const zd* __restrict__ S, zd* __restrict__ G) {
+  const int n = (m + 1) * b * b;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    G[i] = i < b * b ? S[i] : zd{0.0, 0.0};
+}
+
+// [x; y] <- [c x + s y; -conj(s) x + c y]
+__device__ __forceinline__ void brot(zd& x, zd& y, double c, zd s) {
+  const zd nx = {c * x.re + (s.re * y.re - s.im * y.im), c * x.im + (s.re * y.im + s.im * y.re)};
+  const zd ny = {-(s.re * x.re + s.im * x.im) + c * y.re, -(s.re * x.im - s.im * x.re) + c * y.im};
+  x = nx;
+  y = ny;
+}
+
+// Step j of the block Arnoldi process on the small matrices: enter column
+// block j of the block Hessenberg matrix (the Gram blocks H_ij, i <= j, and
+// the triangular factor R of the new block below them), apply the earlier
+// rotations, zero its b subdiagonals with b rotations per column, rotate the
+// right-hand side and read the per-rhs residual estimates off the last b
+// rows.  flags[0] counts the active columns that are still above tolerance.
+__global__ __launch_bounds__(64) void k_bhess(int j, int m, int b, const zd* __restrict__ Hc,
+                                              const zd* __restrict__ R, zd* __restrict__ H, double* __restrict__ cs,
+                                              zd* __restrict__ sn, zd* __restrict__ G, const int* __restrict__ act,
+                                              const double* __restrict__ bref, double tol, int fixed,
+                                              double* __restrict__ est, int* __restrict__ flags) {
+  const int tid = threadIdx.x;
+  const size_t mb = (size_t)m * b;
+  const int c0 = j * b, nrow = (j + 2) * b;
+  for (int idx = tid; idx < nrow * b; idx += blockDim.x) {
+    const int row = idx / b, q = idx % b;
+    H[(size_t)row * mb + c0 + q] = row < (j + 1) * b ? Hc[(size_t)(row / b) * b * b + (size_t)(row % b) * b + q]
+                                                     : R[(size_t)(row - (j + 1) * b) * b + q];
+  }
+  __syncthreads();
+  if (tid < b) {
+    const int c = c0 + tid;
+    for (int cp = 0; cp < c0; ++cp)
+      for (int t = 0; t < b; ++t)
+        brot(H[(size_t)cp * mb + c], H[(size_t)(cp + 1 + t) * mb + c], cs[(size_t)cp * b + t], sn[(size_t)cp * b + t]);
+  }
+  __syncthreads();
+  for (int q = 0; q < b; ++q) {
+    const int c = c0 + q;
+    if (tid == 0) {
+      for (int t = 0; t < b; ++t) {
+        zd& a = H[(size_t)c * mb + c];
+        zd& y = H[(size_t)(c + 1 + t) * mb + c];
+        const double aa = hypot(a.re, a.im), yy = hypot(y.re, y.im);
+        double cc;
+        zd ss;
+        if (yy == 0.0) {  // nothing to eliminate (also a decoupled inactive column)
+          cc = 1.0;
+          ss = {0.0, 0.0};
+        } else if (aa == 0.0) {
+          cc = 0.0;
+          ss = {y.re / yy, -y.im / yy};  // conj(y) / |y|
+        } else {
+          const double rr = hypot(aa, yy);
+          cc = aa / rr;
+          // (a / |a|) conj(y) / r
+          const zd u = {a.re / aa, a.im / aa};
+          ss = {(u.re * y.re + u.im * y.im) / rr, (u.im * y.re - u.re * y.im) / rr};
+        }
+        cs[(size_t)c * b + t] = cc;
+        sn[(size_t)c * b + t] = ss;
+        brot(a, y, cc, ss);
+        y = {0.0, 0.0};
+      }
+    }
+    __syncthreads();
+    if (tid < b) {
+      if (tid > q)
+        for (int t = 0; t < b; ++t)
+          brot(H[(size_t)c * mb + c0 + tid], H[(size_t)(c + 1 + t) * mb + c0 + tid], cs[(size_t)c * b + t],
+               sn[(size_t)c * b + t]);
+      for (int t = 0; t < b; ++t)
+        brot(G[(size_t)c * b + tid], G[(size_t)(c + 1 + t) * b + tid], cs[(size_t)c * b + t], sn[(size_t)c * b + t]);
+    }
+    __syncthreads();
+  }
+  if (tid == 0) flags[0] = 0;
+  __syncthreads();
+  if (tid < b) {
+    double e2 = 0.0;
+    for (int r = (j + 1) * b; r < (j + 2) * b; ++r) {
+      const zd g = G[(size_t)r * b + tid];
+      e2 += g.re * g.re + g.im * g.im;
+    }
+    const double e = sqrt(e2);
+    if (act[tid]) {
+      est[tid] = bref[tid] > 0.0 ? e / bref[tid] : 0.0;
+      if (fixed || !(e <= tol * bref[tid])) atomicAdd(&flags[0], 1);
+    }
+  }
+}
+
+// Y = T^-1 G on the rotated upper triangle T of the first n column blocks
+// (one thread per rhs column); Y row-major [n b][b].
+__global__ __launch_bounds__(64) void k_bsolve(int n, int m, int b, const zd* __restrict__ H, const zd* __restrict__ G,
+                                               zd* __restrict__ Y) {
+  const int q = threadIdx.x;
+  if (q >= b) return;
+  const size_t mb = (size_t)m * b;
+  const int nb = n * b;
+  for (int i = nb - 1; i >= 0; --i) {
+    zd z = G[(size_t)i * b + q];
+    for (int k = i + 1; k < nb; ++k) {
+      const zd h = H[(size_t)i * mb + k], y = Y[(size_t)k * b + q];
+      z.re -= h.re * y.re - h.im * y.im;
+      z.im -= h.re * y.im + h.im * y.re;
+    }
+    const zd d = H[(size_t)i * mb + i];
+    const double den = d.re * d.re + d.im * d.im;
+    Y[(size_t)i * b + q] = den > 0.0 ? zd{(z.re * d.re + z.im * d.im) / den, (z.im * d.re - z.re * d.im) / den}
+                                     : zd{0.0, 0.0};
+  }
+}
+
 // ---------------------------------------------------------------- workspace
 struct Arena {
   char* base;
@@ -203,6 +405,16 @@ struct Solver {
   zd *part, *hcol, *nrm, *H, *sn, *g, *y;
   double *cs, *bref, *ibref, *beta, *scl, *est, *fin, *fout, *rel;
   int *live, *steps, *flags, *nlive;
+  // block GMRES (one block Krylov space for all rhs): block Hessenberg
+  // ((m+1) b x m b), its rotations, the rotated right-hand side ((m+1) b x b),
+  // the Gram blocks of a step, the triangular factor of the new block and its
+  // inverse, the least-squares solution and the Gram partial sums
+  bool blk = false;
+  unsigned gblk = 0;
+  zd *bH = nullptr, *bsn = nullptr, *bG = nullptr, *bHc = nullptr, *bR = nullptr, *bRi = nullptr, *bW = nullptr,
+     *bY = nullptr, *bpart = nullptr;
+  double* bcs = nullptr;
+  int* bact = nullptr;
 
   void layout(Arena& a) {
     const size_t v64 = nelem * 16;
@@ -242,6 +454,20 @@ struct Solver {
     steps = (int*)a.take(nrhs * sizeof(int));
     flags = (int*)a.take(2 * sizeof(int));
     nlive = (int*)a.take(2 * sizeof(int));
+    if (blk) {
+      const size_t b = (size_t)nrhs, mb = (size_t)m * b;
+      bH = (zd*)a.take((m + 1) * b * mb * sizeof(zd));
+      bsn = (zd*)a.take(mb * b * sizeof(zd));
+      bcs = (double*)a.take(mb * b * sizeof(double));
+      bG = (zd*)a.take((m + 1) * b * b * sizeof(zd));
+      bHc = (zd*)a.take((m + 1) * b * b * sizeof(zd));
+      bR = (zd*)a.take(b * b * sizeof(zd));
+      bRi = (zd*)a.take(b * b * sizeof(zd));
+      bW = (zd*)a.take(b * b * sizeof(zd));
+      bY = (zd*)a.take(mb * b * sizeof(zd));
+      bpart = (zd*)a.take((size_t)4 * gblk * BG_KB * b * b * sizeof(zd));
+      bact = (int*)a.take((b + 8) * sizeof(int));  // activity, breakdown flag, working count, start flags
+    }
   }
 
   void* Vk(int prec, int k) const { return (char*)basis + (size_t)k * nelem * esize(prec); }
@@ -312,6 +538,7 @@ struct Group {
   std::vector<hipGraphExec_t> exec[3];  // per precision, per step j
   int* pinned;                          // 2 ints per lattice
   hipEvent_t ev[2];
+  bool block = false;                   // block GMRES (one lattice) instead of batched
 };
 
 // out = A in for every lattice, in precision prec (in/out chosen per task)
@@ -498,6 +725,95 @@ static int run_gmres(Group& G, int prec, double tol, int max_cycles, int fixed, 
   return LQCD_OK;
 }
 
+
+// Restarted block GMRES(m) on one lattice, FP64: x (the task's current
+// vector) is refined in place; per-rhs statistics go to t.hs.
+static int run_block_gmres(Task& t, double tol, int max_cycles, int fixed, bool x_zero) {
+  Solver& S = t.S;
+  hipStream_t s = S.s;
+  const int b = S.nrhs, m = S.m;
+  const size_t nel = S.nelem, nrows = nel / b, bb = (size_t)b * b;
+  const int np = 4 * (int)S.gblk;
+  int* bad = S.bact + b;       // rank-deficiency flag of the last factorisation
+  int* working = S.bact + b + 1;
+  int* startf = S.bact + b + 2;  // 2 ints
+  auto V = [&](int k) { return (zd*)S.Vk(LQCD_F64, k); };
+  for (int cycle = 0; cycle < max_cycles; ++cycle) {
+    zd* v0 = V(0);
+    if (cycle == 0 && x_zero) {
+      HIPCHK(convert(LQCD_F64, t.b, LQCD_F64, v0, nel, b, nullptr, s));
+      HIPCHK(S.norms(LQCD_F64, v0, 1.0, nullptr));
+    } else {
+      HIPCHK(S.apply(LQCD_F64, t.x, v0, nullptr));
+      HIPCHK(b_minus_y(LQCD_F64, t.b, v0, nel, b, nullptr, S.part, S.nblk, s));
+      HIPCHK(reduce_parts(S.part, S.nblk, 1, b, 1.0, S.nrm, s));
+    }
+    hipLaunchKernelGGL(k_bstart, dim3(1), dim3(1), 0, s, b, S.nrm, t.bref, tol, fixed, S.bact, S.fin, startf);
+    int st[2];
+    std::vector<int> act(b);
+    HIPCHK(hipMemcpyAsync(st, startf, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(act.data(), S.bact, b * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (st[1]) return fail(LQCD_ERR_NONFINITE, "block gmres: non-finite residual norm");
+    if (st[0] == 0) break;
+    for (int q = 0; q < b; ++q) t.hs.restarts[q] += act[q];
+    // thin QR of the residual block: R0 = V_0 S
+    HIPCHK(scale_rhs(LQCD_F64, v0, nel, b, S.fin, nullptr, s));
+    HIPCHK(bgram_parts(v0, 0, 1, v0, nrows, b, S.bpart, S.gblk, s));
+    HIPCHK(reduce_parts(S.bpart, np, 1, (int)bb, 1.0, S.bW, s));
+    hipLaunchKernelGGL(k_bchol, dim3(1), dim3(1), 0, s, b, S.bact, S.bW, S.bR, S.bRi, bad);
+    int deficient = 0;
+    HIPCHK(hipMemcpyAsync(&deficient, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (deficient) break;  // the residual block itself is rank deficient: nothing to expand
+    HIPCHK(bgemm(v0, nullptr, 0.0, 1.0, v0, 0, 1, S.bRi, nrows, b, s));
+    hipLaunchKernelGGL(k_binit, dim3(4), dim3(256), 0, s, m, b, S.bR, S.bG);
+    int steps = 0;
+    for (int j = 0; j < m; ++j) {
+      zd* w = V(j + 1);
+      HIPCHK(S.apply(LQCD_F64, V(j), w, nullptr));
+      // block classical Gram-Schmidt: H_ij = V_i^H w for i <= j, then w -= sum_i V_i H_ij
+      for (int k0 = 0; k0 <= j; k0 += BG_KB) {
+        const int K = (j + 1 - k0) < BG_KB ? (j + 1 - k0) : BG_KB;
+        HIPCHK(bgram_parts(V(k0), nel, K, w, nrows, b, S.bpart, S.gblk, s));
+        HIPCHK(reduce_parts(S.bpart, np, K, (int)bb, 1.0, S.bHc + (size_t)k0 * bb, s));
+      }
+      for (int k0 = 0; k0 <= j; k0 += BG_KB) {
+        const int K = (j + 1 - k0) < BG_KB ? (j + 1 - k0) : BG_KB;
+        HIPCHK(bgemm(w, w, 1.0, -1.0, V(k0), nel, K, S.bHc + (size_t)k0 * bb, nrows, b, s));
+      }
+      // thin QR of the new block: w = V_{j+1} R
+      HIPCHK(bgram_parts(w, 0, 1, w, nrows, b, S.bpart, S.gblk, s));
+      HIPCHK(reduce_parts(S.bpart, np, 1, (int)bb, 1.0, S.bW, s));
+      hipLaunchKernelGGL(k_bchol, dim3(1), dim3(1), 0, s, b, S.bact, S.bW, S.bR, S.bRi, bad);
+      hipLaunchKernelGGL(k_bhess, dim3(1), dim3(64), 0, s, j, m, b, S.bHc, S.bR, S.bH, S.bcs, S.bsn, S.bG, S.bact,
+                         t.bref, tol, fixed, S.est, working);
+      int fl[2];
+      HIPCHK(hipMemcpyAsync(fl, bad, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      steps = j + 1;
+      if (fl[0] || fl[1] == 0) break;  // rank-deficient block (the step still counts) or all converged
+      if (j + 1 < m) HIPCHK(bgemm(w, nullptr, 0.0, 1.0, w, 0, 1, S.bRi, nrows, b, s));
+    }
+    // least squares and x += [V_0 .. V_{steps-1}] Y
+    hipLaunchKernelGGL(k_bsolve, dim3(1), dim3(64), 0, s, steps, m, b, S.bH, S.bG, S.bY);
+    for (int k0 = 0; k0 < steps; k0 += BG_KB) {
+      const int K = (steps - k0) < BG_KB ? (steps - k0) : BG_KB;
+      HIPCHK(bgemm(t.x, t.x, 1.0, 1.0, V(k0), nel, K, S.bY + (size_t)k0 * bb, nrows, b, s));
+    }
+    std::vector<double> est(b);
+    HIPCHK(hipMemcpyAsync(est.data(), S.est, b * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int q = 0; q < b; ++q)
+      if (act[q]) {
+        t.hs.iters[q] += steps;
+        t.hs.est[q] = est[q];
+      }
+    x_zero = false;
+  }
+  return LQCD_OK;
+}
+
 static void defaults(lqcd_solver_params* p) {
   memset(p, 0, sizeof *p);
   p->restart = 30;
@@ -519,9 +835,11 @@ static int check_params(const lqcd_solver_params* p) {
   return LQCD_OK;
 }
 
-static void setup(Solver& S, const lqcd_lattice* lat, int nrhs, const lqcd_solver_params* p, bool clov = false) {
+static void setup(Solver& S, const lqcd_lattice* lat, int nrhs, const lqcd_solver_params* p, bool clov = false,
+                  bool blk = false) {
   S.lat = *lat;
   S.clov = clov;
+  S.blk = blk;
   S.V = (size_t)lat->dims[0] * lat->dims[1] * lat->dims[2] * lat->dims[3];
   S.eo = p->eo ? 1 : 0;
   S.nsite = S.eo ? S.V / 2 : S.V;
@@ -532,11 +850,13 @@ static void setup(Solver& S, const lqcd_lattice* lat, int nrhs, const lqcd_solve
   S.plo = p->mode == 1 ? LQCD_F32 : LQCD_F16;
   S.dag = p->dagger != 0;
   S.nblk = reduce_grid(S.nelem);
+  S.gblk = blk ? bgram_blocks(S.nelem / nrhs) : 0;
 }
 
-static size_t task_bytes(const lqcd_lattice* lat, int nrhs, const lqcd_solver_params* p, bool clov = false) {
+static size_t task_bytes(const lqcd_lattice* lat, int nrhs, const lqcd_solver_params* p, bool clov = false,
+                         bool blk = false) {
   Solver S;
-  setup(S, lat, nrhs, p, clov);
+  setup(S, lat, nrhs, p, clov, blk);
   Arena a{nullptr, 0, 0};
   S.layout(a);
   return (a.off + 511) & ~(size_t)255;
@@ -608,7 +928,8 @@ static int solve_group(Group& G, const lqcd_solver_params* params, lqcd_rhs_stat
       t.b = t.S.bp;
       t.bref = t.S.bref;
     }
-    int rc = run_gmres(G, LQCD_F64, tol, params->max_restarts, fixed, x_zero, 1.0);
+    int rc = G.block ? run_block_gmres(G.T[0], tol, params->max_restarts, fixed, x_zero)
+                     : run_gmres(G, LQCD_F64, tol, params->max_restarts, fixed, x_zero, 1.0);
     if (rc) return rc;
   } else {
     // iterative refinement: FP64 residual and update, inner GMRES in plo
@@ -791,8 +1112,9 @@ size_t gmres_workspace_bytes(const lqcd_lattice* lat, int nrhs, const lqcd_solve
 }
 
 static int init_task(Task& t, const lqcd_lattice* lat, const void* U, const void* b, void* x, int nrhs, double m0,
-                     int layout, const lqcd_solver_params* p, char* work, const void* C = nullptr) {
-  setup(t.S, lat, nrhs, p, C != nullptr);
+                     int layout, const lqcd_solver_params* p, char* work, const void* C = nullptr,
+                     bool blk = false) {
+  setup(t.S, lat, nrhs, p, C != nullptr, blk);
   t.S.C64 = C;
   t.S.m0 = m0;
   t.S.d = 4.0 + m0;
@@ -888,6 +1210,37 @@ int gmres_solve_batch(int nprob, const lqcd_problem* probs, const lqcd_solver_pa
     w += task_bytes(&q.lat, q.nrhs, params);
   }
   return run_group(G, params, stats, (hipStream_t)stream, params->use_graph != 0);
+}
+
+size_t block_gmres_workspace_bytes(const lqcd_lattice* lat, int nrhs, const lqcd_solver_params* p) {
+  if (check_lattice(lat) || nrhs < 1 || nrhs > LQCD_BLOCK_MAX_RHS || check_params(p) || p->mode != 0) return 0;
+  return task_bytes(lat, nrhs, p, false, true) + 256;
+}
+
+int block_gmres_solve(const lqcd_lattice* lat, const void* U, const void* b, void* x, int nrhs, double m0, int layout,
+                      const lqcd_solver_params* params, void* work, size_t work_bytes, lqcd_rhs_stats* stats,
+                      void* stream) {
+  int rc = check_lattice(lat);
+  if (rc) return rc;
+  if ((rc = check_block(nrhs, layout, LQCD_F64))) return rc;
+  if ((rc = check_params(params))) return rc;
+  if (nrhs > LQCD_BLOCK_MAX_RHS)
+    return fail(LQCD_ERR_ARG, "block_gmres_solve: nrhs = %d, the block solver takes at most %d", nrhs,
+                LQCD_BLOCK_MAX_RHS);
+  if (params->mode != 0) return fail(LQCD_ERR_ARG, "block_gmres_solve: only FP64 (mode 0) is supported");
+  if (params->use_graph) return fail(LQCD_ERR_ARG, "block_gmres_solve: graph capture is not supported");
+  if (!U || !b || !x) return fail(LQCD_ERR_ARG, "block_gmres_solve: null array pointer");
+  const size_t need = block_gmres_workspace_bytes(lat, nrhs, params);
+  if (!work || work_bytes < need)
+    return fail(LQCD_ERR_WORKSPACE, "block_gmres_solve: workspace of %zu bytes given, %zu needed", work_bytes, need);
+  if (4.0 + m0 == 0.0 && params->eo)
+    return fail(LQCD_ERR_SINGULAR, "block_gmres_solve: 4 + m0 = 0, D_oo is not invertible");
+  Group G;
+  G.block = true;
+  G.T.resize(1);
+  char* w = (char*)work + ((256 - ((uintptr_t)work & 255)) & 255);
+  init_task(G.T[0], lat, U, b, x, nrhs, m0, layout, params, w, nullptr, true);
+  return run_group(G, params, stats, (hipStream_t)stream, false);
 }
 
 }  // extern "C"

@@ -79,3 +79,25 @@ def test_tune_table_roundtrip(tmp_path):
     lq.set_batch_kernel(0)
     with pytest.raises(lq.LqcdError):
         lq.set_batch_grid(-1)
+
+
+def test_block_gmres_rejects_bad_arguments_on_host():
+    """Argument checks of the block solver run before any device work."""
+    lib = lq.load()
+    good = lq._lattice((4, 4, 4, 4))
+    p = lq.solver_params()
+    assert lib.block_gmres_workspace_bytes(ctypes.byref(good), 16, ctypes.byref(p)) > 0
+    assert lib.block_gmres_workspace_bytes(ctypes.byref(good), 17, ctypes.byref(p)) == 0
+    p1 = lq.solver_params(mode="ir-f32")
+    assert lib.block_gmres_workspace_bytes(ctypes.byref(good), 4, ctypes.byref(p1)) == 0
+    assert lib.block_gmres_solve(ctypes.byref(good), 1, 1, 1, 17, 0.1, lq.LAYOUT2, ctypes.byref(p), 1, 1 << 40,
+                                 None, None) == -1
+    assert lib.block_gmres_solve(ctypes.byref(good), 1, 1, 1, 4, 0.1, lq.LAYOUT2, ctypes.byref(p1), 1, 1 << 40,
+                                 None, None) == -1
+    pg = lq.solver_params(use_graph=True)
+    assert lib.block_gmres_solve(ctypes.byref(good), 1, 1, 1, 4, 0.1, lq.LAYOUT2, ctypes.byref(pg), 1, 1 << 40,
+                                 None, None) == -1
+    assert lib.block_gmres_solve(ctypes.byref(good), None, 1, 1, 4, 0.1, lq.LAYOUT2, ctypes.byref(p), 1, 1 << 40,
+                                 None, None) == -1
+    assert lib.block_gmres_solve(ctypes.byref(good), 1, 1, 1, 4, 0.1, lq.LAYOUT2, ctypes.byref(p), 1, 16,
+                                 None, None) == -6

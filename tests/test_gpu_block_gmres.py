@@ -1,0 +1,164 @@
+"""GPU block_gmres_solve (one block Krylov space for all rhs) against the
+oracle's block GMRES: one cycle of k steps reaches the oracle's minimiser over
+K_k(A, R0) (a different orthogonalisation, equal up to rounding), converged
+solves are checked by an oracle apply, dense LU and the oracle's block step
+count, and the block solver needs no more steps than batched GMRES."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import lqcd_synth as syn
+import paper_2601_05816_amd as lq
+from oracle import block_gmres as obg
+from oracle import dirac, evenodd
+
+from helpers import from_layout_np, rel_err_per_rhs, to_layout_np
+
+pytestmark = pytest.mark.gpu
+
+
+def _solve(U, b, m0, layout=lq.LAYOUT2, x0=None, **kw):
+    import torch
+
+    Ud = torch.from_numpy(U).to("cuda")
+    bd = torch.from_numpy(to_layout_np(b, layout)).to("cuda")
+    x0d = None if x0 is None else torch.from_numpy(to_layout_np(x0, layout)).to("cuda")
+    x, st, rc = lq.block_gmres_solve(Ud, bd, m0, layout=layout, x0=x0d, **kw)
+    return from_layout_np(x.cpu().numpy(), layout, 4), st, rc
+
+
+@pytest.mark.parametrize("eo", [False, True])
+@pytest.mark.parametrize("nrhs,k", [(1, 6), (3, 4), (5, 3), (16, 2)])
+def test_one_cycle_matches_oracle(gpu_lib, eo, nrhs, k):
+    """restart = k, one cycle, tol = 0: x = argmin over the block Krylov space
+    of the (Schur or full) system, compared with the oracle's block GMRES."""
+    dims = (4, 4, 4, 4)
+    m0 = 0.1
+    U = syn.gauge_field(dims, "haar", config=41)
+    b = syn.spinor_block(dims, nrhs, config=41)
+    x, st, rc = _solve(U, b, m0, eo=eo, restart=k, max_restarts=1, tol=0.0)
+    assert rc == lq.NOT_CONVERGED and np.all(st["iters"] == k)
+    if eo:
+        rhs = evenodd.prepare_source(U, b, m0)
+        ye, ost = obg.block_gmres(lambda v: evenodd.apply_schur(U, v, m0), rhs, np.zeros(nrhs), restart=k,
+                                  max_restarts=1)
+        want = evenodd.reconstruct(U, b, ye, m0)
+    else:
+        want, ost = obg.block_gmres(lambda v: dirac.apply_dw(U, v, m0), b, np.zeros(nrhs), restart=k,
+                                    max_restarts=1)
+    assert ost.steps == k
+    assert np.all(rel_err_per_rhs(x, want) <= 1e-10)
+
+
+@pytest.mark.parametrize("eo", [False, True])
+@pytest.mark.parametrize("layout", [lq.RHS_OUTER, lq.LAYOUT2])
+def test_converged_solve_dense_lu_and_step_count(gpu_lib, eo, layout):
+    dims = (4, 4, 4, 4)
+    m0 = 0.1
+    U = syn.gauge_field(dims, "haar", config=42)
+    b = syn.spinor_block(dims, 4, config=42)
+    x, st, rc = _solve(U, b, m0, layout=layout, eo=eo, restart=8, tol=1e-10)
+    assert rc == lq.OK and st["converged"].all()
+    rr = rel_err_per_rhs(dirac.apply_dw(U, x, m0), b)
+    assert np.all(rr <= 1e-10)
+    assert np.allclose(rr, st["true_relres"], rtol=1e-2, atol=1e-15)
+    D = dirac.dense(U, m0)
+    x_lu = np.linalg.solve(D, b.reshape(4, -1).T).T.reshape(b.shape)
+    assert np.all(rel_err_per_rhs(x, x_lu) <= np.linalg.cond(D) * 1e-10)
+    _, ost = obg.block_solve(U, b, m0, tol=1e-10, restart=8, eo=eo)
+    assert np.all(ost.converged)
+    assert abs(int(st["iters"].max()) - int(ost.steps)) <= 2
+
+
+def test_fewer_steps_than_batched(gpu_lib):
+    """Every rhs minimises over a space that contains its own Krylov space, so
+    the block solver needs no more steps than batched GMRES (here fewer)."""
+    import torch
+
+    dims = (8, 8, 4, 4)
+    m0 = -0.05
+    U = syn.gauge_field(dims, "near_identity", config=43, eps=0.3)
+    b = syn.spinor_block(dims, 8, config=43)
+    x, st, rc = _solve(U, b, m0, eo=True, restart=20, tol=1e-10)
+    assert rc == lq.OK
+    assert np.all(rel_err_per_rhs(dirac.apply_dw(U, x, m0), b) <= 1e-10)
+    Ud = torch.from_numpy(U).to("cuda")
+    bd = torch.from_numpy(to_layout_np(b, lq.LAYOUT2)).to("cuda")
+    _, sb, rcb = lq.gmres_solve(Ud, bd, m0, eo=True, restart=20, tol=1e-10)
+    assert rcb == lq.OK
+    assert int(st["iters"].max()) < int(sb["iters"].max())
+
+
+def test_zero_column_guess_and_fixed_steps(gpu_lib):
+    dims = (4, 4, 4, 8)
+    m0 = 0.1
+    U = syn.gauge_field(dims, "near_identity", config=44, eps=0.3)
+    b = syn.spinor_block(dims, 3, config=44)
+    b[1] = 0
+    x, st, rc = _solve(U, b, m0, eo=True, restart=10, tol=1e-11)
+    assert rc == lq.OK and st["converged"].all()
+    assert np.all(x[1] == 0) and st["iters"][1] == 0
+    assert np.all(rel_err_per_rhs(dirac.apply_dw(U, x[[0, 2]], m0), b[[0, 2]]) <= 1e-11)
+    # an exact guess needs no steps
+    x2, st2, rc2 = _solve(U, b, m0, x0=x, eo=True, tol=1e-10)
+    assert rc2 == lq.OK and np.all(st2["iters"] == 0)
+    # fixed protocol: exactly restart x max_restarts block steps, equal to the oracle's
+    b[1] = syn.spinor_block(dims, 1, config=45)[0]
+    x3, st3, rc3 = _solve(U, b, m0, eo=False, restart=4, max_restarts=3, fixed_iters=True)
+    assert rc3 == lq.OK and np.all(st3["iters"] == 12)
+    xo, ost = obg.block_gmres(lambda v: dirac.apply_dw(U, v, m0), b, np.zeros(3), restart=4, max_restarts=3)
+    assert ost.steps == 12
+    assert np.all(rel_err_per_rhs(x3, xo) <= 1e-9)
+
+
+@pytest.mark.parametrize("eo", [False, True])
+def test_adjoint_block_solve(gpu_lib, eo):
+    dims = (4, 4, 6, 4)
+    m0 = 0.1
+    U = syn.gauge_field(dims, "near_identity", config=46, eps=0.3)
+    b = syn.spinor_block(dims, 6, config=46)
+    x, st, rc = _solve(U, b, m0, eo=eo, tol=1e-10, dagger=True)
+    assert rc == lq.OK
+    assert np.all(rel_err_per_rhs(dirac.apply_dw_dagger(U, x, m0), b) <= 1e-10)
+
+
+def test_16x16x16x32_sixteen_rhs_sampled(gpu_lib):
+    """The headline rhs count on a larger lattice: true residual from the
+    library's FP64 apply, and the oracle's apply at sampled sites of x."""
+    dims = (32, 16, 16, 16)
+    m0 = -0.05
+    U = syn.gauge_field(dims, "near_identity", config=47, eps=0.3)
+    b = syn.spinor_block(dims, 16, config=47)
+    x, st, rc = _solve(U, b, m0, eo=True, restart=10, tol=1e-10)
+    assert rc == lq.OK and st["converged"].all() and np.all(st["true_relres"] <= 1e-10)
+    rng = np.random.default_rng(47)
+    V = int(np.prod(dims))
+    sites = rng.integers(0, V, 24)
+    got = dirac.apply_dw_sites(U, x, m0, sites)
+    want = b.reshape(16, V, 4, 3)[:, sites]
+    err = np.abs(got - want).max()
+    assert err <= 1e-8 * np.abs(b).max()
+
+
+def test_errors(gpu_lib):
+    import torch
+
+    dims = (4, 4, 4, 4)
+    U = torch.from_numpy(syn.gauge_field(dims, "haar", config=48)).to("cuda")
+    b = torch.from_numpy(to_layout_np(syn.spinor_block(dims, 17, config=48), lq.LAYOUT2)).to("cuda")
+    with pytest.raises(lq.LqcdError) as e:
+        lq.block_gmres_solve(U, b, 0.1)
+    assert e.value.code == -1
+    b4 = b[..., :4].contiguous()
+    with pytest.raises(lq.LqcdError) as e:
+        lq.block_gmres_solve(U, b4, 0.1, mode="ir-f32")
+    assert e.value.code == -1
+    with pytest.raises(lq.LqcdError) as e:
+        lq.block_gmres_solve(U, b4, -4.0, eo=True)
+    assert e.value.code == -7
+    small = torch.empty(16, dtype=torch.uint8, device="cuda")
+    p = lq.solver_params()
+    rc = lq.load().block_gmres_solve(ctypes.byref(lq._lattice(dims)), U.data_ptr(), b4.data_ptr(), b4.data_ptr(), 4,
+                                     0.1, lq.LAYOUT2, ctypes.byref(p), small.data_ptr(), 16, None, None)
+    assert rc == -6
