@@ -163,6 +163,49 @@ def gmres_section(lq, U64, psi64, nrhs):
     return out
 
 
+def block_gmres_section(lq, U64, psi64, nrhs, batched=None):
+    """Block GMRES (all rhs share one block Krylov space) on the headline
+    system: time and block steps to a true 1e-10 with GMRES(30), odd-even,
+    against the batched solver, and the fixed protocol of 100 steps (10
+    restarts of 10) for the cost of one block step."""
+    import torch
+
+    b = psi64[..., :nrhs].contiguous()
+    out = {"lattice": list(DIMS), "nrhs": nrhs, "restart": 30, "eo": True, "tol": 1e-10}
+    p = lq.solver_params(restart=30, eo=True, tol=1e-10, max_restarts=400)
+    work = torch.empty(lq.block_gmres_workspace_bytes(DIMS, nrhs, p), dtype=torch.uint8, device=b.device)
+    torch.cuda.synchronize()
+    t = time.time()
+    x, st, rc = lq.block_gmres_solve(U64, b, M0, layout=lq.LAYOUT2, work=work, restart=30, eo=True, tol=1e-10,
+                                     max_restarts=400)
+    torch.cuda.synchronize()
+    dt = time.time() - t
+    out["to_1e-10"] = {"seconds": round(dt, 3), "status": int(rc), "converged": bool(st["converged"].all()),
+                       "block_steps": int(st["iters"].max()), "max_true_relres": float(st["true_relres"].max()),
+                       "workspace_gb": round(work.numel() / 1e9, 2)}
+    if batched is not None:
+        out["to_1e-10"]["batched_f64_seconds"] = batched["seconds"]
+        out["to_1e-10"]["batched_f64_steps_max"] = batched["iters_max"]
+        out["speedup_vs_batched"] = round(batched["seconds"] / dt, 3)
+    log(f"block GMRES to 1e-10: {json.dumps(out['to_1e-10'])}")
+    del work
+    torch.cuda.empty_cache()
+    p = lq.solver_params(restart=10, max_restarts=10, eo=True, fixed_iters=True)
+    work = torch.empty(lq.block_gmres_workspace_bytes(DIMS, nrhs, p), dtype=torch.uint8, device=b.device)
+    torch.cuda.synchronize()
+    t = time.time()
+    x, st, rc = lq.block_gmres_solve(U64, b, M0, layout=lq.LAYOUT2, work=work, restart=10, max_restarts=10, eo=True,
+                                     fixed_iters=True)
+    torch.cuda.synchronize()
+    dt = time.time() - t
+    out["fixed_100_steps"] = {"seconds": round(dt, 3), "ms_per_step": round(dt * 10, 3),
+                              "true_relres_max": float(st["true_relres"].max())}
+    log(f"block GMRES fixed 100 steps: {dt:.3f} s")
+    del work
+    torch.cuda.empty_cache()
+    return out
+
+
 def clover_section(lq, syn, U64, psi64, steps):
     """The clover-improved operator D = D_W - C on the headline workload
     (synthetic clover field, two Hermitian 6x6 blocks per site, scale 0.2):
@@ -346,6 +389,20 @@ def profile_only(args):
         ye = torch.empty_like(xe)
         ms = timed(lambda: lq.dirac_apply_eo(U, xe, M0, layout=lq.LAYOUT2, out=ye), args.steps, args.warmup)
         out.update(nrhs=NRHS, schur_ms=round(ms, 4))
+    elif args.only == "block-fixed":  # block GMRES, 100 block steps = 10 restarts of 10, odd-even
+        U.mul_(0.3)
+        b = torch.randn(DIMS + (4, 3, NRHS), dtype=torch.complex128, device=dev, generator=g)
+        kw = dict(restart=10, max_restarts=10, eo=True, fixed_iters=True)
+        work = torch.empty(lq.block_gmres_workspace_bytes(DIMS, NRHS, lq.solver_params(**kw)), dtype=torch.uint8,
+                           device=dev)
+        out["seconds"] = []
+        for i in range(args.warmup + args.steps):
+            torch.cuda.synchronize()
+            t = time.time()
+            lq.block_gmres_solve(U, b, M0, layout=lq.LAYOUT2, work=work, **kw)
+            torch.cuda.synchronize()
+            out["seconds"].append(round(time.time() - t, 3))
+            log(f"block GMRES 100 steps ({'warmup' if i < args.warmup else 'timed'}): {out['seconds'][-1]} s")
     else:  # the paper's fixed protocol: 100 iterations = 10 restarts of 10, odd-even, FP64
         U.mul_(0.3)
         b = torch.randn(DIMS + (4, 3, NRHS), dtype=torch.complex128, device=dev, generator=g)
@@ -376,6 +433,7 @@ def main():
     ap.add_argument("--no-gmres", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven eight-lattice batch")
     ap.add_argument("--no-clover", action="store_true", help="skip the clover-improved operator")
+    ap.add_argument("--no-block", action="store_true", help="skip block GMRES")
     ap.add_argument("--no-autograd", action="store_true", help="skip the differentiation timing")
     ap.add_argument("--gmres-nrhs", type=int, default=NRHS)
     ap.add_argument("--variant", type=int, default=0, help="Wilson kernel: 0 auto, 1 site, 2 pencil")
@@ -387,7 +445,7 @@ def main():
                     help="kernel configurations measured by the autotuner on MI355X (used when present)")
     ap.add_argument("--retune", action="store_true", help="ignore the tune file and autotune every apply")
     ap.add_argument("--save-tune", default="", help="write the autotuner's table here at the end")
-    ap.add_argument("--only", choices=["sweep-f64", "schur-f64", "gmres-fixed"], default="",
+    ap.add_argument("--only", choices=["sweep-f64", "schur-f64", "gmres-fixed", "block-fixed"], default="",
                     help="profiling mode: run one workload only (GPU-drawn inputs, tune file), print its times")
     args = ap.parse_args()
     if args.only:
@@ -541,6 +599,9 @@ def main():
     # ------------------------------------------------------------------ GMRES
     if not args.no_gmres:
         result["gmres"] = gmres_section(lq, U64, psi64, args.gmres_nrhs)
+    if not args.no_block and args.gmres_nrhs <= lq.BLOCK_MAX_RHS:
+        result["block_gmres"] = block_gmres_section(lq, U64, psi64, args.gmres_nrhs,
+                                                    None if args.no_gmres else result["gmres"]["f64"])
 
     # ------------------------------- clover term, uneven batch, differentiation
     if not args.no_clover:

@@ -26,8 +26,8 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
 // lane l loads element (row0 + l / 16, l % 16) of V_k and of W, i.e. the A
 // operand V_k^T (i = column of V, k = row) and the B operand W.
 template <int KB>
-__global__ __launch_bounds__(256) void k_bgram(const zd* __restrict__ V, size_t vstride, int K,
-                                               const zd* __restrict__ W, size_t nrows, int b, size_t rows_per_blk,
+__global__ __launch_bounds__(256) void k_bgram(const zd* V, size_t vstride, int K, const zd* W, size_t nrows, int b,
+                                               size_t rows_per_blk,
                                                zd* __restrict__ parts) {
   const int l = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = l & 15, kq = l >> 4;
@@ -39,6 +39,7 @@ __global__ __launch_bounds__(256) void k_bgram(const zd* __restrict__ V, size_t 
     hr[k] = d4{0.0, 0.0, 0.0, 0.0};
     hi[k] = d4{0.0, 0.0, 0.0, 0.0};
   }
+  const bool self = K == 1 && V == W;  // W^H W: one load serves both operands
   for (size_t q = r0 + 4 * (size_t)wave; q < r1; q += 16) {
     const size_t row = q + kq;
     const bool ok = row < r1 && col < b;
@@ -46,7 +47,7 @@ __global__ __launch_bounds__(256) void k_bgram(const zd* __restrict__ V, size_t 
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
       if (k < K) {
-        const zd v = ok ? V[(size_t)k * vstride + row * b + col] : zd{0.0, 0.0};
+        const zd v = self ? w : (ok ? V[(size_t)k * vstride + row * b + col] : zd{0.0, 0.0});
         // conj(v) w = (vr wr + vi wi) + i (vr wi - vi wr)
         hr[k] = mfma(v.re, w.re, hr[k]);
         hr[k] = mfma(v.im, w.im, hr[k]);
@@ -79,17 +80,15 @@ template <int KB>
 __global__ __launch_bounds__(256) void k_bgemm(zd* out, const zd* Y, double alpha, double beta, const zd* V,
                                                size_t vstride, int K, const zd* __restrict__ C, size_t nrows, int b) {
   __shared__ zd tile[4][256];
+  __shared__ zd cl[KB][16][16];  // coefficient blocks, zero-padded to 16 x 16
   const int l = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = l & 15, kq = l >> 4;
   const size_t bb = (size_t)b * b;
-  zd cb[KB][4];  // C_k[r0 + kq][col] for r0 = 0, 4, 8, 12
-#pragma unroll
-  for (int k = 0; k < KB; ++k)
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int r = 4 * s + kq;
-      cb[k][s] = (k < K && r < b && col < b) ? C[(size_t)k * bb + (size_t)r * b + col] : zd{0.0, 0.0};
-    }
+  for (int e = threadIdx.x; e < KB * 256; e += blockDim.x) {
+    const int k = e >> 8, r = (e >> 4) & 15, c = e & 15;
+    cl[k][r][c] = (k < K && r < b && c < b) ? C[(size_t)k * bb + (size_t)r * b + c] : zd{0.0, 0.0};
+  }
+  __syncthreads();
   zd* sh = tile[wave];
   const size_t ntiles = (nrows + 15) / 16;
   for (size_t t = (size_t)blockIdx.x * 4 + wave; t < ntiles; t += (size_t)gridDim.x * 4) {
@@ -109,7 +108,7 @@ __global__ __launch_bounds__(256) void k_bgemm(zd* out, const zd* Y, double alph
           const int r = 4 * s + kq;
           if (4 * s < b) {  // uniform: skip steps past the last coefficient row
             const zd a = r < b ? sh[col * b + r] : zd{0.0, 0.0};
-            const zd c = cb[k][s];
+            const zd c = cl[k][r][col];
             // a c = (ar cr - ai ci) + i (ar ci + ai cr)
             dr = mfma(a.re, c.re, dr);
             dr = mfma(-a.im, c.im, dr);
@@ -157,12 +156,12 @@ hipError_t bgram_parts(const void* V, size_t vstride, int K, const void* W, size
 
 hipError_t bgemm(void* out, const void* Y, double alpha, double beta, const void* V, size_t vstride, int K,
                  const void* C, size_t nrows, int b, hipStream_t s) {
-  if (b < 1 || b > 16 || K < 0 || K > BG_KB) return hipErrorInvalidValue;
+  if (b < 1 || b > 16 || K < 0 || K > BM_KB) return hipErrorInvalidValue;
   const size_t ntiles = (nrows + 15) / 16;
   size_t grid = (ntiles + 3) / 4;
   if (grid > 2048) grid = 2048;
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL((k_bgemm<BG_KB>), dim3((unsigned)grid), dim3(256), 0, s, (zd*)out, (const zd*)Y, alpha, beta,
+  hipLaunchKernelGGL((k_bgemm<BM_KB>), dim3((unsigned)grid), dim3(256), 0, s, (zd*)out, (const zd*)Y, alpha, beta,
                      (const zd*)V, vstride, K, (const zd*)C, nrows, b);
   return hipGetLastError();
 }

@@ -38,8 +38,9 @@ hipError_t pack(int layout, bool to_internal, void* abi, void* ie, void* io, con
 // on the FP64 matrix cores.  bgram_parts writes 4 * nblk partial sums of the
 // K Gram blocks V_k^H W (K <= BG_KB, each b x b, row-major) for
 // reduce_parts(parts, 4 * nblk, K, b * b, ...); nblk = bgram_blocks(nrows).
-// bgemm: out = alpha Y + beta sum_k V_k C_k, K <= BG_KB coefficient blocks.
+// bgemm: out = alpha Y + beta sum_k V_k C_k, K <= BM_KB coefficient blocks.
 constexpr int BG_KB = 4;
+constexpr int BM_KB = 8;
 unsigned bgram_blocks(size_t nrows);
 hipError_t bgram_parts(const void* V, size_t vstride, int K, const void* W, size_t nrows, int b, void* parts,
                        unsigned nblk, hipStream_t s);

@@ -778,8 +778,8 @@ static int run_block_gmres(Task& t, double tol, int max_cycles, int fixed, bool 
         HIPCHK(bgram_parts(V(k0), nel, K, w, nrows, b, S.bpart, S.gblk, s));
         HIPCHK(reduce_parts(S.bpart, np, K, (int)bb, 1.0, S.bHc + (size_t)k0 * bb, s));
       }
-      for (int k0 = 0; k0 <= j; k0 += BG_KB) {
-        const int K = (j + 1 - k0) < BG_KB ? (j + 1 - k0) : BG_KB;
+      for (int k0 = 0; k0 <= j; k0 += BM_KB) {
+        const int K = (j + 1 - k0) < BM_KB ? (j + 1 - k0) : BM_KB;
         HIPCHK(bgemm(w, w, 1.0, -1.0, V(k0), nel, K, S.bHc + (size_t)k0 * bb, nrows, b, s));
       }
       // thin QR of the new block: w = V_{j+1} R
@@ -797,8 +797,8 @@ static int run_block_gmres(Task& t, double tol, int max_cycles, int fixed, bool 
     }
     // least squares and x += [V_0 .. V_{steps-1}] Y
     hipLaunchKernelGGL(k_bsolve, dim3(1), dim3(64), 0, s, steps, m, b, S.bH, S.bG, S.bY);
-    for (int k0 = 0; k0 < steps; k0 += BG_KB) {
-      const int K = (steps - k0) < BG_KB ? (steps - k0) : BG_KB;
+    for (int k0 = 0; k0 < steps; k0 += BM_KB) {
+      const int K = (steps - k0) < BM_KB ? (steps - k0) : BM_KB;
       HIPCHK(bgemm(t.x, t.x, 1.0, 1.0, V(k0), nel, K, S.bY + (size_t)k0 * bb, nrows, b, s));
     }
     std::vector<double> est(b);
