@@ -389,6 +389,18 @@ def profile_only(args):
         ye = torch.empty_like(xe)
         ms = timed(lambda: lq.dirac_apply_eo(U, xe, M0, layout=lq.LAYOUT2, out=ye), args.steps, args.warmup)
         out.update(nrhs=NRHS, schur_ms=round(ms, 4))
+    elif args.only == "clover-f64":  # D = D_W - C: full apply, then the Schur apply (two passes)
+        C = 0.1 * torch.randn(DIMS + (42,), dtype=torch.complex128, device=dev, generator=g)
+        Ci = 0.1 * torch.randn(DIMS + (42,), dtype=torch.complex128, device=dev, generator=g)
+        psi = torch.randn(DIMS + (4, 3, NRHS), dtype=torch.complex128, device=dev, generator=g)
+        eta = torch.empty_like(psi)
+        ms = timed(lambda: lq.dirac_apply_clover(U, C, psi, M0, layout=lq.LAYOUT2, out=eta), args.steps, args.warmup)
+        xe = psi.reshape((v, 4, 3, NRHS))[: v // 2].contiguous()
+        ye = torch.empty_like(xe)
+        me = timed(lambda: lq.dirac_apply_eo_clover(U, C, Ci, xe, M0, layout=lq.LAYOUT2, out=ye), args.steps,
+                   args.warmup)
+        out.update(nrhs=NRHS, full_ms=round(ms, 4), schur_ms=round(me, 4))
+        log(f"clover full {ms:.4f} ms, Schur {me:.4f} ms")
     elif args.only == "block-fixed":  # block GMRES, 100 block steps = 10 restarts of 10, odd-even
         U.mul_(0.3)
         b = torch.randn(DIMS + (4, 3, NRHS), dtype=torch.complex128, device=dev, generator=g)
@@ -445,7 +457,8 @@ def main():
                     help="kernel configurations measured by the autotuner on MI355X (used when present)")
     ap.add_argument("--retune", action="store_true", help="ignore the tune file and autotune every apply")
     ap.add_argument("--save-tune", default="", help="write the autotuner's table here at the end")
-    ap.add_argument("--only", choices=["sweep-f64", "schur-f64", "gmres-fixed", "block-fixed"], default="",
+    ap.add_argument("--only", choices=["sweep-f64", "schur-f64", "clover-f64", "gmres-fixed", "block-fixed"],
+                    default="",
                     help="profiling mode: run one workload only (GPU-drawn inputs, tune file), print its times")
     args = ap.parse_args()
     if args.only:

@@ -2,9 +2,11 @@
 // equation after eq. (1); Algorithm 1 applies C together with the diagonal):
 // the full apply, the site-local inverse of D_oo = (4 + m0) - C_o, and the
 // odd-even Schur complement S = D_ee - D_eo D_oo^{-1} D_oe with a
-// site-dependent D_oo.  One (site, rhs) per work item, the body of site.h
-// with the clover epilogue; the clover field is read once per site and rhs
-// (an L1/L2 hit for the other rhs of the site in the rhs-innermost layouts).
+// site-dependent D_oo.  The full apply takes the kernel kind chosen for the
+// plain operator (time-streaming pencils or one (site, rhs) per work item,
+// both with the clover epilogue); the odd-even passes run one (site, rhs) per
+// work item.  The clover field is read once per site and rhs (an L1/L2 hit
+// for the other rhs of the site in the rhs-innermost layouts).
 #include <stdint.h>
 
 #include "kernels.h"
@@ -175,8 +177,18 @@ static inline unsigned nblk(size_t items) { return (unsigned)((items + 255) / 25
     default: return hipErrorInvalidValue;                                                              \
   }
 
+// The full clover apply runs on the pencil kernel whenever the configuration
+// chosen for the plain operator of the same problem is a pencil one (the
+// clover epilogue adds one site-local block product per site and rhs), else
+// on the one-(site, rhs)-per-work-item kernel.  The odd-even passes always
+// take the latter (measured faster there at 32^3 x 64, 16 rhs, FP64).
 hipError_t wilson_full_clover(const lqcd_lattice* lat, const void* U, const void* C, const void* psi, void* eta,
                               int nrhs, double diag, double hopc, int layout, int prec, bool dagger, hipStream_t s) {
+  kcfg c = choose_cfg(KIND_FULL, lat, nrhs, prec, layout);
+  if (c.variant >= 2) {
+    c.variant = 3;
+    return wilson_full_clover_pencil(lat, U, C, psi, eta, nrhs, diag, hopc, layout, prec, dagger, c, s);
+  }
   const geo4 g = make_geo(lat);
   CL_DISPATCH(prec, layout, (dagger ? 1 : 0),
               hipLaunchKernelGGL((k_wilson_full_cl<PP, LL, SS>), dim3(nblk(g.V * (size_t)nrhs)), dim3(256), 0, s,

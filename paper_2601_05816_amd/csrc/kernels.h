@@ -37,6 +37,10 @@ hipError_t wilson_full_pencil(const lqcd_lattice* lat, const void* U, const void
 hipError_t wilson_eo_pencil(const lqcd_lattice* lat, const void* U, const void* in, const void* xin, void* out,
                             int p, int nrhs, double alpha, double beta, int layout, int prec, bool dagger,
                             const int* live, const kcfg& c, hipStream_t s);
+// the same pencils for D = D_W - C (the epilogue of wilson_full_clover)
+hipError_t wilson_full_clover_pencil(const lqcd_lattice* lat, const void* U, const void* C, const void* psi,
+                                     void* eta, int nrhs, double diag, double hopc, int layout, int prec, bool dagger,
+                                     const kcfg& c, hipStream_t s);
 
 // Pencil kernels with two rhs per work item (pencil_nr.hip): rhs-innermost
 // layout, FP32 / FP16 storage, even nrhs.

@@ -223,6 +223,21 @@ __global__ __launch_bounds__(256) void k_wilson_eo_p(const typename prec_traits<
   wilson_eo_p_body<PREC, LAYOUT, SG>(U, in, xin, out, pg, p, nrhs, alpha, beta, live, blockIdx.x);
 }
 
+// Clover-improved operator D = D_W - C on the same pencil grid (body in
+// pencil_kernels.h with the clover epilogue).  The odd-even clover passes
+// stay on the one-(site, rhs)-per-work-item kernels: with the clover
+// product added, the pencil version of those passes measured slower.
+template <int PREC, int LAYOUT, int SG>
+__global__ __launch_bounds__(256) void k_wilson_full_pcl(const typename prec_traits<PREC>::store* __restrict__ U,
+                                                         const typename prec_traits<PREC>::store* __restrict__ C,
+                                                         const typename prec_traits<PREC>::store* __restrict__ psi,
+                                                         typename prec_traits<PREC>::store* __restrict__ eta,
+                                                         pencil_geo pg, int nrhs,
+                                                         typename prec_traits<PREC>::real diag,
+                                                         typename prec_traits<PREC>::real hopc) {
+  wilson_full_p_body<PREC, LAYOUT, SG, true>(U, psi, eta, pg, nrhs, diag, hopc, blockIdx.x, C);
+}
+
 // ------------------------------------------------------------ configuration
 bool occupancy_lds(int occ, size_t static_bytes, size_t* dyn_bytes) {
   *dyn_bytes = 0;
@@ -283,6 +298,19 @@ static hipError_t launch_eo_p(const lqcd_lattice* lat, const void* U, const void
   return hipSuccess;
 }
 
+template <int PREC, int LAYOUT, int SG>
+static hipError_t launch_full_pcl(const lqcd_lattice* lat, const void* U, const void* C, const void* psi, void* eta,
+                                  int nrhs, double diag, double hopc, const kcfg& c, hipStream_t s) {
+  typedef typename prec_traits<PREC>::store S;
+  typedef typename prec_traits<PREC>::real R;
+  pencil_geo pg = make_pencil(lat, nrhs, false, c);
+  size_t dyn = 0;
+  if (!occupancy_lds(c.occ, 0, &dyn)) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((k_wilson_full_pcl<PREC, LAYOUT, SG>), dim3(pencil_blocks(pg)), dim3(256), dyn, s, (const S*)U,
+                     (const S*)C, (const S*)psi, (S*)eta, pg, nrhs, (R)diag, (R)hopc);
+  return hipSuccess;
+}
+
 #define LQ_KEY(p, l, d) ((p) * 100 + (l) * 10 + (d))
 #define LQ_CASE(P, L, D, FN, ...) \
   case LQ_KEY(P, L, D): {                                \
@@ -314,6 +342,13 @@ hipError_t wilson_eo_pencil(const lqcd_lattice* lat, const void* U, const void* 
                             int p, int nrhs, double alpha, double beta, int layout, int prec, bool dagger,
                             const int* live, const kcfg& c, hipStream_t s) {
   LQ_DISPATCH(prec, layout, (dagger ? 1 : 0), launch_eo_p, lat, U, in, xin, out, p, nrhs, alpha, beta, live, c, s);
+  return hipGetLastError();
+}
+
+hipError_t wilson_full_clover_pencil(const lqcd_lattice* lat, const void* U, const void* C, const void* psi,
+                                     void* eta, int nrhs, double diag, double hopc, int layout, int prec, bool dagger,
+                                     const kcfg& c, hipStream_t s) {
+  LQ_DISPATCH(prec, layout, (dagger ? 1 : 0), launch_full_pcl, lat, U, C, psi, eta, nrhs, diag, hopc, c, s);
   return hipGetLastError();
 }
 

@@ -4,18 +4,23 @@
 // a list of work units) share them.
 #pragma once
 
+#include "clover.h"
 #include "pencil.h"
 
 namespace lq {
 
 // ---------------------------------------------------------- full lattice
-template <int PREC, int LAYOUT, int SG>
+// CL: the clover-improved operator D = D_W - C, C(x) psi(x) subtracted with
+// the diagonal term (C: 42 packed entries per site).
+template <int PREC, int LAYOUT, int SG, bool CL = false>
 __device__ __forceinline__ void wilson_full_p_body(const typename prec_traits<PREC>::store* __restrict__ U,
                                                        const typename prec_traits<PREC>::store* __restrict__ psi,
                                                        typename prec_traits<PREC>::store* __restrict__ eta,
                                                        pencil_geo pg, int nrhs,
                                                        typename prec_traits<PREC>::real diag,
-                                                       typename prec_traits<PREC>::real hopc, unsigned b) {
+                                                       typename prec_traits<PREC>::real hopc, unsigned b,
+                                                       const typename prec_traits<PREC>::store* __restrict__ C =
+                                                           nullptr) {
   typedef typename prec_traits<PREC>::store S;
   typedef typename prec_traits<PREC>::real R;
   int x, y, z, rhs, t0;
@@ -51,6 +56,11 @@ __device__ __forceinline__ void wilson_full_p_body(const typename prec_traits<PR
     for (int i = 0; i < 12; ++i) {
       cx<R> a = acc.c[i / 3][i % 3], b = p0.c[i / 3][i % 3];
       acc.c[i / 3][i % 3] = {fma(diag, b.re, a.re), fma(diag, b.im, a.im)};
+    }
+    if (CL) {
+      const spinor<R> c0 = clover_mul<S, R>(C + s0 * 42, p0);
+#pragma unroll
+      for (int i = 0; i < 12; ++i) acc.c[i / 3][i % 3] = acc.c[i / 3][i % 3] - c0.c[i / 3][i % 3];
     }
     hplus = project<0, SG>(p0);
   }
@@ -94,6 +104,11 @@ __device__ __forceinline__ void wilson_full_p_body(const typename prec_traits<PR
     if (it + 1 < pg.Lt) {
 #pragma unroll
       for (int i = 0; i < 12; ++i) acc.c[i / 3][i % 3] = scale(diag, p1.c[i / 3][i % 3]);
+      if (CL) {
+        const spinor<R> c1 = clover_mul<S, R>(C + s1 * 42, p1);
+#pragma unroll
+        for (int i = 0; i < 12; ++i) acc.c[i / 3][i % 3] = acc.c[i / 3][i % 3] - c1.c[i / 3][i % 3];
+      }
       reconstruct<0, SG>(acc, hscale(hopc, colour_mul<true>(U0 + site * 9, hplus)));
       hplus = project<0, SG>(p1);
     }

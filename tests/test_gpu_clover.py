@@ -1,7 +1,9 @@
 """The clover-improved operator D = D_W - C on the GPU against the oracle:
 full apply (three precisions, three layouts, D and D^dagger), the site-local
 inverse of D_oo, and the odd-even Schur complement with a site-dependent
-D_oo; a full-size case checked on sampled sites."""
+D_oo; a full-size case checked on sampled sites.  Every test runs with both
+kernel kinds configured (one work item per site and rhs; time-streaming
+pencils)."""
 import numpy as np
 import pytest
 
@@ -18,6 +20,17 @@ LAYOUTS = [lq.RHS_OUTER, lq.LAYOUT1, lq.LAYOUT2]
 
 def _g5h(x):
     return dirac.apply_gamma5(x.reshape(x.shape[0], -1, 1, 1, 1, 4, 3)).reshape(x.shape)
+
+
+@pytest.fixture(params=[1, 3], ids=["site", "pencil"], autouse=True)
+def clover_kernel(request, gpu_lib):
+    """Every clover test runs with the plain operator configured for the
+    one-(site, rhs) kernels and for the time-streaming pencils: the full
+    clover apply follows that choice (the odd-even clover passes always take
+    the one-(site, rhs) kernels)."""
+    gpu_lib.set_kernel_variant(request.param)
+    yield request.param
+    gpu_lib.set_kernel_variant(0)
 
 
 @pytest.mark.parametrize("prec", [lq.F64, lq.F32, lq.F16])

@@ -1,0 +1,55 @@
+"""The full apply at the largest lattice of the parity suite, 48^3 x 96 with
+16 rhs (about 71 GB of FP64 operands on one GPU), in the tuned launch
+configuration: inputs drawn on the GPU, the oracle evaluated at sampled
+sites on a 3^4 neighbourhood gathered around each site (D_W at a site only
+reads its nearest neighbours, so the centre of the gathered block is exact)."""
+import numpy as np
+import pytest
+
+import paper_2601_05816_amd as lq
+from oracle import dirac
+
+from helpers import rel_err_per_rhs
+
+pytestmark = pytest.mark.gpu
+
+DIMS = (96, 48, 48, 48)
+NRHS = 16
+
+
+def _neighbourhood(coord):
+    """Site numbers of the 3^4 block centred on coord (periodic), in the
+    block's own row-major order."""
+    offs = np.stack(np.meshgrid(*([np.arange(-1, 2)] * 4), indexing="ij"), axis=-1).reshape(-1, 4)
+    pts = (np.asarray(coord)[None, :] + offs) % np.asarray(DIMS)[None, :]
+    return np.ravel_multi_index(pts.T, DIMS)
+
+
+@pytest.mark.parametrize("prec", [lq.F64, lq.F32])
+def test_max_size_apply_sampled(gpu_lib, prec):
+    import torch
+
+    V = int(np.prod(DIMS))
+    dt = torch.complex128 if prec == lq.F64 else torch.complex64
+    g = torch.Generator(device="cuda").manual_seed(11)
+    U = torch.randn((4,) + DIMS + (3, 3), dtype=dt, device="cuda", generator=g)
+    psi = torch.randn(DIMS + (4, 3, NRHS), dtype=dt, device="cuda", generator=g)
+    m0 = -0.05
+    out = lq.dirac_apply(U, psi, m0, layout=lq.LAYOUT2)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(12)
+    sites = rng.integers(0, V, 12)
+    Uf = U.reshape(4, V, 3, 3)
+    pf = psi.reshape(V, 4, 3, NRHS)
+    of = out.reshape(V, 4, 3, NRHS)
+    for s in sites:
+        coord = np.unravel_index(int(s), DIMS)
+        nb = torch.from_numpy(_neighbourhood(coord)).to("cuda")
+        Ub = Uf[:, nb].cpu().numpy().astype(np.complex128).reshape((4, 3, 3, 3, 3, 3, 3))
+        pb = np.moveaxis(pf[nb].cpu().numpy().astype(np.complex128), -1, 0).reshape((NRHS, 3, 3, 3, 3, 4, 3))
+        want = dirac.apply_dw_sites(Ub, pb, m0, [40])  # centre (1, 1, 1, 1) of the 3^4 block
+        got = np.moveaxis(of[int(s)].cpu().numpy().astype(np.complex128), -1, 0)[:, None]
+        tol = 1e-12 if prec == lq.F64 else 1e-5
+        assert np.all(rel_err_per_rhs(got, want) <= tol), (int(s), coord)
+    del U, psi, out
+    torch.cuda.empty_cache()
