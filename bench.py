@@ -323,6 +323,86 @@ def batch_section(lq, syn, steps):
     return out
 
 
+def small_section(lq, syn, with_oracle):
+    """The small workloads beside the headline: a 4^4 Haar lattice (m0 = 0.1,
+    one rhs: one apply and GMRES(30) on the full system; launch-latency
+    bound, not a roofline point) and a 16^3 x 32 near-identity lattice
+    (m0 = -0.05, nrhs 1 / 4 / 12: full and Schur applies in FP64 and FP32,
+    labelled cache-resident because the working set is of the order of the
+    256 MB Infinity Cache; odd-even GMRES(30) to 1e-10 at 12 rhs, FP64 against
+    FP32 refinement), with the oracle timed on the same inputs (4^4 apply and
+    GMRES; one rhs of the 16^3 x 32 apply)."""
+    import torch
+
+    dev = torch.device("cuda:0")
+    out = {}
+    dims = (4, 4, 4, 4)
+    U = syn.gauge_field(dims, "haar", config=1)
+    b = syn.spinor_block(dims, 1, config=1)
+    Ud = torch.from_numpy(U).to(dev)
+    bd = torch.from_numpy(np.ascontiguousarray(np.moveaxis(b, 0, -1))).to(dev)
+    ms = timed(lambda: lq.dirac_apply(Ud, bd, 0.1, layout=lq.LAYOUT2), 20, 3)
+    torch.cuda.synchronize()
+    t = time.time()
+    x, st, rc = lq.gmres_solve(Ud, bd, 0.1, layout=lq.LAYOUT2, eo=False, restart=30, tol=1e-10)
+    torch.cuda.synchronize()
+    w1 = {"lattice": list(dims), "nrhs": 1, "apply_ms": round(ms, 4), "gmres_seconds": round(time.time() - t, 4),
+          "gmres_iters": int(st["iters"][0]), "converged": bool(st["converged"].all())}
+    if with_oracle:
+        from oracle import dirac, solve as osolve
+
+        t = time.time()
+        dirac.apply_dw(U, b, 0.1)
+        w1["oracle_apply_s"] = round(time.time() - t, 4)
+        t = time.time()
+        _, ost = osolve.solve(U, b, 0.1, tol=1e-10, restart=30, eo=False)
+        w1["oracle_gmres_s"] = round(time.time() - t, 3)
+        w1["oracle_gmres_iters"] = int(ost.iters[0])
+    out["haar_4x4x4x4"] = w1
+    log(f"4^4: {json.dumps(w1)}")
+
+    dims = (32, 16, 16, 16)
+    v = int(np.prod(dims))
+    U = syn.gauge_field(dims, "near_identity", config=2, eps=EPS)
+    psi = syn.spinor_block(dims, 12, config=2)
+    U64 = torch.from_numpy(U).to(dev)
+    p64 = torch.from_numpy(np.ascontiguousarray(np.moveaxis(psi, 0, -1))).to(dev)
+    pts = []
+    for prec_name, prec, esz in (("f64", lq.F64, 16), ("f32", lq.F32, 8)):
+        Up = U64 if prec == lq.F64 else U64.to(torch.complex64)
+        for n in (1, 4, 12):
+            x = p64[..., :n].contiguous()
+            x = x if prec == lq.F64 else x.to(torch.complex64)
+            y = torch.empty_like(x)
+            tf = timed(lambda: lq.dirac_apply(Up, x, -0.05, layout=lq.LAYOUT2, out=y), 20, 3)
+            xe = x.reshape((v,) + tuple(x.shape[4:]))[: v // 2].contiguous()
+            ye = torch.empty_like(xe)
+            te = timed(lambda: lq.dirac_apply_eo(Up, xe, -0.05, layout=lq.LAYOUT2, out=ye), 20, 3)
+            pts.append({"prec": prec_name, "nrhs": n, "full_ms": round(tf, 4),
+                        "full_gbs": round(bytes_full(v, n, esz) / tf / 1e6, 1), "schur_ms": round(te, 4),
+                        "schur_gbs_two_pass": round(bytes_schur_two_pass(v, n, esz) / te / 1e6, 1),
+                        "working_set_mb": round((bytes_full(v, n, esz)) / 1e6, 1), "cache_resident": True})
+    w2 = {"lattice": list(dims), "applies": pts}
+    b12 = p64.contiguous()
+    for mode in ("f64", "ir-f32"):
+        torch.cuda.synchronize()
+        t = time.time()
+        x, st, rc = lq.gmres_solve(U64, b12, -0.05, layout=lq.LAYOUT2, eo=True, restart=30, tol=1e-10, mode=mode)
+        torch.cuda.synchronize()
+        w2["gmres_" + mode.replace("-", "_")] = {"seconds": round(time.time() - t, 3), "status": int(rc),
+                                                  "iters_max": int(st["iters"].max()),
+                                                  "max_true_relres": float(st["true_relres"].max())}
+    if with_oracle:
+        from oracle import dirac
+
+        t = time.time()
+        dirac.apply_dw(U, psi[:1], -0.05)
+        w2["oracle_apply_s_per_rhs"] = round(time.time() - t, 3)
+    out["near_identity_16x16x16x32"] = w2
+    log(f"16^3x32: GMRES f64 {w2['gmres_f64']['seconds']} s, ir-f32 {w2['gmres_ir_f32']['seconds']} s")
+    return out
+
+
 def autograd_section(lq, syn):
     """Differentiation at 16^3 x 32, nrhs = 8, m0 = 0.05: forward solve, then the
     backward of L = sum_i Re<chi_i, x_i> (adjoint solve, link force, dL/dm0)."""
@@ -441,11 +521,13 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--fast-inputs", action="store_true",
                     help="draw the inputs on the GPU (seeded torch generator) instead of the seeded host "
-                         "recipe; for profiling runs, where values do not matter")
+                         "recipe; for profiling runs, where values do not matter (skips the solver sections, the "
+                         "small workloads and the oracle baseline)")
     ap.add_argument("--no-gmres", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven eight-lattice batch")
     ap.add_argument("--no-clover", action="store_true", help="skip the clover-improved operator")
     ap.add_argument("--no-block", action="store_true", help="skip block GMRES")
+    ap.add_argument("--no-small", action="store_true", help="skip the 4^4 and 16^3 x 32 workloads")
     ap.add_argument("--no-autograd", action="store_true", help="skip the differentiation timing")
     ap.add_argument("--gmres-nrhs", type=int, default=NRHS)
     ap.add_argument("--variant", type=int, default=0, help="Wilson kernel: 0 auto, 1 site, 2 pencil")
@@ -485,6 +567,7 @@ def main():
     v = int(np.prod(DIMS))
     t0 = time.time()
     if args.fast_inputs:
+        args.no_gmres = args.no_block = args.no_small = True
         gen = torch.Generator(device=dev).manual_seed(CONFIG)
         U64 = torch.randn((4,) + DIMS + (3, 3), dtype=torch.complex128, device=dev, generator=gen)
         psi64 = torch.randn(DIMS + (4, 3, NRHS), dtype=torch.complex128, device=dev, generator=gen)
@@ -612,6 +695,29 @@ def main():
     # ------------------------------------------------------------------ GMRES
     if not args.no_gmres:
         result["gmres"] = gmres_section(lq, U64, psi64, args.gmres_nrhs)
+        # time to 1e-10 per rhs at smaller blocks (same lattice, first rhs of the block)
+        gs = []
+        for n in (1, 4):
+            if n >= args.gmres_nrhs:
+                continue
+            bn = psi64[..., :n].contiguous()
+            rec = {"nrhs": n}
+            for mode in ("f64", "ir-f32", "ir-f16"):
+                torch.cuda.synchronize()
+                t = time.time()
+                _, st, rc = lq.gmres_solve(U64, bn, M0, layout=lq.LAYOUT2, restart=30, eo=True, mode=mode, tol=1e-10,
+                                           max_restarts=400, max_outer=60)
+                torch.cuda.synchronize()
+                dt = time.time() - t
+                rec[mode.replace("-", "_")] = {"seconds": round(dt, 3), "seconds_per_rhs": round(dt / n, 4),
+                                               "status": int(rc), "iters_max": int(st["iters"].max())}
+            gs.append(rec)
+            log(f"GMRES nrhs={n}: {json.dumps(rec)}")
+        nb16 = result["gmres"]
+        gs.append({"nrhs": args.gmres_nrhs, **{m.replace("-", "_"): {
+            "seconds": nb16[m]["seconds"], "seconds_per_rhs": round(nb16[m]["seconds"] / args.gmres_nrhs, 4),
+            "status": nb16[m]["status"], "iters_max": nb16[m]["iters_max"]} for m in ("f64", "ir-f32", "ir-f16")}})
+        result["gmres_nrhs_sweep"] = gs
     if not args.no_block and args.gmres_nrhs <= lq.BLOCK_MAX_RHS:
         result["block_gmres"] = block_gmres_section(lq, U64, psi64, args.gmres_nrhs,
                                                     None if args.no_gmres else result["gmres"]["f64"])
@@ -623,6 +729,8 @@ def main():
         result["batch"] = batch_section(lq, syn, max(5, args.steps // 5))
     if not args.no_autograd:
         result["autograd"] = autograd_section(lq, syn)
+    if not args.no_small:
+        result["small_workloads"] = small_section(lq, syn, not args.no_cpu)
 
     # ------------------------------------------------------- oracle baseline
     if not args.no_cpu:
