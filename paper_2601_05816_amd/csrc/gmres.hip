@@ -9,7 +9,13 @@
 //                                  in passes of DOT_KB vectors over w
 //   w -= sum_k h_kj v_k, |w|^2     one fused pass
 //   Givens / gamma / relnorm       one thread per rhs, FP64
-//   v_{j+1} = w / |w|
+//   v_{j+1} = w / |w|              FP64 bases: not a pass of its own; the basis
+//                                  is kept unnormalised, v_k = s_k u_k with a
+//                                  scale s_k per rhs and vector, and the
+//                                  scales enter the coefficients of the next
+//                                  step.  FP32 / FP16 bases are scaled in a
+//                                  pass (unnormalised vectors could leave
+//                                  their range over a cycle).
 // A rhs whose relnorm falls below tol (or whose Krylov space closes) stops
 // taking steps (its lanes are masked) while the others continue; the cycle
 // ends when none is left (the "max over rhs" exit of Algorithm 2).  At the end of a cycle
@@ -36,11 +42,12 @@ typedef cx<double> zd;
 
 // ------------------------------------------------------------ small kernels
 // Start of a cycle: beta = |r|, relative residual against bref, activity,
-// Givens state reset, scale factor 1/beta for v_0.
+// Givens state reset.  lazy: v_0 = sk[0] r with sk[0] = 1/beta (r stays as
+// stored); else scl = 1/beta for an explicit scaling pass and sk[0] = 1.
 __global__ void k_cycle_start(int nrhs, int m, const zd* __restrict__ nrm, const double* __restrict__ bref,
-                              double tol, int fixed, int* __restrict__ live, int* __restrict__ steps,
-                              zd* __restrict__ g, double* __restrict__ scl, double* __restrict__ beta,
-                              int* __restrict__ flags /*[0] active count, [1] nonfinite*/) {
+                              double tol, int fixed, int lazy, int* __restrict__ live, int* __restrict__ steps,
+                              zd* __restrict__ g, double* __restrict__ sk, double* __restrict__ scl,
+                              double* __restrict__ beta, int* __restrict__ flags /*[0] active, [1] nonfinite*/) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nrhs) return;
   const double b = sqrt(nrm[r].re);
@@ -50,6 +57,7 @@ __global__ void k_cycle_start(int nrhs, int m, const zd* __restrict__ nrm, const
   if (!finite) atomicAdd(&flags[1], 1);
   const bool act = finite && bref[r] > 0.0 && b > 0.0 && (fixed || b > tol * bref[r]);
   live[r] = act ? 1 : 0;
+  sk[r] = lazy ? (act ? 1.0 / b : 0.0) : 1.0;
   scl[r] = act ? 1.0 / b : 0.0;
   for (int k = 0; k <= m; ++k) g[(size_t)r * (m + 1) + k] = {0.0, 0.0};
   g[(size_t)r * (m + 1)] = {b, 0.0};
@@ -58,18 +66,31 @@ __global__ void k_cycle_start(int nrhs, int m, const zd* __restrict__ nrm, const
 
 // Column j of the Hessenberg matrix for every live rhs: apply the previous
 // rotations, build the rotation that zeroes h_{j+1,j}, rotate gamma.
+//
+// The basis may be stored unnormalised: v_k = sk[k] u_k.  hcol holds the raw
+// dots d_k = <u_k, w> with w = A u_j, nrm holds |u_{j+1}|^2 of the updated
+// vector u_{j+1} = w - sum_k sk[k]^2 d_k u_k; the true entries are
+// h_kj = sk[k] sk[j] d_k and h_{j+1,j} = sk[j] |u_{j+1}|, and
+// sk[j+1] = 1 / |u_{j+1}|.
 __global__ void k_arnoldi_col(int j, int m, int nrhs, const zd* __restrict__ hcol, const zd* __restrict__ nrm,
                               zd* __restrict__ H, double* __restrict__ cs, zd* __restrict__ sn, zd* __restrict__ g,
-                              const double* __restrict__ bref, double tol, int fixed, int* __restrict__ live,
-                              int* __restrict__ steps, double* __restrict__ est, double* __restrict__ scl) {
+                              const double* __restrict__ bref, double tol, int fixed, int lazy,
+                              int* __restrict__ live, int* __restrict__ steps, double* __restrict__ est,
+                              double* __restrict__ sk, double* __restrict__ scl) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nrhs || !live[r]) return;
   zd* Hr = H + (size_t)r * (m + 1) * m;  // H[i][j] at Hr[i*m + j]
   double* c = cs + (size_t)r * m;
   zd* s = sn + (size_t)r * m;
   zd* gr = g + (size_t)r * (m + 1);
-  for (int k = 0; k <= j; ++k) Hr[(size_t)k * m + j] = hcol[(size_t)k * nrhs + r];
-  const double hn = sqrt(nrm[r].re);
+  const double scj = sk[(size_t)j * nrhs + r];
+  for (int k = 0; k <= j; ++k) {
+    const double f = sk[(size_t)k * nrhs + r] * scj;
+    const zd d = hcol[(size_t)k * nrhs + r];
+    Hr[(size_t)k * m + j] = {f * d.re, f * d.im};
+  }
+  const double un = sqrt(nrm[r].re);
+  const double hn = scj * un;
   for (int i = 0; i < j; ++i) {
     const zd a = Hr[(size_t)i * m + j], b = Hr[(size_t)(i + 1) * m + j];
     const zd t1 = {c[i] * a.re + (s[i].re * b.re - s[i].im * b.im), c[i] * a.im + (s[i].re * b.im + s[i].im * b.re)};
@@ -100,8 +121,20 @@ __global__ void k_arnoldi_col(int j, int m, int nrhs, const zd* __restrict__ hco
   steps[r] = j + 1;
   const double rel = hypot(gr[j + 1].re, gr[j + 1].im) / bref[r];
   est[r] = rel;
-  scl[r] = hn > 0.0 ? 1.0 / hn : 0.0;
+  // lazy: v_{j+1} = sk[j+1] u_{j+1}; else the caller scales u_{j+1} by scl
+  sk[(size_t)(j + 1) * nrhs + r] = lazy ? (un > 0.0 ? 1.0 / un : 0.0) : 1.0;
+  scl[r] = un > 0.0 ? 1.0 / un : 0.0;
   if ((!fixed && rel < tol) || hn == 0.0 || !isfinite(rel)) live[r] = 0;
+}
+
+// Coefficients of the fused update u_{j+1} = w - sum_k coef_k u_k for the
+// unnormalised basis: coef_k = sk[k]^2 d_k.
+__global__ void k_cgs_coef(int K, int nrhs, const zd* __restrict__ d, const double* __restrict__ sk,
+                           zd* __restrict__ coef) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= K * nrhs) return;
+  const double f = sk[i] * sk[i];
+  coef[i] = {f * d[i].re, f * d[i].im};
 }
 
 __global__ void k_count_live(int nrhs, const int* __restrict__ live, int* __restrict__ out) {
@@ -114,7 +147,7 @@ __global__ void k_count_live(int nrhs, const int* __restrict__ live, int* __rest
 
 // Back substitution R y = gamma on the rotated triangle, y[k][rhs].
 __global__ void k_lsq(int m, int nrhs, const zd* __restrict__ H, const zd* __restrict__ g,
-                      const int* __restrict__ steps, zd* __restrict__ y) {
+                      const int* __restrict__ steps, const double* __restrict__ sk, zd* __restrict__ y) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nrhs) return;
   const int n = steps[r];
@@ -130,6 +163,12 @@ __global__ void k_lsq(int m, int nrhs, const zd* __restrict__ H, const zd* __res
     const zd d = Hr[(size_t)i * m + i];
     const double den = d.re * d.re + d.im * d.im;
     y[(size_t)i * nrhs + r] = {(acc.re * d.re + acc.im * d.im) / den, (acc.im * d.re - acc.re * d.im) / den};
+  }
+  // coefficients of the stored (unnormalised) basis vectors: v_i = sk[i] u_i
+  for (int i = 0; i < n; ++i) {
+    const double f = sk[(size_t)i * nrhs + r];
+    zd& yi = y[(size_t)i * nrhs + r];
+    yi = {f * yi.re, f * yi.im};
   }
 }
 
@@ -402,7 +441,8 @@ struct Solver {
   void* tmplo;                    // odd temporary in the working precision (eo)
   void* rlo;                      // inner rhs (refinement modes)
   void* dlo;                      // inner solution (refinement modes)
-  zd *part, *hcol, *nrm, *H, *sn, *g, *y;
+  zd *part, *hcol, *coef, *nrm, *H, *sn, *g, *y;
+  double* sk;  // per basis vector and rhs: v_k = sk[k] u_k (the stored vectors are unnormalised)
   double *cs, *bref, *ibref, *beta, *scl, *est, *fin, *fout, *rel;
   int *live, *steps, *flags, *nlive;
   // block GMRES (one block Krylov space for all rhs): block Hessenberg
@@ -436,6 +476,8 @@ struct Solver {
     Cilo = (clov && eo && mode) ? a.take(V * 42 * esize(pw)) : nullptr;
     part = (zd*)a.take((size_t)nblk * DOT_KB * nrhs * sizeof(zd));
     hcol = (zd*)a.take((size_t)(m + 1) * nrhs * sizeof(zd));
+    coef = (zd*)a.take((size_t)(m + 1) * nrhs * sizeof(zd));
+    sk = (double*)a.take((size_t)(m + 1) * nrhs * sizeof(double));
     nrm = (zd*)a.take((size_t)nrhs * sizeof(zd));
     H = (zd*)a.take((size_t)nrhs * (m + 1) * m * sizeof(zd));
     sn = (zd*)a.take((size_t)nrhs * m * sizeof(zd));
@@ -608,14 +650,17 @@ static hipError_t arnoldi_step(Group& G, int prec, int j, double sc, double tol,
       if ((e = dot_parts(prec, S.basis, nel, k0, K, w, nel, S.nrhs, S.live, S.part, S.nblk, s)) != hipSuccess) return e;
       if ((e = reduce_parts(S.part, S.nblk, K, S.nrhs, sc, S.hcol + (size_t)k0 * S.nrhs, s)) != hipSuccess) return e;
     }
-    if ((e = cgs_update(prec, S.basis, nel, j + 1, S.hcol, w, nel, S.nrhs, S.live, S.part, S.nblk, s)) != hipSuccess)
+    const int nc = (j + 1) * S.nrhs;
+    hipLaunchKernelGGL(k_cgs_coef, dim3((nc + 255) / 256), dim3(256), 0, s, j + 1, S.nrhs, S.hcol, S.sk, S.coef);
+    if ((e = cgs_update(prec, S.basis, nel, j + 1, S.coef, w, nel, S.nrhs, S.live, S.part, S.nblk, s)) != hipSuccess)
       return e;
     if ((e = reduce_parts(S.part, (int)cgs_update_parts(prec, nel, S.nrhs, S.nblk), 1, S.nrhs, sc, S.nrm, s)) !=
         hipSuccess)
       return e;
+    const int lazy = prec == LQCD_F64;
     hipLaunchKernelGGL(k_arnoldi_col, dim3(S.small_grid()), dim3(64), 0, s, j, m, S.nrhs, S.hcol, S.nrm, S.H, S.cs,
-                       S.sn, S.g, t.bref, tol, fixed, S.live, S.steps, S.est, S.scl);
-    if ((e = scale_rhs(prec, w, nel, S.nrhs, S.scl, S.live, s)) != hipSuccess) return e;
+                       S.sn, S.g, t.bref, tol, fixed, lazy, S.live, S.steps, S.est, S.sk, S.scl);
+    if (!lazy && (e = scale_rhs(prec, w, nel, S.nrhs, S.scl, S.live, s)) != hipSuccess) return e;
   }
   return hipGetLastError();
 }
@@ -668,7 +713,7 @@ static int run_gmres(Group& G, int prec, double tol, int max_cycles, int fixed, 
       Solver& S = G.T[k].S;
       HIPCHK(hipMemsetAsync(S.flags, 0, 2 * sizeof(int), s));
       hipLaunchKernelGGL(k_cycle_start, dim3(S.small_grid()), dim3(64), 0, s, S.nrhs, m, S.nrm, G.T[k].bref, tol,
-                         fixed, S.live, S.steps, S.g, S.scl, S.beta, S.flags);
+                         fixed, prec == LQCD_F64, S.live, S.steps, S.g, S.sk, S.scl, S.beta, S.flags);
       HIPCHK(hipMemcpyAsync(&fl[2 * k], S.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
     }
     HIPCHK(hipStreamSynchronize(s));
@@ -682,7 +727,7 @@ static int run_gmres(Group& G, int prec, double tol, int max_cycles, int fixed, 
       std::vector<int> lv(t.S.nrhs);
       HIPCHK(hipMemcpy(lv.data(), t.S.live, t.S.nrhs * sizeof(int), hipMemcpyDeviceToHost));
       for (int r = 0; r < t.S.nrhs; ++r) t.hs.restarts[r] += lv[r];
-      HIPCHK(scale_rhs(prec, t.S.Vk(prec, 0), t.S.nelem, t.S.nrhs, t.S.scl, t.S.live, s));
+      if (prec != LQCD_F64) HIPCHK(scale_rhs(prec, t.S.Vk(prec, 0), t.S.nelem, t.S.nrhs, t.S.scl, t.S.live, s));
     }
     for (int j = 0; j < m; ++j) {
       HIPCHK(run_step(G, prec, j, sc, tol, fixed));
@@ -707,7 +752,7 @@ static int run_gmres(Group& G, int prec, double tol, int max_cycles, int fixed, 
     for (int k = 0; k < nt; ++k) {
       Task& t = G.T[k];
       Solver& S = t.S;
-      hipLaunchKernelGGL(k_lsq, dim3(S.small_grid()), dim3(64), 0, s, m, S.nrhs, S.H, S.g, S.steps, S.y);
+      hipLaunchKernelGGL(k_lsq, dim3(S.small_grid()), dim3(64), 0, s, m, S.nrhs, S.H, S.g, S.steps, S.sk, S.y);
       HIPCHK(lincomb(prec, S.basis, S.nelem, m, S.y, S.steps, prec, t.x, S.nelem, S.nrhs, 1.0, s));
       steps_h[k].resize(S.nrhs);
       est_h[k].resize(S.nrhs);
