@@ -33,7 +33,12 @@ Readings taken where the definition leaves choices:
   norm); the step that found it still enters the least-squares problem (its
   Hessenberg columns are complete), later steps are not taken;
 * each cycle restarts from the true residual B - A X with only the columns
-  that have not converged (converged columns keep their x);
+  that have not converged (converged columns keep their x); if that residual
+  block is itself numerically rank deficient (a diagonal entry of its
+  triangular factor at or below the breakdown threshold, e.g. two equal
+  right-hand sides), the columns at those diagonal entries sit out the cycle
+  (their x is not updated, they are active again at the next restart), one
+  factorisation at a time until the remaining block has full rank;
 * the thresholds are absolute residual norms per column (the caller turns a
   relative tolerance into them), so the full-system reading of the odd-even
   solve carries over unchanged.
@@ -140,11 +145,14 @@ def block_gmres(apply, B: np.ndarray, thresholds: np.ndarray, restart: int = 30,
         if act.size == 0:
             break
         cycles += 1
+        while True:
+            V0, S, deficient = _thin_qr(Rm[:, act])
+            if not deficient:
+                break
+            scale = float(np.max(np.linalg.norm(Rm[:, act], axis=0)))
+            drop = np.abs(np.diag(S)) <= BREAKDOWN * scale
+            act = act[~drop]
         b = act.size
-        V0, S, deficient = _thin_qr(Rm[:, act])
-        if deficient:
-            breakdowns += 1
-            break
         V = [V0]
         Hbar = np.zeros(((m + 1) * b, m * b), dtype=np.complex128)
         G = np.zeros(((m + 1) * b, b), dtype=np.complex128)

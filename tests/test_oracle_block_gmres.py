@@ -118,3 +118,19 @@ def test_zero_and_converged_columns():
     # restarting from the solution: nothing left to do
     x2, st2 = bg.block_gmres(op, B, thr, restart=8, max_restarts=40, x0=x)
     assert st2.steps == 0 and np.array_equal(x2, x)
+
+
+def test_rank_deficient_right_hand_sides():
+    """Two equal right-hand sides make the residual block rank deficient: the
+    dependent column sits out the first cycle and both converge to the same
+    solution (dense LU)."""
+    dims = (2, 2, 2, 4)
+    m0 = 0.1
+    U = syn.gauge_field(dims, "haar", config=39)
+    b = syn.spinor_block(dims, 3, config=39)
+    b[2] = b[0]
+    x, st = bg.block_solve(U, b, m0, tol=1e-11, restart=6, max_restarts=60, eo=False)
+    assert np.all(st.converged)
+    D = dirac.dense(U, m0)
+    want = np.linalg.solve(D, b.reshape(3, -1).T).T.reshape(b.shape)
+    assert np.all(np.linalg.norm((x - want).reshape(3, -1), axis=1) <= 1e-8 * np.linalg.norm(want.reshape(3, -1), axis=1))
