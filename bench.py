@@ -280,10 +280,12 @@ def batch_section(lq, syn, steps):
     # ------------------------------------------------ FP32 apply, one launch vs eight
     probs32 = [(U.to(torch.complex64), b.to(torch.complex64), m0) for U, b, m0 in probs64]
     outs = [torch.empty_like(b) for _, b, _ in probs32]
-    batch_cfg = lq.autotune_batch(probs32, outs, reps=3)
-    t_batch = timed(lambda: lq.dirac_apply_batch(probs32, outs=outs), steps, 2)
+    # per-lattice kernel configurations first: the separate launches use them
+    # directly, the persistent launch takes each lattice's pencil geometry
     for U, b, m0 in probs32:
         lq.autotune(U, b, torch.empty_like(b), m0, layout=lq.LAYOUT2, reps=2)
+    batch_cfg = lq.autotune_batch(probs32, outs, reps=3)
+    t_batch = timed(lambda: lq.dirac_apply_batch(probs32, outs=outs), steps, 2)
     t_seq = timed(lambda: [lq.dirac_apply(U, b, m0, layout=lq.LAYOUT2, out=o) for (U, b, m0), o in zip(probs32, outs)],
                   steps, 2)
     nbytes = sum(bytes_full(int(np.prod(c["dims"])), c["nrhs"], 8) for c in comp)

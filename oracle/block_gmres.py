@@ -29,9 +29,11 @@ Readings taken where the definition leaves choices:
 * a cycle ends after m steps, when every active column's estimate is at or
   below its threshold ("max over rhs" exit, as Algorithm 2), or at a
   breakdown: the new block is numerically rank deficient (a diagonal entry of
-  its triangular factor at or below 1e-12 of the block's largest column
-  norm); the step that found it still enters the least-squares problem (its
-  Hessenberg columns are complete), later steps are not taken;
+  its triangular factor at or below 1e-6 of the block's largest column norm:
+  a Cholesky factorisation of the block's Gram matrix, as the GPU uses,
+  resolves rank only to about the square root of the working precision); the
+  step that found it still enters the least-squares problem (its Hessenberg
+  columns are complete), later steps are not taken;
 * each cycle restarts from the true residual B - A X with only the columns
   that have not converged (converged columns keep their x); if that residual
   block is itself numerically rank deficient (a diagonal entry of its
@@ -55,7 +57,7 @@ import numpy as np
 from . import dirac, evenodd
 from .gmres import _norms
 
-BREAKDOWN = 1e-12
+BREAKDOWN = 1e-6
 
 
 @dataclass
@@ -66,6 +68,7 @@ class BlockStats:
     true_res: np.ndarray       # ||b_q - A x_q|| at exit, per rhs
     est_res: np.ndarray        # last least-squares residual estimate per rhs
     breakdowns: int            # cycles ended by a rank-deficient block
+    iters: np.ndarray = None   # block steps during which each rhs was active
 
 
 def _to_mat(blk: np.ndarray) -> np.ndarray:
@@ -134,6 +137,7 @@ def block_gmres(apply, B: np.ndarray, thresholds: np.ndarray, restart: int = 30,
     X = np.zeros_like(Bm) if x0 is None else _to_mat(x0)
     thr = np.asarray(thresholds, dtype=np.float64).reshape(nrhs)
     est = np.full(nrhs, np.inf)
+    iters = np.zeros(nrhs, dtype=np.int64)
     steps_total, cycles, breakdowns = 0, 0, 0
     for _cycle in range(max_restarts):
         if max_steps is not None and steps_total >= max_steps:
@@ -188,8 +192,9 @@ def block_gmres(apply, B: np.ndarray, thresholds: np.ndarray, restart: int = 30,
             break
         Vm = np.concatenate(V[:done_steps], axis=1)
         X[:, act] = X[:, act] + Vm @ Y
+        iters[act] += done_steps
     true = np.linalg.norm(Bm - _apply_mat(apply, X, shape), axis=0)
-    return _to_blk(X, shape), BlockStats(steps_total, cycles, true <= thr, true, est, breakdowns)
+    return _to_blk(X, shape), BlockStats(steps_total, cycles, true <= thr, true, est, breakdowns, iters)
 
 
 def block_solve(U, b, m0, tol=1e-10, restart=30, max_restarts=200, eo=False, max_steps=None):

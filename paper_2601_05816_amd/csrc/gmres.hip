@@ -230,11 +230,16 @@ __global__ void k_bstart(int b, const zd* __restrict__ nrm, const double* __rest
 
 // G = R^H R for the Gram block G of the active columns (R upper triangular,
 // unit rows and columns for the inactive ones) and Rinv = R^-1.  A pivot at
-// or below 1e-24 of the largest diagonal entry of G (a diagonal entry of R
-// at or below 1e-12 of the largest column norm) marks the block numerically
-// rank deficient: *bad = 1, that pivot's row is left zero and Rinv unset.
-__global__ void k_bchol(int b, const int* __restrict__ act, const zd* __restrict__ G, zd* __restrict__ R,
-                        zd* __restrict__ Rinv, int* __restrict__ bad) {
+// or below 1e-12 of the largest diagonal entry of G (a diagonal entry of R
+// at or below 1e-6 of the largest column norm; the pivots carry rounding
+// errors of the order of 1e-16 of G's diagonal, so a smaller threshold would
+// not see an exactly dependent column) marks the block numerically rank
+// deficient: *bad = 1, that pivot's row is left zero and Rinv unset.
+// With deflate (the residual block at a restart) the first such column is
+// instead taken out of the cycle (act = 0, f = 0) and *bad = 2: the caller
+// zeroes it and factorises again.
+__global__ void k_bchol(int b, int* __restrict__ act, const zd* __restrict__ G, zd* __restrict__ R,
+                        zd* __restrict__ Rinv, int* __restrict__ bad, int deflate, double* __restrict__ f) {
   if (threadIdx.x || blockIdx.x) return;
   double gmax = 0.0;
   for (int q = 0; q < b; ++q)
@@ -248,7 +253,13 @@ __global__ void k_bchol(int b, const int* __restrict__ act, const zd* __restrict
     }
     double d = G[q * b + q].re;
     for (int p = 0; p < q; ++p) d -= R[p * b + q].re * R[p * b + q].re + R[p * b + q].im * R[p * b + q].im;
-    if (!(d > 1e-24 * gmax)) {
+    if (!(d > 1e-12 * gmax)) {
+      if (deflate) {
+        act[q] = 0;
+        f[q] = 0.0;
+        *bad = 2;
+        return;
+      }
       deficient = 1;
       R[q * b + q] = {d > 0.0 ? sqrt(d) : 0.0, 0.0};
       continue;
@@ -801,16 +812,22 @@ static int run_block_gmres(Task& t, double tol, int max_cycles, int fixed, bool 
     HIPCHK(hipStreamSynchronize(s));
     if (st[1]) return fail(LQCD_ERR_NONFINITE, "block gmres: non-finite residual norm");
     if (st[0] == 0) break;
-    for (int q = 0; q < b; ++q) t.hs.restarts[q] += act[q];
-    // thin QR of the residual block: R0 = V_0 S
-    HIPCHK(scale_rhs(LQCD_F64, v0, nel, b, S.fin, nullptr, s));
-    HIPCHK(bgram_parts(v0, 0, 1, v0, nrows, b, S.bpart, S.gblk, s));
-    HIPCHK(reduce_parts(S.bpart, np, 1, (int)bb, 1.0, S.bW, s));
-    hipLaunchKernelGGL(k_bchol, dim3(1), dim3(1), 0, s, b, S.bact, S.bW, S.bR, S.bRi, bad);
+    // thin QR of the residual block R0 = V_0 S; columns that make it rank
+    // deficient (dependent on earlier ones) sit out this cycle, one at a time
     int deficient = 0;
-    HIPCHK(hipMemcpyAsync(&deficient, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    for (int attempt = 0; attempt <= b; ++attempt) {
+      HIPCHK(scale_rhs(LQCD_F64, v0, nel, b, S.fin, nullptr, s));
+      HIPCHK(bgram_parts(v0, 0, 1, v0, nrows, b, S.bpart, S.gblk, s));
+      HIPCHK(reduce_parts(S.bpart, np, 1, (int)bb, 1.0, S.bW, s));
+      hipLaunchKernelGGL(k_bchol, dim3(1), dim3(1), 0, s, b, S.bact, S.bW, S.bR, S.bRi, bad, 1, S.fin);
+      HIPCHK(hipMemcpyAsync(&deficient, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      if (deficient != 2) break;
+    }
+    if (deficient) return fail(LQCD_ERR_NONFINITE, "block gmres: residual block could not be factorised");
+    HIPCHK(hipMemcpyAsync(act.data(), S.bact, b * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    if (deficient) break;  // the residual block itself is rank deficient: nothing to expand
+    for (int q = 0; q < b; ++q) t.hs.restarts[q] += act[q];
     HIPCHK(bgemm(v0, nullptr, 0.0, 1.0, v0, 0, 1, S.bRi, nrows, b, s));
     hipLaunchKernelGGL(k_binit, dim3(4), dim3(256), 0, s, m, b, S.bR, S.bG);
     int steps = 0;
@@ -830,7 +847,7 @@ static int run_block_gmres(Task& t, double tol, int max_cycles, int fixed, bool 
       // thin QR of the new block: w = V_{j+1} R
       HIPCHK(bgram_parts(w, 0, 1, w, nrows, b, S.bpart, S.gblk, s));
       HIPCHK(reduce_parts(S.bpart, np, 1, (int)bb, 1.0, S.bW, s));
-      hipLaunchKernelGGL(k_bchol, dim3(1), dim3(1), 0, s, b, S.bact, S.bW, S.bR, S.bRi, bad);
+      hipLaunchKernelGGL(k_bchol, dim3(1), dim3(1), 0, s, b, S.bact, S.bW, S.bR, S.bRi, bad, 0, S.fin);
       hipLaunchKernelGGL(k_bhess, dim3(1), dim3(64), 0, s, j, m, b, S.bHc, S.bR, S.bH, S.bcs, S.bsn, S.bG, S.bact,
                          t.bref, tol, fixed, S.est, working);
       int fl[2];
