@@ -1,8 +1,8 @@
 """The clover-improved operator D = D_W - C on the GPU against the oracle:
 full apply (three precisions, three layouts, D and D^dagger), the site-local
 inverse of D_oo, and the odd-even Schur complement with a site-dependent
-D_oo; a full-size case checked on sampled sites.  Every test runs with both
-kernel kinds configured (one work item per site and rhs; time-streaming
+D_oo; a full-size case checked on sampled sites.  The apply tests run with
+both kernel kinds configured (one work item per site and rhs; time-streaming
 pencils)."""
 import numpy as np
 import pytest
@@ -22,12 +22,12 @@ def _g5h(x):
     return dirac.apply_gamma5(x.reshape(x.shape[0], -1, 1, 1, 1, 4, 3)).reshape(x.shape)
 
 
-@pytest.fixture(params=[1, 3], ids=["site", "pencil"], autouse=True)
+@pytest.fixture(params=[1, 3], ids=["site", "pencil"])
 def clover_kernel(request, gpu_lib):
-    """Every clover test runs with the plain operator configured for the
+    """The apply tests run with the plain operator configured for the
     one-(site, rhs) kernels and for the time-streaming pencils: the full
     clover apply follows that choice (the odd-even clover passes always take
-    the one-(site, rhs) kernels)."""
+    the one-(site, rhs) kernels).  The solves run with the tuned default."""
     gpu_lib.set_kernel_variant(request.param)
     yield request.param
     gpu_lib.set_kernel_variant(0)
@@ -36,7 +36,7 @@ def clover_kernel(request, gpu_lib):
 @pytest.mark.parametrize("prec", [lq.F64, lq.F32, lq.F16])
 @pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("dagger", [False, True])
-def test_clover_apply_vs_oracle(gpu_lib, prec, layout, dagger):
+def test_clover_apply_vs_oracle(gpu_lib, clover_kernel, prec, layout, dagger):
     dims = (4, 4, 6, 4)
     U = rounded(syn.gauge_field(dims, "haar", config=21), prec)
     cp = rounded(syn.clover_field(dims, config=21, scale=0.4), prec)
@@ -69,7 +69,7 @@ def test_clover_inverse_singular(gpu_lib):
 
 @pytest.mark.parametrize("prec", [lq.F64, lq.F32])
 @pytest.mark.parametrize("layout", [lq.LAYOUT1, lq.LAYOUT2])
-def test_clover_schur_vs_oracle(gpu_lib, prec, layout):
+def test_clover_schur_vs_oracle(gpu_lib, clover_kernel, prec, layout):
     """S and S^dagger = gamma5 S gamma5 with the clover term."""
     dims = (4, 4, 2, 6)
     m0 = -0.2
@@ -88,7 +88,7 @@ def test_clover_schur_vs_oracle(gpu_lib, prec, layout):
         assert np.all(rel_err_per_rhs(got, w) <= TOL[prec] * 4)
 
 
-def test_clover_full_size_sampled(gpu_lib):
+def test_clover_full_size_sampled(gpu_lib, clover_kernel):
     """32^3 x 64, 16 rhs, FP64: sampled sites against the oracle's site-by-site
     Wilson apply minus C(x) psi(x)."""
     import torch
