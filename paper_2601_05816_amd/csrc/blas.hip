@@ -80,6 +80,7 @@ template <int P, int KB>
 __global__ __launch_bounds__(256) void k_dot_parts(const store_t<P>* __restrict__ V, size_t vstride, int k0, int K,
                                                    const store_t<P>* __restrict__ w, size_t nelem, int nrhs,
                                                    const int* __restrict__ live, cx<double>* __restrict__ part) {
+  if (none_live(live, nrhs)) return;
   stride_info s = grid_rhs(nrhs);
   cx<double> acc[KB];
 #pragma unroll
@@ -100,6 +101,7 @@ __global__ __launch_bounds__(256) void k_dot_parts(const store_t<P>* __restrict_
 template <int P>
 __global__ __launch_bounds__(256) void k_norm_parts(const store_t<P>* __restrict__ x, size_t nelem, int nrhs,
                                                     const int* __restrict__ live, cx<double>* __restrict__ part) {
+  if (none_live(live, nrhs)) return;
   stride_info s = grid_rhs(nrhs);
   cx<double> acc[1] = {{0.0, 0.0}};
   const bool on = s.active && (!live || live[s.rhs]);
@@ -117,6 +119,7 @@ __global__ __launch_bounds__(256) void k_cgs_update(const store_t<P>* __restrict
                                                     const cx<double>* __restrict__ h, store_t<P>* __restrict__ w,
                                                     size_t nelem, int nrhs, const int* __restrict__ live,
                                                     cx<double>* __restrict__ part) {
+  if (none_live(live, nrhs)) return;
   stride_info s = grid_rhs(nrhs);
   cx<double> acc[1] = {{0.0, 0.0}};
   const bool on = s.active && (!live || live[s.rhs]);
@@ -158,6 +161,7 @@ __global__ __launch_bounds__(256) void k_cgs_update_c(const store_t<P>* __restri
                                                       const cx<double>* __restrict__ h, store_t<P>* __restrict__ w,
                                                       size_t nelem, int nrhs, int iters,
                                                       const int* __restrict__ live, cx<double>* __restrict__ part) {
+  if (none_live(live, nrhs)) return;
   const int sb = (int)(blockDim.x / nrhs) * nrhs;
   const int tid = threadIdx.x;
   const int rhs = tid % nrhs;
@@ -180,6 +184,7 @@ __global__ __launch_bounds__(256) void k_cgs_update_c(const store_t<P>* __restri
 template <int P>
 __global__ __launch_bounds__(256) void k_scale_c(store_t<P>* __restrict__ x, size_t nelem, int nrhs, int iters,
                                                  const double* __restrict__ s, const int* __restrict__ live) {
+  if (none_live(live, nrhs)) return;
   const int sb = (int)(blockDim.x / nrhs) * nrhs;
   const int tid = threadIdx.x;
   const int rhs = tid % nrhs;
@@ -199,6 +204,7 @@ template <int P>
 __global__ __launch_bounds__(256) void k_bmy(const store_t<P>* __restrict__ b, store_t<P>* __restrict__ y,
                                              size_t nelem, int nrhs, const int* __restrict__ live,
                                              cx<double>* __restrict__ part) {
+  if (none_live(live, nrhs)) return;
   stride_info s = grid_rhs(nrhs);
   cx<double> acc[1] = {{0.0, 0.0}};
   const bool on = s.active && (!live || live[s.rhs]);
@@ -234,6 +240,7 @@ __global__ __launch_bounds__(256) void k_reduce_parts(const cx<double>* __restri
 template <int P>
 __global__ __launch_bounds__(256) void k_scale(store_t<P>* __restrict__ x, size_t nelem, int nrhs,
                                                const double* __restrict__ s, const int* __restrict__ live) {
+  if (none_live(live, nrhs)) return;
   stride_info si = grid_rhs(nrhs);
   if (!si.active || (live && !live[si.rhs])) return;
   const double f = s[si.rhs];

@@ -102,6 +102,7 @@ __global__ __launch_bounds__(256) void k_dot_parts_v(const typename vio<P>::stor
                                                      int k0, int K, const typename vio<P>::store* __restrict__ w,
                                                      size_t nrow, int nrhs, const int* __restrict__ live,
                                                      cx<double>* __restrict__ part) {
+  if (none_live(live, nrhs)) return;
   constexpr int VW = vio<P>::VW;
   typedef typename vio<P>::acc_t A;
   const int G = nrhs / VW;
@@ -145,6 +146,7 @@ __global__ __launch_bounds__(256) void k_cgs_update_v(const typename vio<P>::sto
                                                       int K, const cx<double>* __restrict__ h,
                                                       typename vio<P>::store* __restrict__ w, size_t nrow, int nrhs,
                                                       const int* __restrict__ live, cx<double>* __restrict__ part) {
+  if (none_live(live, nrhs)) return;
   constexpr int VW = vio<P>::VW;
   typedef typename vio<P>::acc_t A;
   const int G = nrhs / VW;
@@ -181,6 +183,7 @@ __global__ __launch_bounds__(256) void k_cgs_update_v(const typename vio<P>::sto
 template <int P>
 __global__ __launch_bounds__(256) void k_scale_v(typename vio<P>::store* __restrict__ x, size_t nrow, int nrhs,
                                                  const double* __restrict__ f, const int* __restrict__ live) {
+  if (none_live(live, nrhs)) return;
   constexpr int VW = vio<P>::VW;
   const int G = nrhs / VW;
   vsched s = vgrid(G);

@@ -203,4 +203,15 @@ __device__ __forceinline__ unsigned xcd_block(unsigned bid, unsigned nblk) {
   return k * q + (k < r ? k : r) + i;
 }
 
+// True when an activity mask is given and no rhs of the block is active (a
+// lattice of a lock-step batch whose rhs have all converged): the BLAS
+// kernels then return at once; their partial sums are only read for active
+// rhs.
+__device__ __forceinline__ bool none_live(const int* __restrict__ live, int nrhs) {
+  if (!live) return false;
+  for (int r = 0; r < nrhs; ++r)
+    if (live[r]) return false;
+  return true;
+}
+
 }  // namespace lq

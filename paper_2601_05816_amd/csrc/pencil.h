@@ -70,8 +70,9 @@ inline int largest_divisor_at_most(int n, int cap) {
 }
 
 // Tile: all of X, then as much of Y and Z as one XCD keeps resident (about
-// 16384 work items); segments: enough work items for several waves of
-// residency on the whole chip.  Entries of c that are > 0 and divide the
+// 16384 work items), but no fewer than eight tiles when the lattice allows;
+// segments: enough work items for several waves of residency on the whole
+// chip.  Entries of c that are > 0 and divide the
 // lattice override the automatic choice.
 inline pencil_geo make_pencil(const lqcd_lattice* lat, int nrhs, bool eo, const kcfg& c) {
   pencil_geo pg;
@@ -82,8 +83,16 @@ inline pencil_geo make_pencil(const lqcd_lattice* lat, int nrhs, bool eo, const 
   const int target_cols = (16384 / nrhs) > 0 ? 16384 / nrhs : 1;
   int rest = target_cols / pg.TX;
   if (rest < 1) rest = 1;
-  int TY = (c.ty > 0 && NY % c.ty == 0) ? c.ty : largest_divisor_at_most(NY, rest);
-  int TZ = (c.tz > 0 && NZ % c.tz == 0) ? c.tz : largest_divisor_at_most(NZ, rest / TY);
+  const bool auto_y = !(c.ty > 0 && NY % c.ty == 0), auto_z = !(c.tz > 0 && NZ % c.tz == 0);
+  int TY = auto_y ? largest_divisor_at_most(NY, rest) : c.ty;
+  int TZ = auto_z ? largest_divisor_at_most(NZ, rest / TY) : c.tz;
+  // automatic tiles: at least one tile per XCD where the lattice allows it
+  // (a small lattice would otherwise fit one tile and leave seven XCDs idle)
+  while ((NY / TY) * (NZ / TZ) < 8) {
+    if (auto_z && TZ > 1 && (TZ >= TY || !auto_y)) TZ = largest_divisor_at_most(NZ, TZ / 2);
+    else if (auto_y && TY > 1) TY = largest_divisor_at_most(NY, TY / 2);
+    else break;
+  }
   pg.TY = TY;
   pg.TZ = TZ;
   pg.NTX = 1;
