@@ -58,3 +58,12 @@ def rel_err_per_rhs(got, want):
     g = got.reshape(n, -1)
     w = want.reshape(n, -1)
     return np.linalg.norm(g - w, axis=1) / np.linalg.norm(w, axis=1)
+
+
+def neighbourhood(coord, dims, lo=-1, hi=1):
+    """Site numbers of the block of offsets lo..hi (per direction) around
+    coord on the periodic lattice dims, in the block's own row-major order."""
+    r = np.arange(lo, hi + 1)
+    offs = np.stack(np.meshgrid(r, r, r, r, indexing="ij"), axis=-1).reshape(-1, 4)
+    pts = (np.asarray(coord)[None, :] + offs) % np.asarray(dims)[None, :]
+    return np.ravel_multi_index(pts.T, dims)

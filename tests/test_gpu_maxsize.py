@@ -9,20 +9,12 @@ import pytest
 import paper_2601_05816_amd as lq
 from oracle import dirac
 
-from helpers import rel_err_per_rhs
+from helpers import neighbourhood, rel_err_per_rhs
 
 pytestmark = pytest.mark.gpu
 
 DIMS = (96, 48, 48, 48)
 NRHS = 16
-
-
-def _neighbourhood(coord):
-    """Site numbers of the 3^4 block centred on coord (periodic), in the
-    block's own row-major order."""
-    offs = np.stack(np.meshgrid(*([np.arange(-1, 2)] * 4), indexing="ij"), axis=-1).reshape(-1, 4)
-    pts = (np.asarray(coord)[None, :] + offs) % np.asarray(DIMS)[None, :]
-    return np.ravel_multi_index(pts.T, DIMS)
 
 
 @pytest.mark.parametrize("prec", [lq.F64, lq.F32])
@@ -44,7 +36,7 @@ def test_max_size_apply_sampled(gpu_lib, prec):
     of = out.reshape(V, 4, 3, NRHS)
     for s in sites:
         coord = np.unravel_index(int(s), DIMS)
-        nb = torch.from_numpy(_neighbourhood(coord)).to("cuda")
+        nb = torch.from_numpy(neighbourhood(coord, DIMS)).to("cuda")
         Ub = Uf[:, nb].cpu().numpy().astype(np.complex128).reshape((4, 3, 3, 3, 3, 3, 3))
         pb = np.moveaxis(pf[nb].cpu().numpy().astype(np.complex128), -1, 0).reshape((NRHS, 3, 3, 3, 3, 4, 3))
         want = dirac.apply_dw_sites(Ub, pb, m0, [40])  # centre (1, 1, 1, 1) of the 3^4 block
