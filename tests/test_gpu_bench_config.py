@@ -123,3 +123,48 @@ def test_schur_apply_benchmark_config(tuned, prec):
         assert np.all(rel_err_per_rhs(got, want) <= TOL[prec]), (s, coord)
     del U, psi_e, out
     torch.cuda.empty_cache()
+
+
+@pytest.fixture(scope="module")
+def bench_system(tuned):
+    """The benchmark's solver inputs: near-identity links (eps = 0.3, config 3)
+    and 16 Gaussian sources on 32^3 x 64, resident on the GPU."""
+    import torch
+
+    import lqcd_synth as syn
+
+    U = torch.from_numpy(syn.gauge_field(DIMS, "near_identity", config=3, eps=0.3)).to("cuda")
+    b = torch.from_numpy(np.ascontiguousarray(np.moveaxis(syn.spinor_block(DIMS, 16, config=3), 0, -1))).to("cuda")
+    yield U, b
+    del U, b
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("mode", ["f64", "ir-f32", "ir-f16"])
+def test_gmres_benchmark_config(bench_system, mode):
+    """Odd-even GMRES(30) to a true relative residual of 1e-10, as timed by
+    the benchmark; the oracle's D_W at sampled sites of x reproduces b there
+    to within the global residual bound 1e-10 ||b|| (per rhs)."""
+    import torch
+
+    U, b = bench_system
+    nrhs = b.shape[-1]
+    x, st, rc = lq.gmres_solve(U, b, M0, layout=lq.LAYOUT2, restart=30, eo=True, mode=mode, tol=1e-10,
+                               max_restarts=400, max_outer=60)
+    assert rc == lq.OK and st["converged"].all() and np.all(st["true_relres"] <= 1e-10)
+    bnorm = torch.linalg.vector_norm(b.reshape(-1, nrhs), dim=0).cpu().numpy()
+    Uf = U.reshape(4, V, 3, 3)
+    xf = x.reshape(V, 4, 3, nrhs)
+    bf = b.reshape(V, 4, 3, nrhs)
+    rng = np.random.default_rng(500)
+    for s in rng.integers(0, V, NSAMPLE):
+        coord = np.unravel_index(int(s), DIMS)
+        nb = torch.from_numpy(neighbourhood(coord, DIMS)).to("cuda")
+        Ub = _host(Uf[:, nb], lq.F64).reshape((4,) + (3,) * 4 + (3, 3))
+        xb = np.moveaxis(_host(xf[nb], lq.F64), -1, 0).reshape((nrhs,) + (3,) * 4 + (4, 3))
+        Dx = dirac.apply_dw_sites(Ub, xb, M0, [40])[:, 0]
+        bs = np.moveaxis(_host(bf[int(s)], lq.F64), -1, 0)
+        r = np.linalg.norm((Dx - bs).reshape(nrhs, -1), axis=1)
+        assert np.all(r <= 1e-10 * bnorm * (1 + 1e-6)), (int(s), r / bnorm)
+    del x
+    torch.cuda.empty_cache()
