@@ -275,7 +275,7 @@ __device__ __forceinline__ void wilson_eo_pn_body(const typename prec_traits<PRE
   }
   const int T = pg.n[0], NZ = pg.n[1], NY = pg.n[2], NX = pg.n[3];
   const int NXh = NX >> 1;
-  const size_t V = pg.V, Vh = V / 2;
+  const size_t V = pg.V;
   const size_t S0 = (size_t)NZ * NY * NX, H0 = S0 / 2;
   const int cs = nrhs;
   auto base = [&](size_t h) { return h * 12u * (size_t)nrhs + (size_t)rhs0; };

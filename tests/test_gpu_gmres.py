@@ -10,7 +10,7 @@ import pytest
 import lqcd_synth as syn
 import paper_2601_05816_amd as lq
 from oracle import closed_forms as cf
-from oracle import dirac, gmres as ogmres, solve as osolve
+from oracle import dirac, gmres as ogmres
 
 from helpers import from_layout_np, rel_err_per_rhs, to_layout_np
 

@@ -1,7 +1,6 @@
 """Pins for the oracle's Wilson-Dirac apply (Sec. III-A.1): gamma algebra,
 field generation, gamma5-hermiticity, gauge covariance, free-field and
 pure-gauge plane waves, the 2^4 spectrum, and a per-site loop evaluation."""
-import itertools
 from math import comb
 
 import numpy as np

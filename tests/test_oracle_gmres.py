@@ -7,7 +7,7 @@ import scipy.sparse.linalg as spla
 
 import lqcd_synth as syn
 from oracle import closed_forms as cf
-from oracle import dirac, evenodd, gmres, solve
+from oracle import dirac, gmres, solve
 
 
 def test_givens_zeroes_second_entry():
