@@ -166,7 +166,19 @@ __global__ __launch_bounds__(256) void k_cgs_update_v(const typename vio<P>::sto
       const size_t e = row * nrhs + (size_t)s.gr * VW;
       cx<double> x[VW];
       vio<P>::load(w + e, x);
-      for (int k = 0; k < K; ++k) {
+      // four basis vectors per round, loads issued together, terms added in
+      // the order k = 0, 1, ..., K-1
+      int k = 0;
+      for (; k + 4 <= K; k += 4) {
+        cx<double> ve[4][VW];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) vio<P>::load(V + (size_t)(k + q) * vstride + e, ve[q]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int v = 0; v < VW; ++v) x[v] = cmadd(x[v], -h[(size_t)(k + q) * nrhs + s.gr * VW + v], ve[q][v]);
+      }
+      for (; k < K; ++k) {
         cx<double> ve[VW];
         vio<P>::load(V + (size_t)k * vstride + e, ve);
 #pragma unroll
