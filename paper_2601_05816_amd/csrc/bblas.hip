@@ -73,13 +73,13 @@ __global__ __launch_bounds__(256) void k_bgram(const zd* V, size_t vstride, int 
 // out[row][c] = alpha Y[row][c] + beta sum_k sum_r V_k[row][r] C_k[r][c]
 // (Y is not read when alpha = 0; out may alias Y or V_0: every wavefront
 // reads its 16-row tile completely before it writes it).  A wavefront works
-// on 16 rows: the tile of V_k is staged in LDS (coalesced loads) and read
-// back as the A operand (i = row, k = r), the coefficients are the B
-// operand (k = r, j = c).
+// on 16 rows: lane l loads the A operand (i = row, k = r) straight from V_k,
+// element (row0 + l % 16, 4 s + l / 16) for the four steps s (independent
+// loads, no staging); the coefficients are the B operand (k = r, j = c),
+// held in LDS.
 template <int KB>
 __global__ __launch_bounds__(256) void k_bgemm(zd* out, const zd* Y, double alpha, double beta, const zd* V,
                                                size_t vstride, int K, const zd* __restrict__ C, size_t nrows, int b) {
-  __shared__ zd tile[4][256];
   __shared__ zd cl[KB][16][16];  // coefficient blocks, zero-padded to 16 x 16
   const int l = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = l & 15, kq = l >> 4;
@@ -89,36 +89,32 @@ __global__ __launch_bounds__(256) void k_bgemm(zd* out, const zd* Y, double alph
     cl[k][r][c] = (k < K && r < b && c < b) ? C[(size_t)k * bb + (size_t)r * b + c] : zd{0.0, 0.0};
   }
   __syncthreads();
-  zd* sh = tile[wave];
   const size_t ntiles = (nrows + 15) / 16;
   for (size_t t = (size_t)blockIdx.x * 4 + wave; t < ntiles; t += (size_t)gridDim.x * 4) {
     const size_t t0 = t * 16;
-    const size_t lim = (nrows - t0 < 16 ? nrows - t0 : 16) * (size_t)b;
+    const bool rok = t0 + col < nrows;  // this lane's A row exists
     d4 dr = {0.0, 0.0, 0.0, 0.0}, di = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
       if (k < K) {
-        const zd* src = V + (size_t)k * vstride + t0 * b;
-        for (int e = l; e < 16 * b; e += 64) sh[e] = (size_t)e < lim ? src[e] : zd{0.0, 0.0};
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const zd* src = V + (size_t)k * vstride + (t0 + col) * b;
+        zd a[4];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
           const int r = 4 * s + kq;
+          a[s] = (rok && r < b) ? src[r] : zd{0.0, 0.0};
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
           if (4 * s < b) {  // uniform: skip steps past the last coefficient row
-            const zd a = r < b ? sh[col * b + r] : zd{0.0, 0.0};
-            const zd c = cl[k][r][col];
+            const zd c = cl[k][4 * s + kq][col];
             // a c = (ar cr - ai ci) + i (ar ci + ai cr)
-            dr = mfma(a.re, c.re, dr);
-            dr = mfma(-a.im, c.im, dr);
-            di = mfma(a.re, c.im, di);
-            di = mfma(a.im, c.re, di);
+            dr = mfma(a[s].re, c.re, dr);
+            dr = mfma(-a[s].im, c.im, dr);
+            di = mfma(a[s].re, c.im, di);
+            di = mfma(a[s].im, c.re, di);
           }
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
     }
 #pragma unroll
