@@ -24,48 +24,53 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
 // parts[p][k][i b + j] = sum over the rows of part p of conj(V_k[row][i]) W[row][j]
 // for k < K; p = 4 * block + wave.  A wavefront takes four rows per step:
 // lane l loads element (row0 + l / 16, l % 16) of V_k and of W, i.e. the A
-// operand V_k^T (i = column of V, k = row) and the B operand W.
-template <int KB>
-__global__ __launch_bounds__(256) void k_bgram(const zd* V, size_t vstride, int K, const zd* W, size_t nrows, int b,
-                                               size_t rows_per_blk,
-                                               zd* __restrict__ parts) {
+// operand V_k^T (i = column of V, k = row) and the B operand W.  K is a
+// template parameter so that the K + 1 loads of a step are unconditional and
+// issue together; SELF (K = 1, V = W) forms W^H W from one load.  Lanes past
+// the last row or column load element 0 (which exists) and zero it.
+template <int K, bool SELF>
+__global__ __launch_bounds__(256) void k_bgram(const zd* V, size_t vstride, const zd* W, size_t nrows, int b,
+                                               size_t rows_per_blk, zd* __restrict__ parts) {
   const int l = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = l & 15, kq = l >> 4;
   const size_t r0 = (size_t)blockIdx.x * rows_per_blk;
   const size_t r1 = r0 + rows_per_blk < nrows ? r0 + rows_per_blk : nrows;
-  d4 hr[KB], hi[KB];
+  d4 hr[K], hi[K];
 #pragma unroll
-  for (int k = 0; k < KB; ++k) {
+  for (int k = 0; k < K; ++k) {
     hr[k] = d4{0.0, 0.0, 0.0, 0.0};
     hi[k] = d4{0.0, 0.0, 0.0, 0.0};
   }
-  const bool self = K == 1 && V == W;  // W^H W: one load serves both operands
   for (size_t q = r0 + 4 * (size_t)wave; q < r1; q += 16) {
     const size_t row = q + kq;
     const bool ok = row < r1 && col < b;
-    const zd w = ok ? W[row * b + col] : zd{0.0, 0.0};
+    const size_t at = ok ? row * b + col : 0;
+    zd w = W[at];
+    zd v[K];
 #pragma unroll
-    for (int k = 0; k < KB; ++k) {
-      if (k < K) {
-        const zd v = self ? w : (ok ? V[(size_t)k * vstride + row * b + col] : zd{0.0, 0.0});
-        // conj(v) w = (vr wr + vi wi) + i (vr wi - vi wr)
-        hr[k] = mfma(v.re, w.re, hr[k]);
-        hr[k] = mfma(v.im, w.im, hr[k]);
-        hi[k] = mfma(v.re, w.im, hi[k]);
-        hi[k] = mfma(-v.im, w.re, hi[k]);
-      }
+    for (int k = 0; k < K; ++k) v[k] = SELF ? w : V[(size_t)k * vstride + at];
+    if (!ok) {
+      w = zd{0.0, 0.0};
+#pragma unroll
+      for (int k = 0; k < K; ++k) v[k] = zd{0.0, 0.0};
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      // conj(v) w = (vr wr + vi wi) + i (vr wi - vi wr)
+      hr[k] = mfma(v[k].re, w.re, hr[k]);
+      hr[k] = mfma(v[k].im, w.im, hr[k]);
+      hi[k] = mfma(v[k].re, w.im, hi[k]);
+      hi[k] = mfma(-v[k].im, w.re, hi[k]);
     }
   }
   const size_t bb = (size_t)b * b;
   zd* out = parts + ((size_t)blockIdx.x * 4 + wave) * K * bb;
 #pragma unroll
-  for (int k = 0; k < KB; ++k) {
-    if (k < K) {
+  for (int k = 0; k < K; ++k) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = kq + 4 * v;
-        if (i < b && col < b) out[(size_t)k * bb + (size_t)i * b + col] = zd{hr[k][v], hi[k][v]};
-      }
+    for (int v = 0; v < 4; ++v) {
+      const int i = kq + 4 * v;
+      if (i < b && col < b) out[(size_t)k * bb + (size_t)i * b + col] = zd{hr[k][v], hi[k][v]};
     }
   }
 }
@@ -145,8 +150,26 @@ hipError_t bgram_parts(const void* V, size_t vstride, int K, const void* W, size
   if (b < 1 || b > 16 || K < 1 || K > BG_KB) return hipErrorInvalidValue;
   size_t rpb = (nrows + nblk - 1) / nblk;
   rpb = (rpb + 15) & ~(size_t)15;
-  hipLaunchKernelGGL((k_bgram<BG_KB>), dim3(nblk), dim3(256), 0, s, (const zd*)V, vstride, K, (const zd*)W, nrows, b,
-                     rpb, (zd*)parts);
+  const zd* Vz = (const zd*)V;
+  const zd* Wz = (const zd*)W;
+  zd* P = (zd*)parts;
+  switch (K) {
+    case 1:
+      if (V == W)
+        hipLaunchKernelGGL((k_bgram<1, true>), dim3(nblk), dim3(256), 0, s, Vz, vstride, Wz, nrows, b, rpb, P);
+      else
+        hipLaunchKernelGGL((k_bgram<1, false>), dim3(nblk), dim3(256), 0, s, Vz, vstride, Wz, nrows, b, rpb, P);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_bgram<2, false>), dim3(nblk), dim3(256), 0, s, Vz, vstride, Wz, nrows, b, rpb, P);
+      break;
+    case 3:
+      hipLaunchKernelGGL((k_bgram<3, false>), dim3(nblk), dim3(256), 0, s, Vz, vstride, Wz, nrows, b, rpb, P);
+      break;
+    default:
+      hipLaunchKernelGGL((k_bgram<4, false>), dim3(nblk), dim3(256), 0, s, Vz, vstride, Wz, nrows, b, rpb, P);
+      break;
+  }
   return hipGetLastError();
 }
 
