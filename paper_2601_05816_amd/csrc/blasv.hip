@@ -97,11 +97,14 @@ __device__ __forceinline__ void vblock_combine(A (&re)[KB][VW], A (&im)[KB][VW],
   }
 }
 
-template <int P, int KB>
+// K (the number of basis vectors, 1..DOT_KB) is a template parameter, so
+// that the K + 1 loads of a row are unconditional and issue together.
+template <int P, int K>
 __global__ __launch_bounds__(256) void k_dot_parts_v(const typename vio<P>::store* __restrict__ V, size_t vstride,
-                                                     int k0, int K, const typename vio<P>::store* __restrict__ w,
+                                                     int k0, const typename vio<P>::store* __restrict__ w,
                                                      size_t nrow, int nrhs, const int* __restrict__ live,
                                                      cx<double>* __restrict__ part) {
+  constexpr int KB = K;
   if (none_live(live, nrhs)) return;
   constexpr int VW = vio<P>::VW;
   typedef typename vio<P>::acc_t A;
@@ -124,17 +127,16 @@ __global__ __launch_bounds__(256) void k_dot_parts_v(const typename vio<P>::stor
       const size_t e = row * nrhs + (size_t)s.gr * VW;
       cx<double> we[VW];
       vio<P>::load(w + e, we);
+      cx<double> ve[KB][VW];
+#pragma unroll
+      for (int q = 0; q < KB; ++q) vio<P>::load(V + (size_t)(k0 + q) * vstride + e, ve[q]);
 #pragma unroll
       for (int q = 0; q < KB; ++q)
-        if (q < K) {
-          cx<double> ve[VW];
-          vio<P>::load(V + (size_t)(k0 + q) * vstride + e, ve);
 #pragma unroll
-          for (int v = 0; v < VW; ++v) {
-            // conj(v) w
-            re[q][v] += (A)(ve[v].re * we[v].re + ve[v].im * we[v].im);
-            im[q][v] += (A)(ve[v].re * we[v].im - ve[v].im * we[v].re);
-          }
+        for (int v = 0; v < VW; ++v) {
+          // conj(v) w
+          re[q][v] += (A)(ve[q][v].re * we[v].re + ve[q][v].im * we[v].im);
+          im[q][v] += (A)(ve[q][v].re * we[v].im - ve[q][v].im * we[v].re);
         }
     }
   }
@@ -271,13 +273,31 @@ int vec_width(int prec, int nrhs) {
     default: return hipErrorInvalidValue;                            \
   }
 
+template <int P>
+static hipError_t dot_v(const void* V, size_t vstride, int k0, int K, const void* w, size_t nrow, int nrhs,
+                        const int* live, void* part, unsigned nblk, hipStream_t s) {
+  typedef const typename vio<P>::store* In;
+#define LQ_DOT_V(KK)                                                                                          \
+  case KK:                                                                                                    \
+    hipLaunchKernelGGL((k_dot_parts_v<P, KK>), dim3(nblk), dim3(256), 0, s, (In)V, vstride, k0, (In)w, nrow, \
+                       nrhs, live, (cx<double>*)part);                                                        \
+    break;
+  switch (K) {
+    LQ_DOT_V(1) LQ_DOT_V(2) LQ_DOT_V(3) LQ_DOT_V(4) LQ_DOT_V(5) LQ_DOT_V(6) LQ_DOT_V(7) LQ_DOT_V(8)
+    LQ_DOT_V(9) LQ_DOT_V(10) LQ_DOT_V(11) LQ_DOT_V(12) LQ_DOT_V(13) LQ_DOT_V(14) LQ_DOT_V(15) LQ_DOT_V(16)
+    default: return hipErrorInvalidValue;
+  }
+#undef LQ_DOT_V
+  return hipGetLastError();
+}
+static_assert(DOT_KB == 16, "dot_v instantiates K = 1..16");
+
 hipError_t dot_parts_v(int prec, const void* V, size_t vstride, int k0, int K, const void* w, size_t nelem, int nrhs,
                        const int* live, void* part, unsigned nblk, hipStream_t s) {
   const size_t nrow = nelem / nrhs;
-  VSWITCH(prec, hipLaunchKernelGGL((k_dot_parts_v<PP, DOT_KB>), dim3(nblk), dim3(256), 0, s,
-                                   (const typename vio<PP>::store*)V, vstride, k0, K,
-                                   (const typename vio<PP>::store*)w, nrow, nrhs, live, (cx<double>*)part));
-  return hipGetLastError();
+  if (prec == LQCD_F32) return dot_v<LQCD_F32>(V, vstride, k0, K, w, nrow, nrhs, live, part, nblk, s);
+  if (prec == LQCD_F16) return dot_v<LQCD_F16>(V, vstride, k0, K, w, nrow, nrhs, live, part, nblk, s);
+  return hipErrorInvalidValue;
 }
 
 hipError_t cgs_update_v(int prec, const void* V, size_t vstride, int K, const void* h, void* w, size_t nelem,
