@@ -18,11 +18,14 @@ struct vio<LQCD_F32> {
   enum { VW = 2 };
   typedef double acc_t;
   typedef float2 store;
-  __device__ static __forceinline__ void load(const float2* p, cx<double> (&o)[2]) {
-    const f4v_t v = *(const f4v_t*)p;
+  typedef f4v_t raw;  // one 16-byte access as loaded
+  typedef double ct;  // dot products: FP64 products of FP32 values (exact)
+  __device__ static __forceinline__ raw load_raw(const float2* p) { return *(const f4v_t*)p; }
+  __device__ static __forceinline__ void unpack(const raw& v, cx<double> (&o)[2]) {
     o[0] = {v.x, v.y};
     o[1] = {v.z, v.w};
   }
+  __device__ static __forceinline__ void load(const float2* p, cx<double> (&o)[2]) { unpack(load_raw(p), o); }
   __device__ static __forceinline__ void save(float2* p, const cx<double> (&o)[2]) {
     f4v_t v = {(float)o[0].re, (float)o[0].im, (float)o[1].re, (float)o[1].im};
     *(f4v_t*)p = v;
@@ -33,11 +36,18 @@ struct vio<LQCD_F16> {
   enum { VW = 4 };
   typedef float acc_t;
   typedef h2_t store;
-  __device__ static __forceinline__ void load(const h2_t* p, cx<double> (&o)[4]) {
-    const h8v_t v = *(const h8v_t*)p;
+  typedef h8v_t raw;  // one 16-byte access as loaded
+  typedef float ct;   // dot products: FP32 products of FP16 values (exact: 11-bit significands)
+  __device__ static __forceinline__ raw load_raw(const h2_t* p) { return *(const h8v_t*)p; }
+  __device__ static __forceinline__ void unpack(const raw& v, cx<double> (&o)[4]) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) o[i] = {(double)(float)v[2 * i], (double)(float)v[2 * i + 1]};
   }
+  __device__ static __forceinline__ void unpack(const raw& v, cx<float> (&o)[4]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) o[i] = {(float)v[2 * i], (float)v[2 * i + 1]};
+  }
+  __device__ static __forceinline__ void load(const h2_t* p, cx<double> (&o)[4]) { unpack(load_raw(p), o); }
   __device__ static __forceinline__ void save(h2_t* p, const cx<double> (&o)[4]) {
     h8v_t v;
 #pragma unroll
@@ -125,19 +135,37 @@ __global__ __launch_bounds__(256) void k_dot_parts_v(const typename vio<P>::stor
   if (on) {
     for (size_t row = s.row0; row < nrow; row += s.rstride) {
       const size_t e = row * nrhs + (size_t)s.gr * VW;
-      cx<double> we[VW];
-      vio<P>::load(w + e, we);
-      cx<double> ve[KB][VW];
+      typedef typename vio<P>::ct C;
+      cx<C> we[VW];
+      vio<P>::unpack(vio<P>::load_raw(w + e), we);
+      // Basis vectors in groups of DG, software-pipelined: the loads of
+      // group g + 1 are issued before the products of group g, and a
+      // scheduling barrier keeps the compiler from hoisting every load to
+      // the top (which overflows the registers for large K).  The loads stay
+      // in their 16-byte form until used.
+      constexpr int DG = 4;
+      typename vio<P>::raw vr[KB];
 #pragma unroll
-      for (int q = 0; q < KB; ++q) vio<P>::load(V + (size_t)(k0 + q) * vstride + e, ve[q]);
+      for (int q = 0; q < DG && q < KB; ++q) vr[q] = vio<P>::load_raw(V + (size_t)(k0 + q) * vstride + e);
 #pragma unroll
-      for (int q = 0; q < KB; ++q)
+      for (int g = 0; g < KB; g += DG) {
 #pragma unroll
-        for (int v = 0; v < VW; ++v) {
-          // conj(v) w
-          re[q][v] += (A)(ve[q][v].re * we[v].re + ve[q][v].im * we[v].im);
-          im[q][v] += (A)(ve[q][v].re * we[v].im - ve[q][v].im * we[v].re);
+        for (int q = g + DG; q < g + 2 * DG && q < KB; ++q)
+          vr[q] = vio<P>::load_raw(V + (size_t)(k0 + q) * vstride + e);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int q = g; q < g + DG && q < KB; ++q) {
+          cx<C> ve[VW];
+          vio<P>::unpack(vr[q], ve);
+#pragma unroll
+          for (int v = 0; v < VW; ++v) {
+            // conj(v) w
+            re[q][v] += (A)(ve[v].re * we[v].re + ve[v].im * we[v].im);
+            im[q][v] += (A)(ve[v].re * we[v].im - ve[v].im * we[v].re);
+          }
         }
+        __builtin_amdgcn_sched_barrier(0);
+      }
     }
   }
   vblock_combine<KB, VW, A>(re, im, K, nrhs, on, part);
