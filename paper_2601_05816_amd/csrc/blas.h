@@ -10,6 +10,9 @@
 namespace lq {
 
 constexpr int DOT_KB = 16;  // dot products computed per pass over w
+// coefficient blocks of at most this many bytes are staged in LDS by the
+// Gram-Schmidt update kernels
+constexpr size_t CGS_LDS_BYTES = 32768;
 
 unsigned reduce_grid(size_t nelem);
 hipError_t dot_parts(int prec, const void* V, size_t vstride, int k0, int K, const void* w, size_t nelem, int nrhs,

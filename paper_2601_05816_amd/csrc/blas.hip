@@ -156,12 +156,20 @@ __device__ __forceinline__ void chunk_combine(cx<double> v, int nrhs, int sb, bo
   }
 }
 
-template <int P>
+// LH: the K x nrhs coefficients are first copied to LDS (dynamic, K nrhs
+// entries), so that the vector-memory pipe carries only basis loads.
+template <int P, bool LH>
 __global__ __launch_bounds__(256) void k_cgs_update_c(const store_t<P>* __restrict__ V, size_t vstride, int K,
                                                       const cx<double>* __restrict__ h, store_t<P>* __restrict__ w,
                                                       size_t nelem, int nrhs, int iters,
                                                       const int* __restrict__ live, cx<double>* __restrict__ part) {
   if (none_live(live, nrhs)) return;
+  extern __shared__ char lds_raw[];
+  cx<double>* hs = reinterpret_cast<cx<double>*>(lds_raw);
+  if (LH) {
+    for (int i = threadIdx.x; i < K * nrhs; i += blockDim.x) hs[i] = h[i];
+    __syncthreads();
+  }
   const int sb = (int)(blockDim.x / nrhs) * nrhs;
   const int tid = threadIdx.x;
   const int rhs = tid % nrhs;
@@ -181,12 +189,13 @@ __global__ __launch_bounds__(256) void k_cgs_update_c(const store_t<P>* __restri
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           a[q] = ldd<P>(V + (size_t)(k + q) * vstride + e);
-          c[q] = h[(size_t)(k + q) * nrhs + rhs];
+          c[q] = LH ? hs[(k + q) * nrhs + rhs] : h[(size_t)(k + q) * nrhs + rhs];
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) v = cmadd(v, -c[q], a[q]);
       }
-      for (; k < K; ++k) v = cmadd(v, -h[(size_t)k * nrhs + rhs], ldd<P>(V + (size_t)k * vstride + e));
+      for (; k < K; ++k)
+        v = cmadd(v, -(LH ? hs[k * nrhs + rhs] : h[(size_t)k * nrhs + rhs]), ldd<P>(V + (size_t)k * vstride + e));
       std_<P>(w + e, v);
       acc.re = fma(v.re, v.re, fma(v.im, v.im, acc.re));
     }
@@ -414,9 +423,16 @@ hipError_t cgs_update(int prec, const void* V, size_t vstride, int K, const void
   if (nrhs <= 256) {
     const int it = chunk_iters(nelem, nrhs, nblk);
     const unsigned nb = cgs_update_parts(prec, nelem, nrhs, nblk);
-    PREC_SWITCH(prec, hipLaunchKernelGGL((k_cgs_update_c<PP>), dim3(nb), dim3(256), 0, s, (const store_t<PP>*)V,
-                                         vstride, K, (const cx<double>*)h, (store_t<PP>*)w, nelem, nrhs, it, live,
-                                         (cx<double>*)part));
+    const size_t hb = (size_t)K * nrhs * sizeof(cx<double>);
+    if (hb <= CGS_LDS_BYTES) {
+      PREC_SWITCH(prec, hipLaunchKernelGGL((k_cgs_update_c<PP, true>), dim3(nb), dim3(256), hb, s,
+                                           (const store_t<PP>*)V, vstride, K, (const cx<double>*)h,
+                                           (store_t<PP>*)w, nelem, nrhs, it, live, (cx<double>*)part));
+    } else {
+      PREC_SWITCH(prec, hipLaunchKernelGGL((k_cgs_update_c<PP, false>), dim3(nb), dim3(256), 0, s,
+                                           (const store_t<PP>*)V, vstride, K, (const cx<double>*)h,
+                                           (store_t<PP>*)w, nelem, nrhs, it, live, (cx<double>*)part));
+    }
     return hipGetLastError();
   }
   PREC_SWITCH(prec, hipLaunchKernelGGL((k_cgs_update<PP>), dim3(nblk), dim3(256), 0, s, (const store_t<PP>*)V,

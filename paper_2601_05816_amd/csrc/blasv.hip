@@ -171,12 +171,20 @@ __global__ __launch_bounds__(256) void k_dot_parts_v(const typename vio<P>::stor
   vblock_combine<KB, VW, A>(re, im, K, nrhs, on, part);
 }
 
-template <int P>
+// LH: the K x nrhs coefficients are first copied to LDS (dynamic, K nrhs
+// entries), so that the vector-memory pipe carries only basis loads.
+template <int P, bool LH>
 __global__ __launch_bounds__(256) void k_cgs_update_v(const typename vio<P>::store* __restrict__ V, size_t vstride,
                                                       int K, const cx<double>* __restrict__ h,
                                                       typename vio<P>::store* __restrict__ w, size_t nrow, int nrhs,
                                                       const int* __restrict__ live, cx<double>* __restrict__ part) {
   if (none_live(live, nrhs)) return;
+  extern __shared__ char lds_raw[];
+  cx<double>* hs = reinterpret_cast<cx<double>*>(lds_raw);
+  if (LH) {
+    for (int i = threadIdx.x; i < K * nrhs; i += blockDim.x) hs[i] = h[i];
+    __syncthreads();
+  }
   constexpr int VW = vio<P>::VW;
   typedef typename vio<P>::acc_t A;
   const int G = nrhs / VW;
@@ -206,13 +214,19 @@ __global__ __launch_bounds__(256) void k_cgs_update_v(const typename vio<P>::sto
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
-          for (int v = 0; v < VW; ++v) x[v] = cmadd(x[v], -h[(size_t)(k + q) * nrhs + s.gr * VW + v], ve[q][v]);
+          for (int v = 0; v < VW; ++v) {
+            const int hi = (k + q) * nrhs + s.gr * VW + v;
+            x[v] = cmadd(x[v], -(LH ? hs[hi] : h[hi]), ve[q][v]);
+          }
       }
       for (; k < K; ++k) {
         cx<double> ve[VW];
         vio<P>::load(V + (size_t)k * vstride + e, ve);
 #pragma unroll
-        for (int v = 0; v < VW; ++v) x[v] = cmadd(x[v], -h[(size_t)k * nrhs + s.gr * VW + v], ve[v]);
+        for (int v = 0; v < VW; ++v) {
+          const int hi = k * nrhs + s.gr * VW + v;
+          x[v] = cmadd(x[v], -(LH ? hs[hi] : h[hi]), ve[v]);
+        }
       }
       vio<P>::save(w + e, x);
 #pragma unroll
@@ -331,9 +345,16 @@ hipError_t dot_parts_v(int prec, const void* V, size_t vstride, int k0, int K, c
 hipError_t cgs_update_v(int prec, const void* V, size_t vstride, int K, const void* h, void* w, size_t nelem,
                         int nrhs, const int* live, void* part, unsigned nblk, hipStream_t s) {
   const size_t nrow = nelem / nrhs;
-  VSWITCH(prec, hipLaunchKernelGGL((k_cgs_update_v<PP>), dim3(nblk), dim3(256), 0, s,
-                                   (const typename vio<PP>::store*)V, vstride, K, (const cx<double>*)h,
-                                   (typename vio<PP>::store*)w, nrow, nrhs, live, (cx<double>*)part));
+  const size_t hb = (size_t)K * nrhs * sizeof(cx<double>);
+  if (hb <= CGS_LDS_BYTES) {
+    VSWITCH(prec, hipLaunchKernelGGL((k_cgs_update_v<PP, true>), dim3(nblk), dim3(256), hb, s,
+                                     (const typename vio<PP>::store*)V, vstride, K, (const cx<double>*)h,
+                                     (typename vio<PP>::store*)w, nrow, nrhs, live, (cx<double>*)part));
+  } else {
+    VSWITCH(prec, hipLaunchKernelGGL((k_cgs_update_v<PP, false>), dim3(nblk), dim3(256), 0, s,
+                                     (const typename vio<PP>::store*)V, vstride, K, (const cx<double>*)h,
+                                     (typename vio<PP>::store*)w, nrow, nrhs, live, (cx<double>*)part));
+  }
   return hipGetLastError();
 }
 
