@@ -229,7 +229,8 @@ def clover_section(lq, syn, U64, psi64, steps):
     out["apply_f64"] = {"full_ms": round(t_full, 4), "full_gbs": round(nb / t_full / 1e6, 1),
                         # + 528 flop per site and rhs: two Hermitian 6x6 block products and the subtraction
                         "full_gflops": round((FLOP_SITE_RHS + 528) * v * NRHS / t_full / 1e6, 1),
-                        "schur_ms": round(t_eo, 4), "kernel": "one (site, rhs) per work item"}
+                        "schur_ms": round(t_eo, 4),
+                        "kernel": "full: time-streaming pencils; Schur: one (site, rhs) per work item"}
     log(f"clover apply FP64 nrhs={NRHS}: full {t_full:.3f} ms ({nb / t_full / 1e6:.0f} GB/s), Schur {t_eo:.3f} ms")
     del eta, ye, xe, Ci
     torch.cuda.empty_cache()
