@@ -443,8 +443,10 @@ def autograd_section(lq, syn):
 
 def profile_only(args):
     """One workload under a profiler: GPU-drawn inputs (timing does not depend
-    on the values), the kernel configurations of the tune file, `--steps`
-    launches after `--warmup`; prints one JSON line of launch times."""
+    on the values; gmres-ir solves on the benchmark's near-identity links,
+    whose iteration counts it reproduces), the kernel configurations of the
+    tune file, `--steps` launches after `--warmup`; prints one JSON line of
+    launch times."""
     import torch
 
     import paper_2601_05816_amd as lq
@@ -498,6 +500,26 @@ def profile_only(args):
             torch.cuda.synchronize()
             out["seconds"].append(round(time.time() - t, 3))
             log(f"block GMRES 100 steps ({'warmup' if i < args.warmup else 'timed'}): {out['seconds'][-1]} s")
+    elif args.only == "gmres-ir":  # refinement solves to 1e-10 on the benchmark's near-identity links
+        import lqcd_synth as syn
+
+        U = torch.from_numpy(syn.gauge_field(DIMS, "near_identity", config=CONFIG, eps=EPS)).to(dev)
+        b = torch.randn(DIMS + (4, 3, NRHS), dtype=torch.complex128, device=dev, generator=g)
+        for mode in ("ir-f16", "ir-f32"):
+            kw = dict(restart=30, eo=True, mode=mode, tol=1e-10, max_restarts=400, max_outer=60)
+            work = torch.empty(lq.gmres_workspace_bytes(DIMS, NRHS, lq.solver_params(**kw)), dtype=torch.uint8,
+                               device=dev)
+            out[mode] = []
+            for i in range(args.warmup + args.steps):
+                torch.cuda.synchronize()
+                t = time.time()
+                _, st, rc = lq.gmres_solve(U, b, M0, layout=lq.LAYOUT2, work=work, **kw)
+                torch.cuda.synchronize()
+                out[mode].append(round(time.time() - t, 3))
+                log(f"{mode} to 1e-10 ({'warmup' if i < args.warmup else 'timed'}): {out[mode][-1]} s, "
+                    f"{int(st['iters'].max())} steps, status {rc}")
+            del work
+            torch.cuda.empty_cache()
     else:  # the paper's fixed protocol: 100 iterations = 10 restarts of 10, odd-even, FP64
         U.mul_(0.3)
         b = torch.randn(DIMS + (4, 3, NRHS), dtype=torch.complex128, device=dev, generator=g)
@@ -542,9 +564,10 @@ def main():
                     help="kernel configurations measured by the autotuner on MI355X (used when present)")
     ap.add_argument("--retune", action="store_true", help="ignore the tune file and autotune every apply")
     ap.add_argument("--save-tune", default="", help="write the autotuner's table here at the end")
-    ap.add_argument("--only", choices=["sweep-f64", "schur-f64", "clover-f64", "gmres-fixed", "block-fixed"],
+    ap.add_argument("--only", choices=["sweep-f64", "schur-f64", "clover-f64", "gmres-fixed", "block-fixed", "gmres-ir"],
                     default="",
-                    help="profiling mode: run one workload only (GPU-drawn inputs, tune file), print its times")
+                    help="profiling mode: run one workload only (GPU-drawn inputs except the near-identity links of "
+                         "gmres-ir, tune file), print its times")
     args = ap.parse_args()
     if args.only:
         if args.gpus != 1:
