@@ -67,3 +67,19 @@ def neighbourhood(coord, dims, lo=-1, hi=1):
     offs = np.stack(np.meshgrid(r, r, r, r, indexing="ij"), axis=-1).reshape(-1, 4)
     pts = (np.asarray(coord)[None, :] + offs) % np.asarray(dims)[None, :]
     return np.ravel_multi_index(pts.T, dims)
+
+
+def apply_gpu(U, psi, m0, layout, prec, dagger=False):
+    """dirac_apply on oracle-shaped host arrays (nrhs first), result back in that shape."""
+    Ud = to_dev(U, prec)
+    pd = to_dev(to_layout_np(psi, layout), prec)
+    out = lq.dirac_apply(Ud, pd, m0, layout=layout, dagger=dagger)
+    return from_layout_np(from_dev(out, prec), layout, 4)
+
+
+def apply_eo_gpu(U, psi_e, m0, layout, prec, dagger=False):
+    """dirac_apply_eo on an oracle-shaped even half-lattice block."""
+    Ud = to_dev(U, prec)
+    pd = to_dev(to_layout_np(psi_e, layout), prec)
+    out = lq.dirac_apply_eo(Ud, pd, m0, layout=layout, dagger=dagger)
+    return from_layout_np(from_dev(out, prec), layout, 1)

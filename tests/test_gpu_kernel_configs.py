@@ -1,0 +1,136 @@
+"""GPU parity of the Wilson kernels in forced launch configurations: pencil
+tiles and t segments, non-temporal stores, the autotuner's choice, the
+LDS-fed FP64 kernel, residency caps and the two-rhs-per-lane FP32 / FP16
+kernels, each against the oracle (tolerances as in test_gpu_apply.py)."""
+import numpy as np
+import pytest
+
+import lqcd_synth as syn
+import paper_2601_05816_amd as lq
+from oracle import dirac, evenodd, geometry
+
+from helpers import apply_eo_gpu as _apply_eo_gpu
+from helpers import apply_gpu as _apply_gpu
+from helpers import from_dev, from_layout_np, rel_err_per_rhs, rounded, to_dev, to_layout_np
+
+pytestmark = pytest.mark.gpu
+
+TOL = {lq.F64: 1e-12, lq.F32: 1e-5, lq.F16: 1e-3}
+LAYOUTS = [lq.RHS_OUTER, lq.LAYOUT1, lq.LAYOUT2]
+
+
+@pytest.fixture(autouse=True)
+def automatic_selection_after(gpu_lib):
+    """Every test forces its own configuration; restore automatic selection."""
+    yield
+    gpu_lib.set_kernel_config(0)
+
+
+@pytest.mark.parametrize("kernel_variant", [2, 3])
+@pytest.mark.parametrize("pencil", [(1, 1, 1), (2, 1, 3), (1, 2, 6), (3, 2, 2), (0, 0, 12)])
+def test_pencil_tilings(gpu_lib, kernel_variant, pencil):
+    """Every tile shape and segment count gives the same result (the mapping
+    of work items to columns, rhs and t segments is a bijection)."""
+    gpu_lib.set_kernel_variant(kernel_variant, pencil)
+    dims = (12, 4, 6, 4)
+    U = syn.gauge_field(dims, "haar", config=9)
+    psi = syn.spinor_block(dims, 5, config=9)
+    for layout in LAYOUTS:
+        got = _apply_gpu(U, psi, 0.2, layout, lq.F64)
+        assert np.all(rel_err_per_rhs(got, dirac.apply_dw(U, psi, 0.2)) <= TOL[lq.F64])
+        psi_e = geometry.to_half(psi, dims, 0)
+        got = _apply_eo_gpu(U, psi_e, 0.2, layout, lq.F64)
+        assert np.all(rel_err_per_rhs(got, evenodd.apply_schur(U, psi_e, 0.2)) <= TOL[lq.F64])
+
+
+@pytest.mark.parametrize("kernel_variant", [2, 3])
+@pytest.mark.parametrize("nt", [0, 1])
+def test_nontemporal_stores_and_autotuned_choice(gpu_lib, kernel_variant, nt):
+    """Non-temporal output stores, and whatever configuration the autotuner
+    records, give the oracle's result."""
+    import torch
+
+    dims = (8, 4, 6, 4)
+    U = syn.gauge_field(dims, "near_identity", config=10)
+    psi = syn.spinor_block(dims, 16, config=10)
+    want = dirac.apply_dw(U, psi, -0.05)
+    gpu_lib.set_kernel_config(kernel_variant, 0, 0, 0, nt)
+    got = _apply_gpu(U, psi, -0.05, lq.LAYOUT2, lq.F64)
+    assert np.all(rel_err_per_rhs(got, want) <= TOL[lq.F64])
+    psi_e = geometry.to_half(psi, dims, 0)
+    got = _apply_eo_gpu(U, psi_e, -0.05, lq.LAYOUT2, lq.F64)
+    assert np.all(rel_err_per_rhs(got, evenodd.apply_schur(U, psi_e, -0.05)) <= TOL[lq.F64])
+    # automatic selection after tuning this exact problem
+    gpu_lib.set_kernel_config(0)
+    gpu_lib.tune_clear()
+    Ud = to_dev(U, lq.F64)
+    pd = to_dev(to_layout_np(psi, lq.LAYOUT2), lq.F64)
+    best = gpu_lib.autotune(Ud, pd, torch.empty_like(pd), layout=lq.LAYOUT2, reps=1)
+    assert best["variant"] in (1, 2, 3, 5) and best["ms"] > 0
+    got = from_layout_np(from_dev(lq.dirac_apply(Ud, pd, -0.05, layout=lq.LAYOUT2), lq.F64), lq.LAYOUT2, 4)
+    assert np.all(rel_err_per_rhs(got, want) <= TOL[lq.F64])
+    gpu_lib.tune_clear()
+
+
+@pytest.mark.parametrize("nrhs", [10, 11, 12, 16, 24, 64])
+@pytest.mark.parametrize("pencil", [(0, 0, 0), (2, 1, 3), (1, 2, 1), (3, 2, 2)])
+def test_lds_fed_full_kernel(gpu_lib, nrhs, pencil):
+    """Variant 5 (spinors and links arrive by global-to-LDS transfers, three
+    hops in flight per wavefront): FP64, rhs-innermost, D and D^dagger, tiles
+    and segment counts that leave wavefronts partly idle."""
+    gpu_lib.set_kernel_config(5, pencil[0], pencil[1], pencil[2], 1)
+    try:
+        dims = (6, 4, 6, 4)
+        U = syn.gauge_field(dims, "haar", config=13)
+        psi = syn.spinor_block(dims, nrhs, config=13)
+        for dagger in (False, True):
+            want = (dirac.apply_dw_dagger if dagger else dirac.apply_dw)(U, psi, -0.3)
+            got = _apply_gpu(U, psi, -0.3, lq.LAYOUT2, lq.F64, dagger)
+            assert np.all(rel_err_per_rhs(got, want) <= TOL[lq.F64])
+        # unsupported combinations fall back to the plain pencil kernel
+        got = _apply_gpu(U, psi[:4], -0.3, lq.LAYOUT2, lq.F64)
+        assert np.all(rel_err_per_rhs(got, dirac.apply_dw(U, psi[:4], -0.3)) <= TOL[lq.F64])
+        got = _apply_gpu(U, psi, -0.3, lq.LAYOUT1, lq.F64)
+        assert np.all(rel_err_per_rhs(got, dirac.apply_dw(U, psi, -0.3)) <= TOL[lq.F64])
+    finally:
+        gpu_lib.set_kernel_config(0)
+
+
+@pytest.mark.parametrize("kernel_variant", [2, 3])
+@pytest.mark.parametrize("occ", [1, 2, 4])
+def test_residency_cap(gpu_lib, kernel_variant, occ):
+    """Capping the workgroups per compute unit (through the LDS request) only
+    changes which workgroups run together, never the result: full and Schur
+    applies, FP64 and FP32 (variant 4 for FP32 in the variant-3 case)."""
+    dims = (8, 4, 6, 4)
+    U = syn.gauge_field(dims, "haar", config=12)
+    psi = syn.spinor_block(dims, 16, config=12)
+    for prec in (lq.F64, lq.F32):
+        v = 4 if (kernel_variant == 3 and prec == lq.F32) else kernel_variant
+        gpu_lib.set_kernel_config(v, 2, 2, 0, 1, occ)
+        Up, pp = rounded(U, prec), rounded(psi, prec)
+        got = _apply_gpu(Up, pp, 0.15, lq.LAYOUT2, prec)
+        assert np.all(rel_err_per_rhs(got, dirac.apply_dw(Up, pp, 0.15)) <= TOL[prec])
+        pe = geometry.to_half(pp, dims, 0)
+        got = _apply_eo_gpu(Up, pe, 0.15, lq.LAYOUT2, prec)
+        assert np.all(rel_err_per_rhs(got, evenodd.apply_schur(Up, pe, 0.15)) <= TOL[prec] * 2)
+    gpu_lib.set_kernel_config(0)
+
+
+@pytest.mark.parametrize("prec", [lq.F32, lq.F16])
+@pytest.mark.parametrize("nrhs", [2, 6, 16])
+@pytest.mark.parametrize("pencil", [(0, 0, 0), (2, 1, 3), (1, 2, 1)])
+def test_two_rhs_per_lane_kernels(gpu_lib, prec, nrhs, pencil):
+    """Variant 4 (two rhs per work item, vector loads) for FP32 and FP16, full
+    and Schur applies, D and D^dagger, several tilings."""
+    gpu_lib.set_kernel_variant(4, pencil)
+    dims = (6, 4, 6, 4)
+    U = rounded(syn.gauge_field(dims, "haar", config=11), prec)
+    psi = rounded(syn.spinor_block(dims, nrhs, config=11), prec)
+    for dagger in (False, True):
+        want = (dirac.apply_dw_dagger if dagger else dirac.apply_dw)(U, psi, 0.1)
+        got = _apply_gpu(U, psi, 0.1, lq.LAYOUT2, prec, dagger)
+        assert np.all(rel_err_per_rhs(got, want) <= TOL[prec])
+    psi_e = geometry.to_half(psi, dims, 0)
+    got = _apply_eo_gpu(U, psi_e, 0.1, lq.LAYOUT2, prec)
+    assert np.all(rel_err_per_rhs(got, evenodd.apply_schur(U, psi_e, 0.1)) <= TOL[prec] * 2)
