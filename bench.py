@@ -569,15 +569,13 @@ def main():
                     help="profiling mode: run one workload only (GPU-drawn inputs except the near-identity links of "
                          "gmres-ir, tune file), print its times")
     args = ap.parse_args()
-    if args.only:
-        if args.gpus != 1:
-            sys.exit(2)
-        profile_only(args)
-        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the multi-rhs apply and GMRES are single-device here "
               "(rhs or lattice sharding across GPUs is not built)", file=sys.stderr)
         sys.exit(2)
+    if args.only:
+        profile_only(args)
+        return
 
     import torch
 
