@@ -283,7 +283,20 @@ __global__ __launch_bounds__(256) void k_lincomb(const store_t<P>* __restrict__ 
   if (n == 0) return;
   for (size_t e = si.t; e < nelem; e += si.stride) {
     cx<double> acc = {0.0, 0.0};
-    for (int k = 0; k < n; ++k) acc = cmadd(acc, y[(size_t)k * nrhs + si.rhs], ldd<P>(V + (size_t)k * vstride + e));
+    // four basis vectors per round (loads issued together, terms added in
+    // the order k = 0, 1, ..., n-1)
+    int k = 0;
+    for (; k + 4 <= n; k += 4) {
+      cx<double> a[4], c[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        a[q] = ldd<P>(V + (size_t)(k + q) * vstride + e);
+        c[q] = y[(size_t)(k + q) * nrhs + si.rhs];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc = cmadd(acc, c[q], a[q]);
+    }
+    for (; k < n; ++k) acc = cmadd(acc, y[(size_t)k * nrhs + si.rhs], ldd<P>(V + (size_t)k * vstride + e));
     cx<double> v = ldd<PX>(x + e);
     std_<PX>(x + e, cx<double>{fma(scale, acc.re, v.re), fma(scale, acc.im, v.im)});
   }

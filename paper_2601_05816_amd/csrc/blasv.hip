@@ -286,7 +286,23 @@ __global__ __launch_bounds__(256) void k_lincomb_v(const typename vio<P>::store*
     cx<double> acc[VW];
 #pragma unroll
     for (int v = 0; v < VW; ++v) acc[v] = {0.0, 0.0};
-    for (int k = 0; k < nmax; ++k) {
+    // four basis vectors per round (loads issued together, in their 16-byte
+    // form; terms added in the order k = 0, 1, ...)
+    int k = 0;
+    for (; k + 4 <= nmax; k += 4) {
+      typename vio<P>::raw vr[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) vr[q] = vio<P>::load_raw(V + (size_t)(k + q) * vstride + e);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        cx<double> ve[VW];
+        vio<P>::unpack(vr[q], ve);
+#pragma unroll
+        for (int v = 0; v < VW; ++v)
+          if (k + q < n[v]) acc[v] = cmadd(acc[v], y[(size_t)(k + q) * nrhs + s.gr * VW + v], ve[v]);
+      }
+    }
+    for (; k < nmax; ++k) {
       cx<double> ve[VW];
       vio<P>::load(V + (size_t)k * vstride + e, ve);
 #pragma unroll
