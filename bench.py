@@ -7,10 +7,15 @@ links U = exp(i 0.3 H), m0 = -0.05, rhs-innermost layout), inputs resident in
 HBM.  Reported value: nominal GFLOP/s (1392 flop per site and rhs).  The JSON
 line also carries the roofline of the kernel (algorithmic HBM bytes
 (36 + 24 nrhs) x 16 per site over the measured launch time), an nrhs sweep in
-FP64/FP32/FP16 for the full and the Schur (odd-even) apply, and the oracle's
-CPU throughput on one rhs.
+FP64/FP32/FP16 for the full and the Schur (odd-even) apply, the solvers
+(FP64 GMRES against FP32 / FP16 refinement to a true residual of 1e-10, the
+fixed 100-iteration protocol, block GMRES, the clover operator, the uneven
+multi-lattice batch, differentiation, small lattices) and the oracle's CPU
+throughput on a sample of the same apply (two of the 16 rhs).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-sweep] [--no-cpu]
+    python bench.py --only {sweep-f64,schur-f64,clover-f64,gmres-fixed,block-fixed,gmres-ir}
+                                    (one workload, for profilers)
 """
 from __future__ import annotations
 
