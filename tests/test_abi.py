@@ -101,3 +101,23 @@ def test_block_gmres_rejects_bad_arguments_on_host():
                                  None, None) == -1
     assert lib.block_gmres_solve(ctypes.byref(good), 1, 1, 1, 4, 0.1, lq.LAYOUT2, ctypes.byref(p), 1, 16,
                                  None, None) == -6
+
+
+def test_shipped_tune_table_loads_completely():
+    """Every entry of the MI355X tune table the benchmark loads is accepted
+    by the parser (a malformed line would be skipped silently and its
+    problem would fall back to the default kernel)."""
+    import os
+
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2601_05816_amd",
+                        "tune_mi355x.txt")
+    entries = [l for l in open(path).read().splitlines() if l.strip() and not l.startswith("#")]
+    lq.load()
+    lq.tune_clear()
+    try:
+        assert lq.tune_load(path) == len(entries)
+        for l in entries:
+            cfg = l.split(":")[1].split()
+            assert 1 <= int(cfg[0]) <= 5 and 0 <= int(cfg[5]) <= 8 and float(cfg[6]) > 0
+    finally:
+        lq.tune_clear()
