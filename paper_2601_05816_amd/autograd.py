@@ -8,11 +8,14 @@ WilsonApply  y = D psi
                                     equal to gamma5 D gamma5 g)
     grad_U   = link_force(g, psi, coeff = -1/2)
     grad_m0  = Re <g, psi>         (block_dot)
-WilsonSolve  x = D^-1 eta  (batched GMRES)
-    lambda   = D^-dagger g         (the adjoint solve, gmres_solve with dagger)
+WilsonSolve  x = A^-1 eta, A = D (or D^dagger with dagger=True; batched GMRES)
+    lambda   = A^-dagger g         (the adjoint solve: gmres_solve with the
+                                    opposite dagger flag)
     grad_eta = lambda
-    grad_U   = link_force(lambda, x, coeff = +1/2)
-    grad_m0  = -Re <lambda, x>
+    grad_U   = link_force(lambda, x, coeff = +1/2) for A = D; for A = D^dagger
+               dL = -Re <lambda, dD^dagger x> = -Re <x, dD lambda>, i.e.
+               link_force(x, lambda, coeff = +1/2)
+    grad_m0  = -Re <lambda, x>     (dA/dm0 = 1 either way)
 
 Blocks are FP64 full-lattice tensors in the rhs-innermost layout
 [N0, N1, N2, N3, 4, 3, nrhs]; U is [4, N0, N1, N2, N3, 3, 3].
@@ -72,12 +75,14 @@ class WilsonSolve(torch.autograd.Function):
     def backward(ctx, g):
         U, x = ctx.saved_tensors
         kw = dict(ctx.kw)
-        kw.pop("dagger", None)
+        fwd_dagger = bool(kw.pop("dagger", False))
         kw.pop("x_is_guess", None)
-        lam, st, rc = gmres_solve(U, g.contiguous(), ctx.m0, layout=LAYOUT2, dagger=True, **kw)
+        lam, st, rc = gmres_solve(U, g.contiguous(), ctx.m0, layout=LAYOUT2, dagger=not fwd_dagger, **kw)
         if rc == NOT_CONVERGED:
             raise RuntimeError(f"WilsonSolve backward: adjoint GMRES did not converge ({st['true_relres']})")
-        gU = link_force(U, lam, x, 0.5) if ctx.needs_input_grad[0] else None
+        gU = None
+        if ctx.needs_input_grad[0]:
+            gU = link_force(U, x, lam, 0.5) if fwd_dagger else link_force(U, lam, x, 0.5)
         gm0 = -block_dot(lam, x, _dims(U)).real.sum() if ctx.needs_input_grad[2] else None
         return gU, lam, gm0, None
 

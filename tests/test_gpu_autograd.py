@@ -80,14 +80,19 @@ def test_apply_gradients_vs_oracle_and_gradcheck(gpu_lib):
     assert torch.autograd.gradcheck(lambda u, p: wilson_apply(u, p, 0.3), (Us, ps), eps=1e-6, atol=1e-7)
 
 
-def _dense_loss(U, eta, chi, m0):
+def _dense_loss(U, eta, chi, m0, dagger=False):
     D = dirac.dense(U, m0)
+    if dagger:
+        D = D.conj().T
     n = eta.shape[0]
     x = np.linalg.solve(D, eta.reshape(n, -1).T).T.reshape(eta.shape)
     return float(np.real(np.vdot(chi, x)))
 
 
-def test_solve_gradients_fd_4x4x4x4(gpu_lib):
+@pytest.mark.parametrize("dagger", [False, True])
+def test_solve_gradients_fd_4x4x4x4(gpu_lib, dagger):
+    """x = A^-1 eta with A = D or D^dagger: the gradients of L = Re <chi, x>
+    against central differences of the dense-LU loss."""
     import torch
 
     from paper_2601_05816_amd.autograd import wilson_solve
@@ -100,7 +105,7 @@ def test_solve_gradients_fd_4x4x4x4(gpu_lib):
     Ut = _dev(U).requires_grad_()
     et = _dev(_l2(eta)).requires_grad_()
     mt = torch.tensor(m0, dtype=torch.float64, device="cuda", requires_grad=True)
-    x = wilson_solve(Ut, et, mt, tol=1e-13, eo=True)
+    x = wilson_solve(Ut, et, mt, tol=1e-13, eo=True, dagger=dagger)
     loss = torch.real(torch.sum(torch.conj(_dev(_l2(chi))) * x))
     loss.backward()
     gU = Ut.grad.cpu().numpy()
@@ -111,14 +116,17 @@ def test_solve_gradients_fd_4x4x4x4(gpu_lib):
         for unit in (1.0, 1j):
             up = flat.copy(); up[k] += h * unit
             um = flat.copy(); um[k] -= h * unit
-            fd = (_dense_loss(up.reshape(U.shape), eta, chi, m0) - _dense_loss(um.reshape(U.shape), eta, chi, m0)) / (2 * h)
+            fd = (_dense_loss(up.reshape(U.shape), eta, chi, m0, dagger)
+                  - _dense_loss(um.reshape(U.shape), eta, chi, m0, dagger)) / (2 * h)
             an = gU.reshape(-1)[k].real if unit == 1.0 else gU.reshape(-1)[k].imag
             assert abs(fd - an) < 1e-6 * max(1.0, abs(an)), (k, unit, fd, an)
-    fd = (_dense_loss(U, eta, chi, m0 + h) - _dense_loss(U, eta, chi, m0 - h)) / (2 * h)
+    fd = (_dense_loss(U, eta, chi, m0 + h, dagger) - _dense_loss(U, eta, chi, m0 - h, dagger)) / (2 * h)
     assert abs(fd - float(mt.grad)) < 1e-6 * max(1.0, abs(fd))
-    # grad_eta = lambda = D^-dagger chi
-    D = dirac.dense(U, m0)
-    lam = np.linalg.solve(D.conj().T, chi.reshape(2, -1).T).T.reshape(chi.shape)
+    # grad_eta = lambda = A^-dagger chi
+    A = dirac.dense(U, m0)
+    if dagger:
+        A = A.conj().T
+    lam = np.linalg.solve(A.conj().T, chi.reshape(2, -1).T).T.reshape(chi.shape)
     assert np.all(rel_err_per_rhs(_from_l2(et.grad), lam) < 1e-10)
 
 
