@@ -83,7 +83,7 @@ def test_layouts_bitwise_identical_and_deterministic(gpu_lib):
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
-@pytest.mark.parametrize("prec", [lq.F64, lq.F32])
+@pytest.mark.parametrize("prec", [lq.F64, lq.F32, lq.F16])
 @pytest.mark.parametrize("dagger", [False, True])
 def test_schur_apply(gpu_lib, layout, prec, dagger):
     dims = (4, 4, 6, 4)

@@ -74,6 +74,44 @@ def test_batch_composition_matches_single_applies(gpu_lib):
         assert torch.all(d <= 1e-6 * torch.linalg.vector_norm(b.reshape(-1, b.shape[-1]), dim=0))
 
 
+@pytest.mark.parametrize("kind", [1, 2])
+def test_batch_composition_matches_oracle(gpu_lib, kind):
+    """The eight-lattice composition (L = 8..24, T = 2L, 1..32 rhs, FP32) in
+    one persistent launch against the oracle: at sampled sites of every
+    lattice, D_W evaluated by the oracle on the 3^4 neighbourhood gathered
+    around the site (D_W reads only nearest neighbours) from the FP32 values
+    the GPU read."""
+    import torch
+
+    from helpers import neighbourhood
+
+    comp = syn.batch_composition()
+    probs = []
+    gen = torch.Generator(device="cuda").manual_seed(41)
+    for c in comp:
+        dims = c["dims"]
+        U = torch.randn((4,) + dims + (3, 3), dtype=torch.complex64, device="cuda", generator=gen)
+        psi = torch.randn(dims + (4, 3, c["nrhs"]), dtype=torch.complex64, device="cuda", generator=gen)
+        probs.append((U, psi, -0.05))
+    gpu_lib.set_batch_kernel(kind)
+    outs = lq.dirac_apply_batch(probs)
+    gpu_lib.set_batch_kernel(0)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(42)
+    for (U, psi, m0), out, c in zip(probs, outs, comp):
+        dims, n = c["dims"], c["nrhs"]
+        v = int(np.prod(dims))
+        Uf, pf, of = U.reshape(4, v, 3, 3), psi.reshape(v, 4, 3, n), out.reshape(v, 4, 3, n)
+        for s in rng.integers(0, v, 4):
+            coord = np.unravel_index(int(s), dims)
+            nb = torch.from_numpy(neighbourhood(coord, dims)).to("cuda")
+            Ub = Uf[:, nb].cpu().numpy().astype(np.complex128).reshape((4,) + (3,) * 4 + (3, 3))
+            pb = np.moveaxis(pf[nb].cpu().numpy().astype(np.complex128), -1, 0).reshape((n,) + (3,) * 4 + (4, 3))
+            want = dirac.apply_dw_sites(Ub, pb, m0, [40])
+            got = np.moveaxis(of[int(s)].cpu().numpy().astype(np.complex128), -1, 0)[:, None]
+            assert np.all(rel_err_per_rhs(got, want) <= TOL[lq.F32]), (dims, int(s))
+
+
 @pytest.mark.parametrize("mode", ["f64", "ir-f32"])
 @pytest.mark.parametrize("graph", [False, True])
 @pytest.mark.parametrize("kind", [1, 2])

@@ -95,8 +95,11 @@ def test_full_apply_benchmark_config(tuned, prec, nrhs):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("prec", [lq.F64, lq.F32])
+@pytest.mark.parametrize("prec", [lq.F64, lq.F32, lq.F16])
 def test_schur_apply_benchmark_config(tuned, prec):
+    """Schur apply at 16 rhs in the tuned configuration (FP16: the kernel the
+    timed FP16-storage refinement solve runs), FP16 against the oracle on the
+    FP16 values the GPU reads."""
     import torch
 
     nrhs = 16
@@ -108,7 +111,7 @@ def test_schur_apply_benchmark_config(tuned, prec):
     bd = (6, 6, 6, 6)
     centre = int(geometry.site_index(np.array([2, 2, 2, 2]), bd))
     rng = np.random.default_rng(400 + prec)
-    Uf = U.reshape(4, V, 3, 3)
+    Uf = U.reshape((4, V, 3, 3) + ((2,) if prec == lq.F16 else ()))
     for s in _sites_of_parity(rng, 0, NSAMPLE):
         coord = np.unravel_index(s, DIMS)
         nb = neighbourhood(coord, DIMS, -2, 3)
