@@ -79,6 +79,10 @@ __device__ __forceinline__ cx<float> ld(const h2_t* p) {
   h2_t v = *p;
   return {(float)v.x, (float)v.y};
 }
+// the same for a value already in registers
+__device__ __forceinline__ cx<double> widen(double2 v) { return {v.x, v.y}; }
+__device__ __forceinline__ cx<float> widen(float2 v) { return {v.x, v.y}; }
+__device__ __forceinline__ cx<float> widen(h2_t v) { return {(float)v.x, (float)v.y}; }
 __device__ __forceinline__ void st(double2* p, cx<double> a) { *p = make_double2(a.re, a.im); }
 __device__ __forceinline__ void st(float2* p, cx<float> a) { *p = make_float2(a.re, a.im); }
 __device__ __forceinline__ void st(h2_t* p, cx<float> a) {

@@ -22,7 +22,9 @@ hipError_t wilson_eo(const lqcd_lattice* lat, const void* U, const void* in, con
 // item, 2 time-streaming pencils with links staged in LDS, 3 pencils without
 // staging, 4 pencils with two rhs per work item (FP32/FP16, rhs-innermost,
 // even nrhs; otherwise treated as 3), 5 pencils fed by global-to-LDS loads
-// (FP64, rhs-innermost, nrhs >= 11, full operator; otherwise treated as 3); ty, tz, nseg: pencil tile and t segments
+// (FP64, rhs-innermost, nrhs >= 11, full operator; otherwise treated as 3), 6 pencils whose links
+// reach the rhs lanes of a column by row broadcasts (rhs-fastest layouts, nrhs % 16 == 0; otherwise
+// treated as 3); ty, tz, nseg: pencil tile and t segments
 // (0 = automatic); nt: non-temporal output stores; occ: at most this many
 // workgroups per compute unit (0 = no cap), enforced through the LDS request.
 struct kcfg {
@@ -56,6 +58,15 @@ hipError_t wilson_full_nr(const lqcd_lattice* lat, const void* U, const void* ps
 bool dma_supported(int prec, int layout, int nrhs);
 hipError_t wilson_full_dma(const lqcd_lattice* lat, const void* U, const void* psi, void* eta, int nrhs, double diag,
                            double hopc, int prec, bool dagger, const kcfg& c, hipStream_t s);
+
+// Pencil kernels with links moved to the rhs lanes by row broadcasts
+// (pencil_bc.hip): rhs-fastest layouts, nrhs a multiple of 16, any precision.
+bool bc_supported(int layout, int nrhs);
+hipError_t wilson_full_bc(const lqcd_lattice* lat, const void* U, const void* psi, void* eta, int nrhs, double diag,
+                          double hopc, int layout, int prec, bool dagger, const kcfg& c, hipStream_t s);
+hipError_t wilson_eo_bc(const lqcd_lattice* lat, const void* U, const void* in, const void* xin, void* out, int p,
+                        int nrhs, double alpha, double beta, int layout, int prec, bool dagger, const int* live,
+                        const kcfg& c, hipStream_t s);
 
 // The clover-improved operator (clover.hip): one (site, rhs) per work item.
 // Full: eta = diag psi - C psi + hopc hop(psi).  Odd-even half (out on

@@ -1,7 +1,8 @@
 """GPU parity of the Wilson kernels in forced launch configurations: pencil
 tiles and t segments, non-temporal stores, the autotuner's choice, the
-LDS-fed FP64 kernel, residency caps and the two-rhs-per-lane FP32 / FP16
-kernels, each against the oracle (tolerances as in test_gpu_apply.py)."""
+LDS-fed FP64 kernel, residency caps, the two-rhs-per-lane FP32 / FP16
+kernels and the row-broadcast-link kernels, each against the oracle
+(tolerances as in test_gpu_apply.py)."""
 import numpy as np
 import pytest
 
@@ -17,6 +18,11 @@ pytestmark = pytest.mark.gpu
 
 TOL = {lq.F64: 1e-12, lq.F32: 1e-5, lq.F16: 1e-3}
 LAYOUTS = [lq.RHS_OUTER, lq.LAYOUT1, lq.LAYOUT2]
+
+
+def _g5h(x):
+    """gamma5 on a half-lattice block (nrhs, V/2, 4, 3)."""
+    return dirac.apply_gamma5(x.reshape(x.shape[0], -1, 1, 1, 1, 4, 3)).reshape(x.shape)
 
 
 @pytest.fixture(autouse=True)
@@ -66,7 +72,7 @@ def test_nontemporal_stores_and_autotuned_choice(gpu_lib, kernel_variant, nt):
     Ud = to_dev(U, lq.F64)
     pd = to_dev(to_layout_np(psi, lq.LAYOUT2), lq.F64)
     best = gpu_lib.autotune(Ud, pd, torch.empty_like(pd), layout=lq.LAYOUT2, reps=1)
-    assert best["variant"] in (1, 2, 3, 5) and best["ms"] > 0
+    assert best["variant"] in (1, 2, 3, 5, 6) and best["ms"] > 0
     got = from_layout_np(from_dev(lq.dirac_apply(Ud, pd, -0.05, layout=lq.LAYOUT2), lq.F64), lq.LAYOUT2, 4)
     assert np.all(rel_err_per_rhs(got, want) <= TOL[lq.F64])
     gpu_lib.tune_clear()
@@ -134,3 +140,52 @@ def test_two_rhs_per_lane_kernels(gpu_lib, prec, nrhs, pencil):
     psi_e = geometry.to_half(psi, dims, 0)
     got = _apply_eo_gpu(U, psi_e, 0.1, lq.LAYOUT2, prec)
     assert np.all(rel_err_per_rhs(got, evenodd.apply_schur(U, psi_e, 0.1)) <= TOL[prec] * 2)
+
+
+@pytest.mark.parametrize("prec", [lq.F64, lq.F32, lq.F16])
+@pytest.mark.parametrize("nrhs", [16, 32])
+@pytest.mark.parametrize("pencil", [(0, 0, 0, 0), (2, 1, 3, 1), (1, 2, 1, 0), (3, 2, 2, 1)])
+def test_row_broadcast_link_kernels(gpu_lib, prec, nrhs, pencil):
+    """Variant 6 (each 16-lane row loads its column's links once and moves
+    them to its lanes by row broadcasts): full apply D and D^dagger and the
+    Schur apply in both rhs-fastest layouts, three precisions, tiles and
+    segment counts; unsupported rhs counts fall back to variant 3."""
+    gpu_lib.set_kernel_config(6, pencil[0], pencil[1], pencil[2], pencil[3])
+    dims = (6, 4, 6, 4)
+    U = rounded(syn.gauge_field(dims, "haar", config=14), prec)
+    psi = rounded(syn.spinor_block(dims, nrhs, config=14), prec)
+    psi_e = geometry.to_half(psi, dims, 0)
+    for layout in (lq.LAYOUT1, lq.LAYOUT2):
+        for dagger in (False, True):
+            want = (dirac.apply_dw_dagger if dagger else dirac.apply_dw)(U, psi, -0.2)
+            got = _apply_gpu(U, psi, -0.2, layout, prec, dagger)
+            assert np.all(rel_err_per_rhs(got, want) <= TOL[prec])
+            if dagger:  # S^dagger = gamma5 S gamma5
+                want = _g5h(evenodd.apply_schur(U, _g5h(psi_e), -0.2))
+            else:
+                want = evenodd.apply_schur(U, psi_e, -0.2)
+            got = _apply_eo_gpu(U, psi_e, -0.2, layout, prec, dagger)
+            assert np.all(rel_err_per_rhs(got, want) <= TOL[prec] * 2)
+    got = _apply_gpu(U, psi[:5], -0.2, lq.LAYOUT2, prec)
+    assert np.all(rel_err_per_rhs(got, dirac.apply_dw(U, psi[:5], -0.2)) <= TOL[prec])
+
+
+def test_row_broadcast_link_kernels_in_solves(gpu_lib):
+    """The odd-even row-broadcast kernel inside GMRES (its lanes of converged
+    rhs keep loading and broadcasting links and skip only their stores):
+    FP64 and FP32 refinement reach the tolerance on every rhs."""
+    gpu_lib.set_kernel_config(6, 0, 0, 0, 1)
+    dims = (8, 4, 4, 4)
+    m0 = -0.05
+    U = syn.gauge_field(dims, "near_identity", config=15, eps=0.3)
+    b = syn.spinor_block(dims, 16, config=15)
+    b[3] *= 1e-3  # rhs with different iteration counts
+    Ud = to_dev(U, lq.F64)
+    bd = to_dev(to_layout_np(b, lq.LAYOUT2), lq.F64)
+    for mode in ("f64", "ir-f32"):
+        x, st, rc = lq.gmres_solve(Ud, bd, m0, layout=lq.LAYOUT2, eo=True, mode=mode, tol=1e-10)
+        assert rc == lq.OK
+        xs = from_layout_np(from_dev(x, lq.F64), lq.LAYOUT2, 4)
+        res = dirac.apply_dw(U, xs, m0) - b
+        rel = np.linalg.norm(res.reshape(16, -1), axis=1) / np.linalg.norm(b.reshape(16, -1), axis=1)
+        assert np.all(rel <= 1e-10), (mode, rel)
