@@ -145,6 +145,22 @@ int dirac_apply(const lqcd_lattice* lat, const void* U, const void* psi, void* e
 int dirac_apply_eo(const lqcd_lattice* lat, const void* U, const void* psi_e, void* eta_e,
                    int nrhs, double m0, int layout, int prec, int flags, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * Schur apply as dirac_apply_eo, with its odd half-lattice temporary in a
+ * fixed device array of LQCD_NOALLOC_SCRATCH_BYTES that the library holds on
+ * every GPU it runs on until the process ends.  Calls no hipMalloc, hipFree
+ * or allocating routine; the caller passes U, psi_e and eta_e as for
+ * dirac_apply_eo.  Returns LQCD_ERR_WORKSPACE when the odd block
+ * (V/2 x 12 x nrhs complex numbers of `prec`) is larger than the array.
+ * The first call on a device, with that device current, resolves the
+ * array's address there (hipGetSymbolAddress).  All calls on one device
+ * share its array, so calls that overlap on one device (other streams,
+ * other threads) race; nothing in the array needs clearing between calls. */
+#define LQCD_NOALLOC_SCRATCH_BYTES (256u << 20)
+int dirac_apply_eo_noalloc(const lqcd_lattice* lat, const void* U, const void* psi_e, void* eta_e,
+                           int nrhs, double m0, int layout, int prec, int flags, void* stream);
+
 /* ---- the clover-improved operator D = D_W - C (Sec. III-A.1) ---- */
 
 /* Clover field C: [V][42] complex in the precision `prec` (same storage as

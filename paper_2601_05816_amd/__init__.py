@@ -54,6 +54,7 @@ class Problem(ctypes.Structure):
 
 
 MAX_BATCH = 16
+NOALLOC_SCRATCH_BYTES = 256 << 20  # LQCD_NOALLOC_SCRATCH_BYTES
 
 
 class KernelConfig(ctypes.Structure):
@@ -84,6 +85,8 @@ def load():
     lib.lqcd_lattice_tables.argtypes = [lp, vp, vp]
     lib.dirac_apply.argtypes = [lp, vp, vp, vp, i32, dbl, i32, i32, i32, vp]
     lib.dirac_apply_eo.argtypes = [lp, vp, vp, vp, i32, dbl, i32, i32, i32, vp]
+    lib.dirac_apply_eo_noalloc.argtypes = [lp, vp, vp, vp, i32, dbl, i32, i32, i32, vp]
+    lib.dirac_apply_eo_noalloc.restype = i32
     lib.dirac_apply_clover.argtypes = [lp, vp, vp, vp, vp, i32, dbl, i32, i32, i32, vp]
     lib.dirac_apply_clover.restype = i32
     lib.clover_inverse.argtypes = [lp, vp, vp, dbl, i32, vp]
@@ -279,6 +282,26 @@ def dirac_apply_eo(U, psi_e, m0, layout=LAYOUT2, dagger=False, out=None):
     _check_device(U, psi_e, out)
     _check(load().dirac_apply_eo(ctypes.byref(_lattice(dims)), U.data_ptr(), psi_e.data_ptr(), out.data_ptr(),
                                  nrhs, float(m0), layout, prec, DAGGER if dagger else 0, _stream()))
+    return out
+
+
+def dirac_apply_eo_noalloc(U, psi_e, m0, out, layout=LAYOUT2, dagger=False):
+    """dirac_apply_eo with the odd temporary in the library's fixed device
+    array (no device allocation; `out` must be given).  Raises LqcdError
+    (LQCD_ERR_WORKSPACE) if the odd block exceeds NOALLOC_SCRATCH_BYTES."""
+    prec = _prec_of(psi_e)
+    if _prec_of(U) != prec:
+        raise TypeError("U and psi_e must have the same precision")
+    dims = _dims_of_links(U, prec)
+    nrhs, sdims = _nrhs_of(psi_e, prec, layout, 1)
+    if int(sdims[0]) * 2 != int(np.prod(dims)):
+        raise ValueError(f"half-lattice block has {sdims[0]} sites, lattice {dims} needs {int(np.prod(dims)) // 2}")
+    if out.shape != psi_e.shape or out.dtype != psi_e.dtype:
+        raise ValueError("out must have the shape and dtype of psi_e")
+    _check_device(U, psi_e, out)
+    _check(load().dirac_apply_eo_noalloc(ctypes.byref(_lattice(dims)), U.data_ptr(), psi_e.data_ptr(),
+                                         out.data_ptr(), nrhs, float(m0), layout, prec, DAGGER if dagger else 0,
+                                         _stream()))
     return out
 
 
