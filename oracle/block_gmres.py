@@ -28,12 +28,14 @@ Readings taken where the definition leaves choices:
 * inner product <a, b> = sum conj(a) b, as everywhere in the oracle;
 * a cycle ends after m steps, when every active column's estimate is at or
   below its threshold ("max over rhs" exit, as Algorithm 2), or at a
-  breakdown: the new block is numerically rank deficient (a diagonal entry of
-  its triangular factor at or below 1e-6 of the block's largest column norm:
-  a Cholesky factorisation of the block's Gram matrix, as the GPU uses,
-  resolves rank only to about the square root of the working precision); the
-  step that found it still enters the least-squares problem (its Hessenberg
-  columns are complete), later steps are not taken;
+  breakdown: the new block is numerically rank deficient, i.e. its columns
+  are linearly dependent and K_k(A, R0) stops growing in that direction (a
+  diagonal entry of the Householder triangular factor at or below
+  BREAKDOWN = 1e-12 of the block's largest column norm; Householder QR in
+  complex128 resolves dependence to about 1e-16 of that norm, and 1e-12
+  keeps four orders of magnitude above that floor); the step that found it
+  still enters the least-squares problem (its Hessenberg columns are
+  complete), later steps are not taken;
 * each cycle restarts from the true residual B - A X with only the columns
   that have not converged (converged columns keep their x); if that residual
   block is itself numerically rank deficient (a diagonal entry of its
@@ -57,7 +59,7 @@ import numpy as np
 from . import dirac, evenodd
 from .gmres import _norms
 
-BREAKDOWN = 1e-6
+BREAKDOWN = 1e-12
 
 
 @dataclass

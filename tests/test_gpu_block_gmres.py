@@ -115,8 +115,12 @@ def test_zero_column_guess_and_fixed_steps(gpu_lib):
 @pytest.mark.parametrize("eo", [False, True])
 def test_equal_right_hand_sides(gpu_lib, eo):
     """A rank-deficient rhs block (two equal sources): the dependent column
-    sits out the first cycle, both converge to the dense LU solution, and the
-    block step count is the oracle's."""
+    sits out the first cycle and both converge to the dense LU solution.  The
+    GPU's Cholesky QR flags blocks whose triangular pivots fall below 1e-6 of
+    their scale, the oracle's Householder QR below 1e-12, so where a block is
+    nearly dependent the two may deflate at different steps: compared are
+    what is unique (the solution, within the condition-number bound, and the
+    true residuals), with a stated slack of one cycle on the step counts."""
     dims = (4, 4, 4, 4)
     m0 = 0.1
     U = syn.gauge_field(dims, "haar", config=49)
@@ -127,9 +131,11 @@ def test_equal_right_hand_sides(gpu_lib, eo):
     D = dirac.dense(U, m0)
     x_lu = np.linalg.solve(D, b.reshape(4, -1).T).T.reshape(b.shape)
     assert np.all(rel_err_per_rhs(x, x_lu) <= np.linalg.cond(D) * 1e-10)
-    _, ost = obg.block_solve(U, b, m0, tol=1e-10, restart=8, eo=eo)
+    assert np.all(st["true_relres"] <= 1e-10)
+    xo, ost = obg.block_solve(U, b, m0, tol=1e-10, restart=8, eo=eo)
     assert np.all(ost.converged)
-    assert np.all(np.abs(st["iters"] - ost.iters) <= 2)   # steps while active, per rhs
+    assert np.all(rel_err_per_rhs(x, xo) <= np.linalg.cond(D) * 2e-10)
+    assert np.all(np.abs(st["iters"] - ost.iters) <= 8)   # steps while active, per rhs: one cycle of slack
     assert st["iters"][3] < st["iters"][1]                   # the copy sat out the first cycle
 
 
