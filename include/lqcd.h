@@ -263,6 +263,16 @@ typedef struct {
   int32_t max_outer;     /* cap on refinement steps (modes 1, 2), default 50 */
   int32_t dagger;        /* 1: solve D^dagger x = b instead (the adjoint solve of a gradient) */
   int32_t use_graph;     /* 1: capture each Arnoldi step (all lattices) in a HIP graph and replay it */
+  int32_t rhs_block;     /* gmres_solve / gmres_solve_clover solve the rhs in chunks of this many
+                            consecutive rhs, one after another (eq. (1)'s block of b rhs, b = this width):
+                            the workspace is that of one chunk.  0 = chosen by the library: the full
+                            width if the workspace holds it, else among the widths it holds the one
+                            with the least tuned apply time per rhs (largest width without table
+                            entries); see gmres_rhs_block */
+  int32_t gs;            /* orthogonalisation of the batched Arnoldi step (Algorithm 2 leaves it open):
+                            0 classical Gram-Schmidt, one pass for all dots (default); 1 CGS2, a second
+                            CGS pass against the updated vector; 2 modified Gram-Schmidt, one
+                            vector at a time.  Block GMRES ignores it (block CGS + Cholesky QR) */
   int32_t reserved;
 } lqcd_solver_params;
 
@@ -279,8 +289,16 @@ typedef struct {
 /* Fill p with the defaults listed above. */
 void lqcd_solver_defaults(lqcd_solver_params* p);
 
-/* Device workspace in bytes that gmres_solve needs for these arguments. */
+/* Device workspace in bytes that gmres_solve needs for these arguments: for
+ * p->rhs_block = w in 1..nrhs-1 that of one chunk of w rhs, else that of all
+ * nrhs rhs at once. */
 size_t gmres_workspace_bytes(const lqcd_lattice* lat, int nrhs, const lqcd_solver_params* p);
+
+/* The chunk width gmres_solve uses for these arguments and a workspace of
+ * work_bytes: p->rhs_block if it is in 1..nrhs, else the library's choice
+ * (see lqcd_solver_params.rhs_block); LQCD_ERR_WORKSPACE if not even one
+ * rhs fits. */
+int gmres_rhs_block(const lqcd_lattice* lat, int nrhs, const lqcd_solver_params* p, size_t work_bytes);
 
 /* Solve D x_i = b_i for i = 0..nrhs-1 with batched restarted GMRES
  * (Algorithm 2: every rhs runs its own GMRES(m) in lock-step; classical

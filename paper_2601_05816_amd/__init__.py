@@ -45,7 +45,8 @@ class SolverParams(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int32), ("max_restarts", ctypes.c_int32), ("eo", ctypes.c_int32),
                 ("mode", ctypes.c_int32), ("x_is_guess", ctypes.c_int32), ("fixed_iters", ctypes.c_int32),
                 ("tol", ctypes.c_double), ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int32),
-                ("dagger", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("dagger", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("rhs_block", ctypes.c_int32),
+                ("gs", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Problem(ctypes.Structure):
@@ -122,6 +123,8 @@ def load():
         lib.lqcd_solver_defaults.restype = None
         lib.gmres_workspace_bytes.argtypes = [lp, i32, ctypes.POINTER(SolverParams)]
         lib.gmres_workspace_bytes.restype = ctypes.c_size_t
+        lib.gmres_rhs_block.argtypes = [lp, i32, ctypes.POINTER(SolverParams), ctypes.c_size_t]
+        lib.gmres_rhs_block.restype = i32
         lib.gmres_solve.argtypes = [lp, vp, vp, vp, i32, dbl, i32, ctypes.POINTER(SolverParams), vp,
                                     ctypes.c_size_t, ctypes.POINTER(RhsStats), vp]
         lib.gmres_solve.restype = i32
@@ -371,8 +374,11 @@ def dirac_apply_eo_clover(U, C, Cinv, psi_e, m0, layout=LAYOUT2, dagger=False, o
 MODES = {"f64": 0, "ir-f32": 1, "ir-f16": 2}
 
 
+GS = {"cgs": 0, "cgs2": 1, "mgs": 2}
+
+
 def solver_params(restart=30, max_restarts=200, eo=True, mode=0, tol=1e-10, inner_tol=0.0, max_outer=50,
-                  x_is_guess=False, fixed_iters=False, dagger=False, use_graph=False):
+                  x_is_guess=False, fixed_iters=False, dagger=False, use_graph=False, rhs_block=0, gs="cgs"):
     p = SolverParams()
     load().lqcd_solver_defaults(ctypes.byref(p))
     p.restart, p.max_restarts, p.eo = int(restart), int(max_restarts), int(bool(eo))
@@ -381,11 +387,19 @@ def solver_params(restart=30, max_restarts=200, eo=True, mode=0, tol=1e-10, inne
     p.x_is_guess, p.fixed_iters = int(bool(x_is_guess)), int(bool(fixed_iters))
     p.dagger = int(bool(dagger))
     p.use_graph = int(bool(use_graph))
+    p.rhs_block = int(rhs_block)
+    p.gs = GS[gs] if isinstance(gs, str) else int(gs)
     return p
 
 
 def gmres_workspace_bytes(dims, nrhs, params):
     return int(load().gmres_workspace_bytes(ctypes.byref(_lattice(dims)), int(nrhs), ctypes.byref(params)))
+
+
+def gmres_rhs_block(dims, nrhs, params, work_bytes):
+    """The rhs chunk width gmres_solve uses with a workspace of work_bytes."""
+    return _check(load().gmres_rhs_block(ctypes.byref(_lattice(dims)), int(nrhs), ctypes.byref(params),
+                                         ctypes.c_size_t(int(work_bytes))))
 
 
 def gmres_solve(U, b, m0, layout=LAYOUT2, x0=None, work=None, **kw):
@@ -404,9 +418,8 @@ def gmres_solve(U, b, m0, layout=LAYOUT2, x0=None, work=None, **kw):
         raise ValueError(f"source lattice {sdims} does not match gauge lattice {dims}")
     p = solver_params(x_is_guess=x0 is not None, **kw)
     x = x0.clone() if x0 is not None else torch.empty_like(b)
-    need = gmres_workspace_bytes(dims, nrhs, p)
-    if work is None or work.numel() < need:
-        work = torch.empty(need, dtype=torch.uint8, device=b.device)
+    if work is None:
+        work = torch.empty(gmres_workspace_bytes(dims, nrhs, p), dtype=torch.uint8, device=b.device)
     _check_device(U, b, x, work)
     st = (RhsStats * nrhs)()
     rc = _check(load().gmres_solve(ctypes.byref(_lattice(dims)), U.data_ptr(), b.data_ptr(), x.data_ptr(), nrhs,

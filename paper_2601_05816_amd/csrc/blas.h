@@ -34,8 +34,10 @@ hipError_t convert(int pin, const void* in, int pout, void* out, size_t nelem, i
                    hipStream_t s);
 hipError_t add_scaled(int pin, const void* in, void* out64, size_t nelem, int nrhs, const double* f, hipStream_t s);
 hipError_t convert_links(const void* in, int pout, void* out, size_t n, hipStream_t s);
+// columns col0 .. col0+nrhs-1 of an ABI block of abi_nrhs rhs <-> an
+// internal block of nrhs rhs (abi_nrhs = 0: the ABI block has nrhs rhs)
 hipError_t pack(int layout, bool to_internal, void* abi, void* ie, void* io, const int* dims, int nrhs, int eo,
-                hipStream_t s);
+                hipStream_t s, int abi_nrhs = 0, int col0 = 0);
 
 // Block kernels of block GMRES (bblas.hip), FP64 blocks [nrows][b], b <= 16,
 // on the FP64 matrix cores.  bgram_parts writes 4 * nblk partial sums of the

@@ -344,7 +344,7 @@ __global__ __launch_bounds__(256) void k_convert_flat(const store_t<PI>* __restr
 template <int LAYOUT, bool TO_INTERNAL>
 __global__ __launch_bounds__(256) void k_pack(store_t<LQCD_F64>* __restrict__ abi, store_t<LQCD_F64>* __restrict__ ie,
                                               store_t<LQCD_F64>* __restrict__ io, int n0, int n1, int n2, int n3,
-                                              int nrhs, int eo) {
+                                              int nrhs, int eo, int abi_nrhs, int col0) {
   const size_t V = (size_t)n0 * n1 * n2 * n3;
   const size_t items = V * (size_t)nrhs;
   for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < items; t += (size_t)gridDim.x * blockDim.x) {
@@ -364,8 +364,8 @@ __global__ __launch_bounds__(256) void k_pack(store_t<LQCD_F64>* __restrict__ ab
       dst = ie;
       idx = site;
     }
-    const size_t a = blk<LAYOUT>::base(site, rhs, V, nrhs);
-    const int cs = blk<LAYOUT>::cstride(nrhs);
+    const size_t a = blk<LAYOUT>::base(site, col0 + rhs, V, abi_nrhs);
+    const int cs = blk<LAYOUT>::cstride(abi_nrhs);
     const size_t b = idx * 12u * (size_t)nrhs + (size_t)rhs;
     for (int c = 0; c < 12; ++c) {
       if (TO_INTERNAL) dst[b + (size_t)c * nrhs] = abi[a + (size_t)c * cs];
@@ -537,13 +537,16 @@ hipError_t convert_links(const void* in, int pout, void* out, size_t n, hipStrea
 }
 
 hipError_t pack(int layout, bool to_internal, void* abi, void* ie, void* io, const int* dims, int nrhs, int eo,
-                hipStream_t s) {
+                hipStream_t s, int abi_nrhs, int col0) {
+  if (abi_nrhs <= 0) abi_nrhs = nrhs;
+  if (col0 < 0 || col0 + nrhs > abi_nrhs) return hipErrorInvalidValue;
   const size_t items = (size_t)dims[0] * dims[1] * dims[2] * dims[3] * (size_t)nrhs;
   size_t nb = (items + 255) / 256;
   if (nb > 65536) nb = 65536;
 #define PK(L, T)                                                                                                   \
   hipLaunchKernelGGL((k_pack<L, T>), dim3((unsigned)nb), dim3(256), 0, s, (store_t<LQCD_F64>*)abi,                 \
-                     (store_t<LQCD_F64>*)ie, (store_t<LQCD_F64>*)io, dims[0], dims[1], dims[2], dims[3], nrhs, eo)
+                     (store_t<LQCD_F64>*)ie, (store_t<LQCD_F64>*)io, dims[0], dims[1], dims[2], dims[3], nrhs, eo, \
+                     abi_nrhs, col0)
   switch (layout * 2 + (to_internal ? 1 : 0)) {
     case LQCD_RHS_OUTER * 2 + 1: PK(LQCD_RHS_OUTER, true); break;
     case LQCD_RHS_OUTER * 2 + 0: PK(LQCD_RHS_OUTER, false); break;

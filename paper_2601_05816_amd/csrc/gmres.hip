@@ -145,6 +145,15 @@ __global__ void k_count_live(int nrhs, const int* __restrict__ live, int* __rest
   }
 }
 
+// acc[i] += add[i] (the second CGS pass's dots into the first's)
+__global__ void k_add_zd(int n, const zd* __restrict__ add, zd* __restrict__ acc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    acc[i].re += add[i].re;
+    acc[i].im += add[i].im;
+  }
+}
+
 // Back substitution R y = gamma on the rotated triangle, y[k][rhs].
 __global__ void k_lsq(int m, int nrhs, const zd* __restrict__ H, const zd* __restrict__ g,
                       const int* __restrict__ steps, const double* __restrict__ sk, zd* __restrict__ y) {
@@ -433,6 +442,7 @@ struct Solver {
   lqcd_lattice lat;
   size_t V, nsite, nelem;
   int nrhs, m, eo, mode, plo;
+  int gs;    // 0 CGS, 1 CGS2, 2 MGS
   bool dag;  // solve with D^dagger
   double m0, d;
   hipStream_t s;
@@ -453,6 +463,7 @@ struct Solver {
   void* rlo;                      // inner rhs (refinement modes)
   void* dlo;                      // inner solution (refinement modes)
   zd *part, *hcol, *coef, *nrm, *H, *sn, *g, *y;
+  zd* hcol2;   // second-pass dots (CGS2)
   double* sk;  // per basis vector and rhs: v_k = sk[k] u_k (the stored vectors are unnormalised)
   double *cs, *bref, *ibref, *beta, *scl, *est, *fin, *fout, *rel;
   int *live, *steps, *flags, *nlive;
@@ -487,6 +498,7 @@ struct Solver {
     Cilo = (clov && eo && mode) ? a.take(V * 42 * esize(pw)) : nullptr;
     part = (zd*)a.take((size_t)nblk * DOT_KB * nrhs * sizeof(zd));
     hcol = (zd*)a.take((size_t)(m + 1) * nrhs * sizeof(zd));
+    hcol2 = gs == 1 ? (zd*)a.take((size_t)(m + 1) * nrhs * sizeof(zd)) : nullptr;
     coef = (zd*)a.take((size_t)(m + 1) * nrhs * sizeof(zd));
     sk = (double*)a.take((size_t)(m + 1) * nrhs * sizeof(double));
     nrm = (zd*)a.take((size_t)nrhs * sizeof(zd));
@@ -574,6 +586,7 @@ struct Task {
   const void* b_abi;
   void* x_abi;
   int layout;
+  int abi_nrhs = 0, col0 = 0;  // this task solves columns col0.. of ABI blocks of abi_nrhs rhs (0: all)
   HostState hs;
   void* x;             // solution of the current GMRES run
   const void* b;       // right-hand side of the current GMRES run
@@ -656,15 +669,38 @@ static hipError_t arnoldi_step(Group& G, int prec, int j, double sc, double tol,
     Solver& S = t.S;
     const size_t nel = S.nelem;
     void* w = S.Vk(prec, j + 1);
-    for (int k0 = 0; k0 <= j; k0 += DOT_KB) {
-      const int K = (j + 1 - k0) < DOT_KB ? (j + 1 - k0) : DOT_KB;
-      if ((e = dot_parts(prec, S.basis, nel, k0, K, w, nel, S.nrhs, S.live, S.part, S.nblk, s)) != hipSuccess) return e;
-      if ((e = reduce_parts(S.part, S.nblk, K, S.nrhs, sc, S.hcol + (size_t)k0 * S.nrhs, s)) != hipSuccess) return e;
-    }
     const int nc = (j + 1) * S.nrhs;
-    hipLaunchKernelGGL(k_cgs_coef, dim3((nc + 255) / 256), dim3(256), 0, s, j + 1, S.nrhs, S.hcol, S.sk, S.coef);
-    if ((e = cgs_update(prec, S.basis, nel, j + 1, S.coef, w, nel, S.nrhs, S.live, S.part, S.nblk, s)) != hipSuccess)
-      return e;
+    if (S.gs == 2) {
+      // modified Gram-Schmidt: d_k = <u_k, w> against the vector already
+      // orthogonalised to u_0 .. u_{k-1}, then w -= sk[k]^2 d_k u_k
+      for (int k = 0; k <= j; ++k) {
+        if ((e = dot_parts(prec, S.basis, nel, k, 1, w, nel, S.nrhs, S.live, S.part, S.nblk, s)) != hipSuccess)
+          return e;
+        if ((e = reduce_parts(S.part, S.nblk, 1, S.nrhs, sc, S.hcol + (size_t)k * S.nrhs, s)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_cgs_coef, dim3(((k + 1) * S.nrhs + 255) / 256), dim3(256), 0, s, k + 1, S.nrhs, S.hcol,
+                           S.sk, S.coef);
+        if ((e = cgs_update(prec, S.Vk(prec, k), nel, 1, S.coef + (size_t)k * S.nrhs, w, nel, S.nrhs, S.live, S.part,
+                            S.nblk, s)) != hipSuccess)
+          return e;
+      }
+    } else {
+      // classical Gram-Schmidt: all dots against the same w, one fused update;
+      // CGS2 repeats the pass on the updated vector and adds its dots
+      for (int pass = 0; pass < (S.gs == 1 ? 2 : 1); ++pass) {
+        zd* hc = pass == 0 ? S.hcol : S.hcol2;
+        for (int k0 = 0; k0 <= j; k0 += DOT_KB) {
+          const int K = (j + 1 - k0) < DOT_KB ? (j + 1 - k0) : DOT_KB;
+          if ((e = dot_parts(prec, S.basis, nel, k0, K, w, nel, S.nrhs, S.live, S.part, S.nblk, s)) != hipSuccess)
+            return e;
+          if ((e = reduce_parts(S.part, S.nblk, K, S.nrhs, sc, hc + (size_t)k0 * S.nrhs, s)) != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(k_cgs_coef, dim3((nc + 255) / 256), dim3(256), 0, s, j + 1, S.nrhs, hc, S.sk, S.coef);
+        if ((e = cgs_update(prec, S.basis, nel, j + 1, S.coef, w, nel, S.nrhs, S.live, S.part, S.nblk, s)) !=
+            hipSuccess)
+          return e;
+        if (pass == 1) hipLaunchKernelGGL(k_add_zd, dim3((nc + 255) / 256), dim3(256), 0, s, nc, S.hcol2, S.hcol);
+      }
+    }
     if ((e = reduce_parts(S.part, (int)cgs_update_parts(prec, nel, S.nrhs, S.nblk), 1, S.nrhs, sc, S.nrm, s)) !=
         hipSuccess)
       return e;
@@ -894,6 +930,8 @@ static int check_params(const lqcd_solver_params* p) {
   if (p->mode < 0 || p->mode > 2) return fail(LQCD_ERR_ARG, "gmres: unknown mode %d", p->mode);
   if (!(p->tol >= 0.0)) return fail(LQCD_ERR_ARG, "gmres: tol must be >= 0");
   if (p->mode && p->max_outer < 1) return fail(LQCD_ERR_ARG, "gmres: max_outer must be >= 1");
+  if (p->gs < 0 || p->gs > 2) return fail(LQCD_ERR_ARG, "gmres: unknown orthogonalisation gs = %d", p->gs);
+  if (p->rhs_block < 0) return fail(LQCD_ERR_ARG, "gmres: rhs_block must be >= 0");
   return LQCD_OK;
 }
 
@@ -910,6 +948,7 @@ static void setup(Solver& S, const lqcd_lattice* lat, int nrhs, const lqcd_solve
   S.m = p->restart;
   S.mode = p->mode;
   S.plo = p->mode == 1 ? LQCD_F32 : LQCD_F16;
+  S.gs = blk ? 0 : p->gs;
   S.dag = p->dagger != 0;
   S.nblk = reduce_grid(S.nelem);
   S.gblk = blk ? bgram_blocks(S.nelem / nrhs) : 0;
@@ -957,11 +996,11 @@ static int solve_group(Group& G, const lqcd_solver_params* params, lqcd_rhs_stat
     t.hs.restarts.assign(S.nrhs, 0);
     t.hs.outer.assign(S.nrhs, 0);
     t.hs.est.assign(S.nrhs, 0.0);
-    HIPCHK(pack(t.layout, true, (void*)t.b_abi, S.be, S.bo, dims, S.nrhs, S.eo, s));
+    HIPCHK(pack(t.layout, true, (void*)t.b_abi, S.be, S.bo, dims, S.nrhs, S.eo, s, t.abi_nrhs, t.col0));
     HIPCHK(full_norm2(t, S.be, S.bo, s));
     hipLaunchKernelGGL(k_sqrt_scale, dim3(S.small_grid()), dim3(64), 0, s, S.nrhs, S.nrm, 1.0, S.bref);
     if (params->x_is_guess) {
-      HIPCHK(pack(t.layout, true, t.x_abi, S.xe, S.xo, dims, S.nrhs, S.eo, s));
+      HIPCHK(pack(t.layout, true, t.x_abi, S.xe, S.xo, dims, S.nrhs, S.eo, s, t.abi_nrhs, t.col0));
       hipLaunchKernelGGL(k_zero_mask, dim3(S.small_grid()), dim3(64), 0, s, S.nrhs, S.bref, S.fin);
       HIPCHK(scale_rhs(LQCD_F64, S.xe, S.nelem, S.nrhs, S.fin, nullptr, s));
     } else {
@@ -1092,7 +1131,7 @@ static int solve_group(Group& G, const lqcd_solver_params* params, lqcd_rhs_stat
       HIPCHK(b_minus_y(LQCD_F64, S.be, t1, S.nelem, S.nrhs, nullptr, S.part, S.nblk, s));
       HIPCHK(reduce_parts(S.part, S.nblk, 1, S.nrhs, 1.0, S.nrm, s));
     }
-    HIPCHK(pack(t.layout, false, t.x_abi, S.xe, S.xo, dims, S.nrhs, S.eo, s));
+    HIPCHK(pack(t.layout, false, t.x_abi, S.xe, S.xo, dims, S.nrhs, S.eo, s, t.abi_nrhs, t.col0));
     std::vector<zd> rn(S.nrhs);
     std::vector<double> bn(S.nrhs);
     HIPCHK(hipMemcpyAsync(rn.data(), S.nrm, S.nrhs * sizeof(zd), hipMemcpyDeviceToHost, s));
@@ -1170,7 +1209,88 @@ void lqcd_solver_defaults(lqcd_solver_params* p) {
 
 size_t gmres_workspace_bytes(const lqcd_lattice* lat, int nrhs, const lqcd_solver_params* p) {
   if (check_lattice(lat) || nrhs < 1 || check_params(p)) return 0;
-  return task_bytes(lat, nrhs, p) + 256;
+  const int w = (p->rhs_block > 0 && p->rhs_block < nrhs) ? p->rhs_block : nrhs;
+  return task_bytes(lat, w, p) + 256;
+}
+
+}  // extern "C"
+
+namespace lq {
+
+// Chunk width of a solve (lqcd_solver_params.rhs_block): the caller's, else
+// the full width if the workspace holds it, else among the candidate widths
+// the workspace holds the one whose tuned Wilson time (the autotuner's table
+// entry for the operator the solve applies most: the odd-even hop pass or
+// the full apply, in the inner precision) per rhs is least, counting the
+// chunks it takes; without table entries the largest such width.
+static int choose_rhs_block(const lqcd_lattice* lat, int nrhs, const lqcd_solver_params* p, size_t work_bytes,
+                            bool clov) {
+  if (p->rhs_block > 0) return p->rhs_block < nrhs ? p->rhs_block : nrhs;
+  auto fits = [&](int w) { return task_bytes(lat, w, p, clov) + 256 <= work_bytes; };
+  if (fits(nrhs)) return nrhs;
+  const int prec = p->mode == 0 ? LQCD_F64 : (p->mode == 1 ? LQCD_F32 : LQCD_F16);
+  const int kind = p->eo ? KIND_EO : KIND_FULL;
+  int best = 0, largest = 0;
+  double best_cost = 0.0;
+  for (int w : {64, 48, 32, 24, 16, 12, 8, 4, 2, 1}) {
+    if (w >= nrhs || !fits(w)) continue;
+    if (!largest) largest = w;
+    double ms = 0.0;
+    if (!tuned_time(kind, lat, w, prec, LQCD_LAYOUT2, &ms)) continue;
+    const double cost = ms * (double)((nrhs + w - 1) / w);
+    if (!best || cost < best_cost) {
+      best = w;
+      best_cost = cost;
+    }
+  }
+  return best ? best : largest;
+}
+
+// The solve of nrhs rhs in chunks of w consecutive rhs, one after another,
+// each with the whole workspace (a chunk is an ordinary solve of its
+// columns; the ABI blocks are read and written in place).
+static int solve_chunked(const lqcd_lattice* lat, const void* U, const void* C, const void* b, void* x, int nrhs,
+                         int w, double m0, int layout, const lqcd_solver_params* params, char* work,
+                         lqcd_rhs_stats* stats, hipStream_t stream) {
+  int rc_all = LQCD_OK;
+  for (int c0 = 0; c0 < nrhs; c0 += w) {
+    const int wc = (nrhs - c0) < w ? (nrhs - c0) : w;
+    Group G;
+    G.T.resize(1);
+    Task& t = G.T[0];
+    setup(t.S, lat, wc, params, C != nullptr, false);
+    t.S.C64 = C;
+    t.S.m0 = m0;
+    t.S.d = 4.0 + m0;
+    t.S.U64 = U;
+    t.U = U;
+    t.b_abi = b;
+    t.x_abi = x;
+    t.layout = layout;
+    t.abi_nrhs = nrhs;
+    t.col0 = c0;
+    Arena a{work, 0, 0};
+    t.S.layout(a);
+    const int rc = run_group(G, params, stats ? stats + c0 : nullptr, stream, params->use_graph != 0);
+    if (rc < 0) return rc;
+    if (rc == LQCD_NOT_CONVERGED) rc_all = LQCD_NOT_CONVERGED;
+  }
+  return rc_all;
+}
+
+}  // namespace lq
+
+extern "C" {
+
+int gmres_rhs_block(const lqcd_lattice* lat, int nrhs, const lqcd_solver_params* p, size_t work_bytes) {
+  int rc = check_lattice(lat);
+  if (rc) return rc;
+  if (nrhs < 1) return fail(LQCD_ERR_ARG, "gmres_rhs_block: nrhs = %d", nrhs);
+  if ((rc = check_params(p))) return rc;
+  const int w = choose_rhs_block(lat, nrhs, p, work_bytes, false);
+  if (!w || task_bytes(lat, w, p) + 256 > work_bytes)
+    return fail(LQCD_ERR_WORKSPACE, "gmres_rhs_block: a workspace of %zu bytes holds no chunk", work_bytes);
+  return w;
 }
 
 static int init_task(Task& t, const lqcd_lattice* lat, const void* U, const void* b, void* x, int nrhs, double m0,
@@ -1198,20 +1318,23 @@ int gmres_solve(const lqcd_lattice* lat, const void* U, const void* b, void* x, 
   if ((rc = check_block(nrhs, layout, LQCD_F64))) return rc;
   if ((rc = check_params(params))) return rc;
   if (!U || !b || !x) return fail(LQCD_ERR_ARG, "gmres_solve: null array pointer");
-  const size_t need = gmres_workspace_bytes(lat, nrhs, params);
-  if (!work || work_bytes < need)
-    return fail(LQCD_ERR_WORKSPACE, "gmres_solve: workspace of %zu bytes given, %zu needed", work_bytes, need);
   if (4.0 + m0 == 0.0 && params->eo) return fail(LQCD_ERR_SINGULAR, "gmres_solve: 4 + m0 = 0, D_oo is not invertible");
+  const int wb = choose_rhs_block(lat, nrhs, params, work ? work_bytes : 0, false);
+  const size_t need = wb ? task_bytes(lat, wb, params) + 256 : task_bytes(lat, 1, params) + 256;
+  if (!work || !wb || work_bytes < need)
+    return fail(LQCD_ERR_WORKSPACE, "gmres_solve: workspace of %zu bytes given, %zu needed", work_bytes, need);
+  char* w = (char*)work + ((256 - ((uintptr_t)work & 255)) & 255);
+  if (wb < nrhs) return solve_chunked(lat, U, nullptr, b, x, nrhs, wb, m0, layout, params, w, stats, (hipStream_t)stream);
   Group G;
   G.T.resize(1);
-  char* w = (char*)work + ((256 - ((uintptr_t)work & 255)) & 255);
   init_task(G.T[0], lat, U, b, x, nrhs, m0, layout, params, w);
   return run_group(G, params, stats, (hipStream_t)stream, params->use_graph != 0);
 }
 
 size_t gmres_workspace_bytes_clover(const lqcd_lattice* lat, int nrhs, const lqcd_solver_params* p) {
   if (check_lattice(lat) || nrhs < 1 || check_params(p)) return 0;
-  return task_bytes(lat, nrhs, p, true) + 256;
+  const int w = (p->rhs_block > 0 && p->rhs_block < nrhs) ? p->rhs_block : nrhs;
+  return task_bytes(lat, w, p, true) + 256;
 }
 
 int gmres_solve_clover(const lqcd_lattice* lat, const void* U, const void* C, const void* b, void* x, int nrhs,
@@ -1222,12 +1345,14 @@ int gmres_solve_clover(const lqcd_lattice* lat, const void* U, const void* C, co
   if ((rc = check_block(nrhs, layout, LQCD_F64))) return rc;
   if ((rc = check_params(params))) return rc;
   if (!U || !C || !b || !x) return fail(LQCD_ERR_ARG, "gmres_solve_clover: null array pointer");
-  const size_t need = gmres_workspace_bytes_clover(lat, nrhs, params);
-  if (!work || work_bytes < need)
+  const int wb = choose_rhs_block(lat, nrhs, params, work ? work_bytes : 0, true);
+  const size_t need = wb ? task_bytes(lat, wb, params, true) + 256 : task_bytes(lat, 1, params, true) + 256;
+  if (!work || !wb || work_bytes < need)
     return fail(LQCD_ERR_WORKSPACE, "gmres_solve_clover: workspace of %zu bytes given, %zu needed", work_bytes, need);
+  char* w = (char*)work + ((256 - ((uintptr_t)work & 255)) & 255);
+  if (wb < nrhs) return solve_chunked(lat, U, C, b, x, nrhs, wb, m0, layout, params, w, stats, (hipStream_t)stream);
   Group G;
   G.T.resize(1);
-  char* w = (char*)work + ((256 - ((uintptr_t)work & 255)) & 255);
   init_task(G.T[0], lat, U, b, x, nrhs, m0, layout, params, w, C);
   return run_group(G, params, stats, (hipStream_t)stream, params->use_graph != 0);
 }

@@ -86,6 +86,8 @@ hipError_t clover_invert(const lqcd_lattice* lat, const void* C, void* Cinv, dou
 // Configuration for an apply (tune.hip): the process-wide forced setting if
 // any, else the autotuner's entry for these arguments, else the default.
 kcfg choose_cfg(int kind, const lqcd_lattice* lat, int nrhs, int prec, int layout);
+// The autotuner's measured time of one launch for these arguments, if it has an entry.
+bool tuned_time(int kind, const lqcd_lattice* lat, int nrhs, int prec, int layout, double* ms);
 void set_variant(int v, const int* pencil);
 
 }  // namespace lq

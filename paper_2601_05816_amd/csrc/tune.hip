@@ -62,6 +62,14 @@ kcfg choose_cfg(int kind, const lqcd_lattice* lat, int nrhs, int prec, int layou
   return kDefault;
 }
 
+bool tuned_time(int kind, const lqcd_lattice* lat, int nrhs, int prec, int layout, double* ms) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_table.find(key_of(kind, lat, nrhs, prec, layout));
+  if (it == g_table.end() || !(it->second.second > 0.0)) return false;
+  *ms = it->second.second;
+  return true;
+}
+
 static const int kTiles[][2] = {{0, 0}, {2, 1}, {2, 2}, {4, 2}, {4, 4}, {8, 2}, {8, 4}};
 
 static bool tile_ok(const lqcd_lattice* lat, const int* t, int sg) {

@@ -121,3 +121,36 @@ def test_shipped_tune_table_loads_completely():
             assert 1 <= int(cfg[0]) <= 5 and 0 <= int(cfg[5]) <= 8 and float(cfg[6]) > 0
     finally:
         lq.tune_clear()
+
+
+def test_rhs_block_choice_on_host(tmp_path):
+    """Chunk width of a solve (host logic, no device): the caller's width;
+    else the full width if the workspace holds it, else the width with the
+    least tuned time per rhs among those the workspace holds (the MI355X
+    table for 32^3 x 64), or without table entries the largest; a workspace
+    that holds no chunk is an error."""
+    import ctypes
+
+    lib = lq.load()
+    dims = (64, 32, 32, 32)
+    lat = lq._lattice(dims)
+    p = lq.solver_params(eo=True, mode="f64")
+    full = lq.gmres_workspace_bytes(dims, 64, p)
+    ws = {w: lq.gmres_workspace_bytes(dims, 64, lq.solver_params(eo=True, mode="f64", rhs_block=w))
+          for w in (1, 8, 16, 32)}
+    assert ws[1] < ws[8] < ws[16] < ws[32] < full
+    lq.tune_clear()
+    assert lq.gmres_rhs_block(dims, 64, p, full) == 64
+    assert lq.gmres_rhs_block(dims, 64, p, ws[16]) == 16
+    assert lq.gmres_rhs_block(dims, 64, lq.solver_params(eo=True, rhs_block=8), full) == 8
+    assert lib.gmres_rhs_block(ctypes.byref(lat), 64, ctypes.byref(p), ctypes.c_size_t(ws[1] - 1024)) == -6
+    tune = os.path.join(os.path.dirname(HEADER), "..", "paper_2601_05816_amd", "tune_mi355x.txt")
+    assert lq.tune_load(tune) > 0
+    try:
+        # FP64 odd-even hop pass per launch: 32 rhs 5.27 ms, 16 rhs 2.74 ms, 8 rhs 1.50 ms:
+        # two chunks of 32 cost least
+        assert lq.gmres_rhs_block(dims, 64, p, ws[32]) == 32
+    finally:
+        lq.tune_clear()
+    # a smaller chunk shrinks the workspace in proportion to its rhs
+    assert abs(ws[32] / ws[16] - 2.0) < 0.01

@@ -188,3 +188,68 @@ def test_refinement_vector_paths(gpu_lib, mode, variant):
     gpu_lib.set_kernel_variant(0)
     assert rc == lq.OK
     assert np.all(_true_relres(U, b, x, m0) <= 1e-10)
+
+
+@pytest.mark.parametrize("gs", ["cgs2", "mgs"])
+def test_orthogonalisation_options(gpu_lib, gs):
+    """CGS2 and MGS (Algorithm 2 leaves the orthogonalisation open): the fixed
+    10 x 10 protocol gives the oracle's (MGS) iterate, a converged solve
+    matches dense LU within kappa * tol with the oracle's iteration count, and
+    the FP32 refinement and the lock-step batch run with them."""
+    dims = (4, 4, 4, 8)
+    m0 = 0.1
+    U = syn.gauge_field(dims, "near_identity", config=6)
+    b = syn.spinor_block(dims, 2, config=6)
+    x, st, rc = _solve(U, b, m0, eo=False, restart=10, max_restarts=10, fixed_iters=True, gs=gs)
+    assert rc == lq.OK and np.all(st["iters"] == 100)
+    xo, ost = ogmres.gmres(lambda v: dirac.apply_dw(U, v, m0), b, 0.0, restart=10, max_restarts=10)
+    assert np.all(rel_err_per_rhs(x, xo) <= 1e-9)
+    dims = (4, 4, 4, 4)
+    U = syn.gauge_field(dims, "haar", config=1)
+    b = syn.spinor_block(dims, 3, config=1)
+    x, st, rc = _solve(U, b, m0, restart=30, eo=False, tol=1e-10, gs=gs)
+    assert rc == lq.OK and np.all(_true_relres(U, b, x, m0) <= 1e-10)
+    D = dirac.dense(U, m0)
+    x_lu = np.linalg.solve(D, b.reshape(3, -1).T).T.reshape(b.shape)
+    assert np.all(rel_err_per_rhs(x, x_lu) <= np.linalg.cond(D) * 1e-10)
+    _, ost = ogmres.gmres(lambda v: dirac.apply_dw(U, v, m0), b, 1e-10, restart=30)
+    assert np.all(np.abs(st["iters"] - ost.iters) <= 2)
+    x, st, rc = _solve(U, b, m0, restart=30, eo=True, mode="ir-f32", tol=1e-10, gs=gs)
+    assert rc == lq.OK and np.all(_true_relres(U, b, x, m0) <= 1e-10)
+
+
+@pytest.mark.parametrize("layout", [lq.RHS_OUTER, lq.LAYOUT1, lq.LAYOUT2])
+def test_rhs_chunked_solves(gpu_lib, layout):
+    """rhs_block: a solve in chunks of consecutive rhs gives every rhs the
+    result of the unchunked solve (the same arithmetic per rhs up to the
+    order of partial sums): the fixed 10 x 10 protocol to 1e-12, converged
+    solves to the residual bound with the same step counts (+-1), in FP64
+    and FP32 refinement, with and without an initial guess; with
+    rhs_block = 0 and a workspace that holds only two rhs the library picks
+    width 2."""
+    import torch
+
+    dims = (4, 4, 4, 8)
+    m0 = 0.1
+    U = syn.gauge_field(dims, "near_identity", config=7, eps=0.3)
+    b = syn.spinor_block(dims, 6, config=7)
+    xa, sa, _ = _solve(U, b, m0, layout=layout, eo=True, restart=10, max_restarts=10, fixed_iters=True)
+    xc, sc, rc = _solve(U, b, m0, layout=layout, eo=True, restart=10, max_restarts=10, fixed_iters=True, rhs_block=4)
+    assert rc == lq.OK and np.all(sc["iters"] == sa["iters"])
+    assert np.all(rel_err_per_rhs(xc, xa) <= 1e-12)
+    for mode in ("f64", "ir-f32"):
+        xa, sa, _ = _solve(U, b, m0, layout=layout, eo=True, mode=mode, tol=1e-10)
+        xc, sc, rc = _solve(U, b, m0, layout=layout, eo=True, mode=mode, tol=1e-10, rhs_block=4)
+        assert rc == lq.OK and np.all(_true_relres(U, b, xc, m0) <= 1e-10), mode
+        assert np.all(np.abs(sc["iters"] - sa["iters"]) <= 1), mode
+        assert np.all(rel_err_per_rhs(xc, xa) <= 1e-8), mode
+    # an initial guess: chunks read their columns of x0
+    xg, sg, rc = _solve(U, b, m0, layout=layout, x0=xa, eo=True, tol=1e-9, rhs_block=5)
+    assert rc == lq.OK and np.all(sg["iters"] == 0)
+    # automatic width from the workspace
+    p = lq.solver_params(eo=True, tol=1e-10, rhs_block=2)
+    work = torch.empty(lq.gmres_workspace_bytes(dims, 6, p), dtype=torch.uint8, device="cuda")
+    p0 = lq.solver_params(eo=True, tol=1e-10)
+    assert lq.gmres_rhs_block(dims, 6, p0, work.numel()) == 2
+    xw, sw, rc = _solve(U, b, m0, layout=layout, work=work, eo=True, tol=1e-10)
+    assert rc == lq.OK and np.all(_true_relres(U, b, xw, m0) <= 1e-10)
