@@ -145,6 +145,15 @@ int dirac_apply(const lqcd_lattice* lat, const void* U, const void* psi, void* e
 int dirac_apply_eo(const lqcd_lattice* lat, const void* U, const void* psi_e, void* eta_e,
                    int nrhs, double m0, int layout, int prec, int flags, void* stream);
 
+/* dirac_apply_eo with the odd temporary in a caller workspace (device, at
+ * least dirac_apply_eo_workspace_bytes() = V/2 x 12 x nrhs complex numbers
+ * of `prec`; LQCD_ERR_WORKSPACE if smaller): no allocation, the same two hop
+ * passes.  The workspace size is 0 for invalid arguments. */
+size_t dirac_apply_eo_workspace_bytes(const lqcd_lattice* lat, int nrhs, int prec);
+int dirac_apply_eo_ws(const lqcd_lattice* lat, const void* U, const void* psi_e, void* eta_e,
+                      int nrhs, double m0, int layout, int prec, int flags, void* work,
+                      size_t work_bytes, void* stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * Schur apply as dirac_apply_eo, with its odd half-lattice temporary in a

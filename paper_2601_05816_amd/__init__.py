@@ -86,6 +86,10 @@ def load():
     lib.lqcd_lattice_tables.argtypes = [lp, vp, vp]
     lib.dirac_apply.argtypes = [lp, vp, vp, vp, i32, dbl, i32, i32, i32, vp]
     lib.dirac_apply_eo.argtypes = [lp, vp, vp, vp, i32, dbl, i32, i32, i32, vp]
+    lib.dirac_apply_eo_ws.argtypes = [lp, vp, vp, vp, i32, dbl, i32, i32, i32, vp, ctypes.c_size_t, vp]
+    lib.dirac_apply_eo_ws.restype = i32
+    lib.dirac_apply_eo_workspace_bytes.argtypes = [lp, i32, i32]
+    lib.dirac_apply_eo_workspace_bytes.restype = ctypes.c_size_t
     lib.dirac_apply_eo_noalloc.argtypes = [lp, vp, vp, vp, i32, dbl, i32, i32, i32, vp]
     lib.dirac_apply_eo_noalloc.restype = i32
     lib.dirac_apply_clover.argtypes = [lp, vp, vp, vp, vp, i32, dbl, i32, i32, i32, vp]
@@ -286,6 +290,31 @@ def dirac_apply_eo(U, psi_e, m0, layout=LAYOUT2, dagger=False, out=None):
     _check(load().dirac_apply_eo(ctypes.byref(_lattice(dims)), U.data_ptr(), psi_e.data_ptr(), out.data_ptr(),
                                  nrhs, float(m0), layout, prec, DAGGER if dagger else 0, _stream()))
     return out
+
+
+def dirac_apply_eo_ws(U, psi_e, m0, work, layout=LAYOUT2, dagger=False, out=None):
+    """dirac_apply_eo with the odd temporary in `work` (a device uint8 tensor
+    of at least dirac_apply_eo_workspace_bytes bytes; nothing is allocated
+    when `out` is given)."""
+    import torch
+
+    prec = _prec_of(psi_e)
+    if _prec_of(U) != prec:
+        raise TypeError("U and psi_e must have the same precision")
+    dims = _dims_of_links(U, prec)
+    nrhs, sdims = _nrhs_of(psi_e, prec, layout, 1)
+    if int(sdims[0]) * 2 != int(np.prod(dims)):
+        raise ValueError(f"half-lattice block has {sdims[0]} sites, lattice {dims} needs {int(np.prod(dims)) // 2}")
+    out = torch.empty_like(psi_e) if out is None else out
+    _check_device(U, psi_e, out, work)
+    _check(load().dirac_apply_eo_ws(ctypes.byref(_lattice(dims)), U.data_ptr(), psi_e.data_ptr(), out.data_ptr(),
+                                    nrhs, float(m0), layout, prec, DAGGER if dagger else 0, work.data_ptr(),
+                                    work.numel(), _stream()))
+    return out
+
+
+def dirac_apply_eo_workspace_bytes(dims, nrhs, prec):
+    return int(load().dirac_apply_eo_workspace_bytes(ctypes.byref(_lattice(dims)), int(nrhs), int(prec)))
 
 
 def dirac_apply_eo_noalloc(U, psi_e, m0, out, layout=LAYOUT2, dagger=False):

@@ -99,6 +99,32 @@ int dirac_apply(const lqcd_lattice* lat, const void* U, const void* psi, void* e
   return hip_status(e, "dirac_apply launch");
 }
 
+size_t dirac_apply_eo_workspace_bytes(const lqcd_lattice* lat, int nrhs, int prec) {
+  if (check_lattice(lat) || nrhs < 1 || (prec != LQCD_F64 && prec != LQCD_F32 && prec != LQCD_F16)) return 0;
+  const size_t V = (size_t)lat->dims[0] * lat->dims[1] * lat->dims[2] * lat->dims[3];
+  const size_t esz = prec == LQCD_F64 ? 16 : prec == LQCD_F32 ? 8 : 4;
+  return V / 2 * 12 * (size_t)nrhs * esz;
+}
+
+int dirac_apply_eo_ws(const lqcd_lattice* lat, const void* U, const void* psi_e, void* eta_e, int nrhs, double m0,
+                      int layout, int prec, int flags, void* work, size_t work_bytes, void* stream) {
+  int rc = check_lattice(lat);
+  if (rc) return rc;
+  if ((rc = check_block(nrhs, layout, prec))) return rc;
+  if (!U || !psi_e || !eta_e) return fail(LQCD_ERR_ARG, "dirac_apply_eo_ws: null array pointer");
+  if (flags & ~LQCD_DAGGER) return fail(LQCD_ERR_ARG, "dirac_apply_eo_ws: unknown flags 0x%x", flags);
+  const double d = 4.0 + m0;
+  if (d == 0.0) return fail(LQCD_ERR_SINGULAR, "dirac_apply_eo_ws: 4 + m0 = 0, D_oo is not invertible");
+  const size_t need = dirac_apply_eo_workspace_bytes(lat, nrhs, prec);
+  if (!work || work_bytes < need)
+    return fail(LQCD_ERR_WORKSPACE, "dirac_apply_eo_ws: workspace of %zu bytes given, %zu needed", work_bytes, need);
+  hipStream_t s = (hipStream_t)stream;
+  const bool dag = (flags & LQCD_DAGGER) != 0;
+  hipError_t e = wilson_eo(lat, U, psi_e, nullptr, work, 1, nrhs, 0.0, 1.0, layout, prec, dag, nullptr, s);
+  if (e == hipSuccess) e = wilson_eo(lat, U, work, psi_e, eta_e, 0, nrhs, d, -0.25 / d, layout, prec, dag, nullptr, s);
+  return hip_status(e, "dirac_apply_eo_ws launch");
+}
+
 int dirac_apply_eo(const lqcd_lattice* lat, const void* U, const void* psi_e, void* eta_e, int nrhs, double m0,
                    int layout, int prec, int flags, void* stream) {
   int rc = check_lattice(lat);
