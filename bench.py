@@ -13,9 +13,16 @@ fixed 100-iteration protocol, block GMRES, the clover operator, the uneven
 multi-lattice batch, differentiation, small lattices) and the oracle's CPU
 throughput on a sample of the same apply (two of the 16 rhs).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-sweep] [--no-cpu]
-    python bench.py --only {sweep-f64,schur-f64,clover-f64,gmres-fixed,block-fixed,gmres-ir}
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-sweep] [--no-cpu] [--no-counters]
+    python bench.py --only {apply,sweep-f64,schur-f64,clover-f64,gmres-fixed,block-fixed,gmres-ir}
+                    [--prec f64|f32|f16] [--kind full|schur] [--nrhs N] [--calibrate]
                                     (one workload, for profilers)
+
+The headline kernel's HBM traffic (roofline.traffic) is measured in the same
+run: two child processes run `--only apply --calibrate` under
+`rocprofv3 --pmc FETCH_SIZE` and `--pmc WRITE_SIZE` before this process
+touches the GPU, and the counters are scaled by what they report for a plain
+device copy of known size in the same child (`--no-counters` skips this).
 """
 from __future__ import annotations
 
@@ -39,17 +46,6 @@ FLOP_SITE_RHS = 1392          # 1320 projected hopping + 72 diagonal/combine
 SCHUR_FLOP_SITE_RHS = 2712    # per even site: two hopping passes + axpy
 HBM_PEAK_GBS = 8000.0
 TUNE_FILE = os.path.join(ROOT, "paper_2601_05816_amd", "tune_mi355x.txt")
-# HBM traffic of the headline kernel per launch, from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE (scaled by what the counters report for a plain device copy of
-# known size), keyed by kernel configuration (variant, tile_y, tile_z,
-# segments, nontemporal, wg_per_cu); reported only for the configuration the
-# counters were taken on.
-TRAFFIC = {
-    (3, 4, 4, 1, 1, 1): {"read_bytes": 16_833_717_000, "write_bytes": 6_442_452_000,
-                         "profile": "profiles/wilson_full_pencil_32x32x32x64_nrhs16_f64.md"},
-}
-
-
 def bytes_full(v, nrhs, esz):
     """Algorithmic bytes of one full apply: every link, input and output element once."""
     return (36 + 24 * nrhs) * esz * v
@@ -116,31 +112,101 @@ def to_f16(t):
     return torch.view_as_real(t.to(torch.complex64)).to(torch.float16).contiguous()
 
 
-def gmres_section(lq, U64, psi64, nrhs):
+def measure_traffic(steps=3):
+    """HBM bytes per launch of the headline apply from rocprofv3 counters,
+    each counter in a child process of its own (this process has not
+    initialised the GPU yet).  Scale: true bytes of the probe's plain copy
+    over what the counter reports for it.  Returns (traffic dict, None) or
+    (None, reason)."""
+    import csv
+    import glob
+    import shutil
+    import subprocess
+    import tempfile
+
+    prof = shutil.which("rocprofv3") or "/opt/rocm/bin/rocprofv3"
+    if not os.path.exists(prof):
+        return None, "rocprofv3 not found"
+    out = {}
+    with tempfile.TemporaryDirectory(prefix="lqcd_pmc_") as tmp:
+        env = dict(os.environ, TMPDIR=tmp)
+        for counter in ("FETCH_SIZE", "WRITE_SIZE"):
+            d = os.path.join(tmp, counter)
+            cmd = [prof, "--pmc", counter, "-d", d, "-o", "run", "--output-format", "csv", "--",
+                   sys.executable, os.path.abspath(__file__), "--only", "apply", "--calibrate",
+                   "--steps", str(steps), "--warmup", "1"]
+            try:
+                r = subprocess.run(cmd, capture_output=True, text=True, timeout=240, env=env, cwd=ROOT)
+            except subprocess.TimeoutExpired:
+                return None, f"rocprofv3 {counter} run timed out"
+            files = glob.glob(os.path.join(d, "**", "run_counter_collection.csv"), recursive=True)
+            if r.returncode not in (0, 139) or not files:
+                return None, f"rocprofv3 {counter} run failed (status {r.returncode}): {r.stderr[-300:]}"
+            vals = {}
+            for row in csv.DictReader(open(files[0])):
+                vals.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]))
+            info = json.loads([l for l in r.stdout.splitlines() if l.startswith("{")][-1])
+            wk = [k for k in vals if "k_wilson_full" in k]
+            ck = [k for k in vals if "k_copy<4, false>" in k]
+            if len(wk) != 1 or not ck:
+                return None, f"{counter}: kernels not found in the counter output ({list(vals)[:4]})"
+            kib = float(np.mean(vals[wk[0]]))
+            copy_kib = float(np.mean([v for k in ck for v in vals[k]]))
+            true_copy = info["copy_bytes_per_array"]  # bytes read and bytes written by one copy launch
+            out[counter] = {"kib_per_launch": kib, "copy_kib_per_launch": copy_kib, "scale": true_copy / (copy_kib * 1024),
+                            "bytes_per_launch": kib * 1024 * true_copy / (copy_kib * 1024), "kernel": wk[0][:80],
+                            "launches": len(vals[wk[0]])}
+    read, write = out["FETCH_SIZE"]["bytes_per_launch"], out["WRITE_SIZE"]["bytes_per_launch"]
+    return {"read_bytes": round(read), "write_bytes": round(write), "total_bytes": round(read + write),
+            "fetch_scale": round(out["FETCH_SIZE"]["scale"], 4), "write_scale": round(out["WRITE_SIZE"]["scale"], 4),
+            "kernel": out["FETCH_SIZE"]["kernel"], "launches_counted": out["FETCH_SIZE"]["launches"],
+            "method": "rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, one child process each (bench.py --only apply "
+                      "--calibrate), scaled by the counters of a plain device copy of known size"}, None
+
+
+def solve_times(lq, U64, b, mode, reps, warm, work, **kw):
+    """Wall-clock seconds of `reps` solves after `warm` warm-up solves (all to
+    the same tolerance, same workspace); returns (times, x, stats, status)."""
+    import torch
+
+    times, x, st, rc = [], None, None, None
+    for i in range(warm + reps):
+        torch.cuda.synchronize()
+        t = time.time()
+        x, st, rc = lq.gmres_solve(U64, b, M0, layout=lq.LAYOUT2, work=work, mode=mode, **kw)
+        torch.cuda.synchronize()
+        if i >= warm:
+            times.append(time.time() - t)
+    return times, x, st, rc
+
+
+def time_stats(ts):
+    ts = sorted(ts)
+    return {"seconds": round(float(np.median(ts)), 3), "seconds_min": round(ts[0], 3),
+            "seconds_max": round(ts[-1], 3), "solves_timed": len(ts)}
+
+
+def gmres_section(lq, U64, psi64, nrhs, reps=3):
     """Time to a true relative residual of 1e-10 of the full system with odd-even
     GMRES(30): FP64 against FP64 refinement around FP32 and FP16-storage inner
-    solves; plus the fixed 100-iteration protocol (10 restarts of 10)."""
+    solves, each the median of `reps` solves after a warm-up solve; plus the
+    fixed 100-iteration protocol (10 restarts of 10)."""
     import torch
 
     b = psi64[..., :nrhs].contiguous()
     out = {"lattice": list(DIMS), "nrhs": nrhs, "m0": M0, "restart": 30, "eo": True, "tol": 1e-10}
     sols = {}
+    kw = dict(restart=30, eo=True, tol=1e-10, max_restarts=400, max_outer=60)
     for mode in ("f64", "ir-f32", "ir-f16"):
-        p = lq.solver_params(restart=30, eo=True, mode=mode, tol=1e-10, max_restarts=400, max_outer=60)
+        p = lq.solver_params(mode=mode, **kw)
         work = torch.empty(lq.gmres_workspace_bytes(DIMS, nrhs, p), dtype=torch.uint8, device=b.device)
-        torch.cuda.synchronize()
-        t = time.time()
-        x, st, rc = lq.gmres_solve(U64, b, M0, layout=lq.LAYOUT2, work=work, restart=30, eo=True, mode=mode,
-                                   tol=1e-10, max_restarts=400, max_outer=60)
-        torch.cuda.synchronize()
-        dt = time.time() - t
+        ts, x, st, rc = solve_times(lq, U64, b, mode, reps, 1, work, **kw)
         sols[mode] = x
-        rec = {"seconds": round(dt, 3), "converged": bool(st["converged"].all()), "status": int(rc),
-               "max_true_relres": float(st["true_relres"].max()),
-               "true_relres_per_rhs": [float("%.3e" % v) for v in st["true_relres"]],
-               "iters_max": int(st["iters"].max()),
-               "iters_mean": float(st["iters"].mean()), "outer_max": int(st["outer_iters"].max()),
-               "workspace_gb": round(work.numel() / 1e9, 2)}
+        rec = dict(time_stats(ts), converged=bool(st["converged"].all()), status=int(rc),
+                   max_true_relres=float(st["true_relres"].max()),
+                   true_relres_per_rhs=[float("%.3e" % v) for v in st["true_relres"]],
+                   iters_max=int(st["iters"].max()), iters_mean=float(st["iters"].mean()),
+                   outer_max=int(st["outer_iters"].max()), workspace_gb=round(work.numel() / 1e9, 2))
         if mode != "f64":
             # per rhs: ||x_mode - x_f64|| / ||x_f64|| (the FP64 GPU solve is checked against the oracle in tests)
             d = (x - sols["f64"]).reshape(-1, nrhs)
@@ -154,18 +220,63 @@ def gmres_section(lq, U64, psi64, nrhs):
     out["speedup_ir_f32"] = round(out["f64"]["seconds"] / out["ir-f32"]["seconds"], 3)
     out["speedup_ir_f16"] = round(out["f64"]["seconds"] / out["ir-f16"]["seconds"], 3)
     # the paper's solver protocol: exactly 100 iterations (10 restarts x 10), FP64
-    p = lq.solver_params(restart=10, max_restarts=10, eo=True, fixed_iters=True)
-    work = torch.empty(lq.gmres_workspace_bytes(DIMS, nrhs, p), dtype=torch.uint8, device=b.device)
-    torch.cuda.synchronize()
-    t = time.time()
-    x, st, rc = lq.gmres_solve(U64, b, M0, layout=lq.LAYOUT2, work=work, restart=10, max_restarts=10, eo=True,
-                               fixed_iters=True)
-    torch.cuda.synchronize()
-    dt = time.time() - t
-    out["fixed_100_iterations_f64"] = {"seconds": round(dt, 3), "ms_per_iteration": round(dt * 10, 3),
-                                       "true_relres_max": float(st["true_relres"].max())}
-    log(f"GMRES fixed 100 iterations: {dt:.3f} s")
+    kwf = dict(restart=10, max_restarts=10, eo=True, fixed_iters=True)
+    work = torch.empty(lq.gmres_workspace_bytes(DIMS, nrhs, lq.solver_params(**kwf)), dtype=torch.uint8,
+                       device=b.device)
+    ts, x, st, rc = solve_times(lq, U64, b, "f64", reps, 1, work, **kwf)
+    out["fixed_100_iterations_f64"] = dict(time_stats(ts), ms_per_iteration=round(float(np.median(ts)) * 10, 3),
+                                           true_relres_max=float(st["true_relres"].max()))
+    log(f"GMRES fixed 100 iterations: {json.dumps(out['fixed_100_iterations_f64'])}")
     return out
+
+
+def gmres_nrhs_sweep(lq, U64, psi64, result16=None):
+    """Odd-even GMRES(30) to a true 1e-10 at nrhs 1, 4, 8, 16, 32 and 64 in the
+    three modes (one timed solve per point after a warm-up solve per mode).
+    Sources: the benchmark's 16 host-generated rhs, continued beyond 16 by
+    Gaussian rhs drawn on the GPU from a seeded generator.  The workspace is
+    the full width when it fits the free device memory (less a margin), else
+    the largest that does; the library then solves in chunks of the width
+    it picks (logged)."""
+    import torch
+
+    g = torch.Generator(device=psi64.device).manual_seed(1000 + CONFIG)
+    extra = torch.randn(DIMS + (4, 3, 48), dtype=torch.complex128, device=psi64.device, generator=g)
+    src = torch.cat([psi64, extra], dim=-1)
+    del extra
+    kw = dict(restart=30, eo=True, tol=1e-10, max_restarts=400, max_outer=60)
+    pts = []
+    for mode in ("f64", "ir-f32", "ir-f16"):
+        warmed = False
+        for n in (1, 4, 8, 16, 32, 64):
+            if n == 16 and result16 is not None:
+                r = result16[mode]
+                pts.append({"nrhs": n, "mode": mode, "seconds": r["seconds"], "seconds_per_rhs":
+                            round(r["seconds"] / n, 4), "rhs_block": n, "converged": r["converged"],
+                            "max_true_relres": r["max_true_relres"], "iters_max": r["iters_max"],
+                            "source": "gmres section (median of its solves)"})
+                continue
+            b = src[..., :n].contiguous()
+            full = lq.gmres_workspace_bytes(DIMS, n, lq.solver_params(mode=mode, **kw))
+            free, _ = torch.cuda.mem_get_info()
+            nbytes = min(full, free - b.numel() * 16 - (8 << 30))
+            p = lq.solver_params(mode=mode, **kw)
+            width = lq.gmres_rhs_block(DIMS, n, p, nbytes)
+            work = torch.empty(lq.gmres_workspace_bytes(DIMS, n, lq.solver_params(mode=mode, rhs_block=width, **kw)),
+                               dtype=torch.uint8, device=b.device)
+            ts, x, st, rc = solve_times(lq, U64, b, mode, 1, 0 if warmed else 1, work, **kw)
+            warmed = True
+            rec = {"nrhs": n, "mode": mode, "seconds": round(ts[0], 3), "seconds_per_rhs": round(ts[0] / n, 4),
+                   "rhs_block": width, "converged": bool(st["converged"].all()), "status": int(rc),
+                   "max_true_relres": float(st["true_relres"].max()), "iters_max": int(st["iters"].max()),
+                   "workspace_gb": round(work.numel() / 1e9, 2)}
+            log(f"GMRES sweep: {json.dumps(rec)}")
+            pts.append(rec)
+            del work, x, b
+            torch.cuda.empty_cache()
+    del src
+    torch.cuda.empty_cache()
+    return pts
 
 
 def block_gmres_section(lq, U64, psi64, nrhs, batched=None):
@@ -464,7 +575,40 @@ def profile_only(args):
     v = int(np.prod(DIMS))
     U = torch.randn((4,) + DIMS + (3, 3), dtype=torch.complex128, device=dev, generator=g)
     out = {"mode": args.only, "lattice": list(DIMS), "steps": args.steps, "warmup": args.warmup}
-    if args.only == "sweep-f64":
+    if args.only == "apply":
+        prec = {"f64": lq.F64, "f32": lq.F32, "f16": lq.F16}[args.prec]
+        n = args.nrhs
+
+        def conv(x):
+            if prec == lq.F64:
+                return x
+            return x.to(torch.complex64) if prec == lq.F32 else to_f16(x)
+
+        Up = conv(U)
+        if args.kind == "full":
+            x = conv(torch.randn(DIMS + (4, 3, n), dtype=torch.complex128, device=dev, generator=g))
+            y = torch.empty_like(x)
+            fn = lambda: lq.dirac_apply(Up, x, M0, layout=lq.LAYOUT2, out=y)
+            alg = bytes_full(v, n, {lq.F64: 16, lq.F32: 8, lq.F16: 4}[prec])
+        else:
+            x = conv(torch.randn((v // 2, 4, 3, n), dtype=torch.complex128, device=dev, generator=g))
+            y = torch.empty_like(x)
+            wk = torch.empty(lq.dirac_apply_eo_workspace_bytes(DIMS, n, prec), dtype=torch.uint8, device=dev)
+            fn = lambda: lq.dirac_apply_eo_ws(Up, x, M0, wk, layout=lq.LAYOUT2, out=y)
+            alg = bytes_schur_two_pass(v, n, {lq.F64: 16, lq.F32: 8, lq.F16: 4}[prec])
+        ms = timed(fn, args.steps, args.warmup)
+        out.update(prec=args.prec, kind=args.kind, nrhs=n, ms=round(ms, 4), algorithmic_bytes=alg,
+                   gbs_algorithmic=round(alg / ms / 1e6, 1))
+        log(f"{args.kind} {args.prec} nrhs {n}: {ms:.4f} ms")
+        if args.calibrate:
+            del x, y, Up, U
+            torch.cuda.empty_cache()
+            na = 1 << 28  # doubles per array: 2 GiB read and 2 GiB written per copy launch
+            a = torch.ones(na, dtype=torch.float64, device=dev)
+            b = torch.empty_like(a)
+            lq.hbm_probe(a, b, kind="copy", reps=1)
+            out["copy_bytes_per_array"] = na * 8
+    elif args.only == "sweep-f64":
         pts = []
         for n in (1, 4, 8, 16, 32, 64):  # dispatches: warmup + steps launches per point, in this order
             psi = torch.randn(DIMS + (4, 3, n), dtype=torch.complex128, device=dev, generator=g)
@@ -477,7 +621,8 @@ def profile_only(args):
     elif args.only == "schur-f64":
         xe = torch.randn((v // 2, 4, 3, NRHS), dtype=torch.complex128, device=dev, generator=g)
         ye = torch.empty_like(xe)
-        ms = timed(lambda: lq.dirac_apply_eo(U, xe, M0, layout=lq.LAYOUT2, out=ye), args.steps, args.warmup)
+        wk = torch.empty(lq.dirac_apply_eo_workspace_bytes(DIMS, NRHS, lq.F64), dtype=torch.uint8, device=dev)
+        ms = timed(lambda: lq.dirac_apply_eo_ws(U, xe, M0, wk, layout=lq.LAYOUT2, out=ye), args.steps, args.warmup)
         out.update(nrhs=NRHS, schur_ms=round(ms, 4))
     elif args.only == "clover-f64":  # D = D_W - C: full apply, then the Schur apply (two passes)
         C = 0.1 * torch.randn(DIMS + (42,), dtype=torch.complex128, device=dev, generator=g)
@@ -569,10 +714,18 @@ def main():
                     help="kernel configurations measured by the autotuner on MI355X (used when present)")
     ap.add_argument("--retune", action="store_true", help="ignore the tune file and autotune every apply")
     ap.add_argument("--save-tune", default="", help="write the autotuner's table here at the end")
-    ap.add_argument("--only", choices=["sweep-f64", "schur-f64", "clover-f64", "gmres-fixed", "block-fixed", "gmres-ir"],
+    ap.add_argument("--only", choices=["apply", "sweep-f64", "schur-f64", "clover-f64", "gmres-fixed", "block-fixed",
+                                       "gmres-ir"],
                     default="",
                     help="profiling mode: run one workload only (GPU-drawn inputs except the near-identity links of "
                          "gmres-ir, tune file), print its times")
+    ap.add_argument("--prec", choices=["f64", "f32", "f16"], default="f64", help="--only apply: storage precision")
+    ap.add_argument("--kind", choices=["full", "schur"], default="full", help="--only apply: full D_W or Schur S")
+    ap.add_argument("--nrhs", type=int, default=NRHS, help="--only apply: rhs count")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="--only apply: also run the HBM probe's plain copy (for scaling byte counters)")
+    ap.add_argument("--no-counters", action="store_true",
+                    help="skip the rocprofv3 counter runs that measure the headline kernel's HBM traffic")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the multi-rhs apply and GMRES are single-device here "
@@ -581,6 +734,14 @@ def main():
     if args.only:
         profile_only(args)
         return
+
+    # the headline kernel's HBM traffic, counted in child processes before
+    # this one touches the GPU
+    traffic, traffic_note = None, "not measured (--no-counters or a forced kernel configuration)"
+    if not (args.no_counters or args.variant or args.pencil or args.retune) and os.path.exists(args.tune_file):
+        t0c = time.time()
+        traffic, traffic_note = measure_traffic()
+        log(f"counters: {traffic if traffic else traffic_note} ({time.time() - t0c:.0f}s)")
 
     import torch
 
@@ -668,12 +829,12 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
     }
-    key = None if tuned is None else tuple(int(tuned[k]) for k in ("variant", "tile_y", "tile_z", "segments",
-                                                                    "nontemporal", "wg_per_cu"))
-    if key in TRAFFIC:
-        tr = TRAFFIC[key]
-        result["roofline"]["traffic"] = tr["read_bytes"] + tr["write_bytes"]
-        result["traffic_detail"] = dict(tr, key=list(key))
+    if traffic:
+        result["roofline"]["traffic"] = traffic["total_bytes"]
+        result["traffic_detail"] = dict(traffic, over_algorithmic=round(traffic["total_bytes"] / alg_bytes, 3),
+                                        algorithmic_bytes=alg_bytes)
+    else:
+        result["traffic_detail"] = {"note": traffic_note}
 
     if args.copy_calibration:
         n = (2 << 30) // 16
@@ -705,7 +866,9 @@ def main():
                 ye = torch.empty_like(xe)
                 if args.variant == 0 and not args.pencil and not use_table:
                     lq.autotune(Up, xe, ye, M0, layout=lq.LAYOUT2, eo=True, reps=2)
-                t_eo = timed(lambda: lq.dirac_apply_eo(Up, xe, M0, layout=lq.LAYOUT2, out=ye), steps, 2)
+                wk = torch.empty(lq.dirac_apply_eo_workspace_bytes(DIMS, n, prec), dtype=torch.uint8, device=dev)
+                t_eo = timed(lambda: lq.dirac_apply_eo_ws(Up, xe, M0, wk, layout=lq.LAYOUT2, out=ye), steps, 2)
+                del wk
                 rec = {"prec": prec_name, "nrhs": n,
                        "full_ms": round(t_full, 4),
                        "full_gflops": round(FLOP_SITE_RHS * v * n / t_full / 1e6, 1),
@@ -724,29 +887,8 @@ def main():
     # ------------------------------------------------------------------ GMRES
     if not args.no_gmres:
         result["gmres"] = gmres_section(lq, U64, psi64, args.gmres_nrhs)
-        # time to 1e-10 per rhs at smaller blocks (same lattice, first rhs of the block)
-        gs = []
-        for n in (1, 4):
-            if n >= args.gmres_nrhs:
-                continue
-            bn = psi64[..., :n].contiguous()
-            rec = {"nrhs": n}
-            for mode in ("f64", "ir-f32", "ir-f16"):
-                torch.cuda.synchronize()
-                t = time.time()
-                _, st, rc = lq.gmres_solve(U64, bn, M0, layout=lq.LAYOUT2, restart=30, eo=True, mode=mode, tol=1e-10,
-                                           max_restarts=400, max_outer=60)
-                torch.cuda.synchronize()
-                dt = time.time() - t
-                rec[mode.replace("-", "_")] = {"seconds": round(dt, 3), "seconds_per_rhs": round(dt / n, 4),
-                                               "status": int(rc), "iters_max": int(st["iters"].max())}
-            gs.append(rec)
-            log(f"GMRES nrhs={n}: {json.dumps(rec)}")
-        nb16 = result["gmres"]
-        gs.append({"nrhs": args.gmres_nrhs, **{m.replace("-", "_"): {
-            "seconds": nb16[m]["seconds"], "seconds_per_rhs": round(nb16[m]["seconds"] / args.gmres_nrhs, 4),
-            "status": nb16[m]["status"], "iters_max": nb16[m]["iters_max"]} for m in ("f64", "ir-f32", "ir-f16")}})
-        result["gmres_nrhs_sweep"] = gs
+        result["gmres_nrhs_sweep"] = gmres_nrhs_sweep(lq, U64, psi64,
+                                                      result["gmres"] if args.gmres_nrhs == 16 else None)
     if not args.no_block and args.gmres_nrhs <= lq.BLOCK_MAX_RHS:
         result["block_gmres"] = block_gmres_section(lq, U64, psi64, args.gmres_nrhs,
                                                     None if args.no_gmres else result["gmres"]["f64"])
