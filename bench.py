@@ -378,8 +378,9 @@ def batch_section(lq, syn, steps):
     """The uneven eight-lattice batch (L = 8..24, T = 2L, eps_k = 0.2 + 0.3 k/7,
     1..32 rhs each, m0 = -0.05): the FP32 apply of all eight lattices in one
     persistent launch against eight separate launches, and the batched GMRES(30)
-    to a true 1e-10 (FP32 operator inside FP64 refinement, hipGraph-captured
-    Arnoldi steps) against solving the lattices one after the other."""
+    to a true 1e-10 (FP32 operator inside FP64 refinement), eager and with
+    hipGraph-captured Arnoldi steps, against solving the lattices one after
+    the other the same way (each the median of three runs after a warm-up)."""
     import torch
 
     dev = torch.device("cuda:0")
@@ -413,32 +414,51 @@ def batch_section(lq, syn, steps):
     del probs32, outs
     torch.cuda.empty_cache()
     # ------------------------------------------------ batched GMRES vs one solve per lattice
+    # (each the median of three after a warm-up run)
     kw = dict(restart=30, eo=True, mode="ir-f32", tol=1e-10, max_restarts=400, max_outer=60)
-    torch.cuda.synchronize()
-    t = time.time()
-    xs, stats, rc = lq.gmres_solve_batch(probs64, use_graph=True, **kw)
-    torch.cuda.synchronize()
-    t_bs = time.time() - t
-    rec = {"seconds": round(t_bs, 3), "status": int(rc),
-           "converged": bool(all(st["converged"].all() for st in stats)),
-           "max_true_relres": float(max(st["true_relres"].max() for st in stats)),
-           "iters_max": [int(st["iters"].max()) for st in stats]}
-    del xs
+
+    def batched(graph):
+        def f():
+            xs, stats, rc = lq.gmres_solve_batch(probs64, use_graph=graph, **kw)
+            return stats, rc
+        return f
+
+    def sequential(graph):
+        def f():
+            out = []
+            for U, b, m0 in probs64:
+                x, st, rc1 = lq.gmres_solve(U, b, m0, layout=lq.LAYOUT2, use_graph=graph, **kw)
+                out.append(st)
+                del x
+            return out, None
+        return f
+
+    def run(fn):
+        ts, res = [], None
+        for i in range(4):
+            torch.cuda.synchronize()
+            t = time.time()
+            res = fn()
+            torch.cuda.synchronize()
+            if i:
+                ts.append(time.time() - t)
+        return ts, res
+
+    res = {}
+    for graph in (False, True):
+        ts_b, (stats, rc) = run(batched(graph))
+        ts_s, (sstats, _) = run(sequential(graph))
+        rec = dict(time_stats(ts_b), status=int(rc), converged=bool(all(st["converged"].all() for st in stats)),
+                   max_true_relres=float(max(st["true_relres"].max() for st in stats)),
+                   iters_max=[int(st["iters"].max()) for st in stats])
+        seq = dict(time_stats(ts_s), converged=bool(all(st["converged"].all() for st in sstats)),
+                   max_true_relres=float(max(st["true_relres"].max() for st in sstats)))
+        tag = "graph" if graph else "eager"
+        res[tag] = {"batched": rec, "one_lattice_at_a_time": seq,
+                    "speedup_batched": round(seq["seconds"] / rec["seconds"], 3)}
+        log(f"batch GMRES ir-f32 ({tag}): batched {rec['seconds']:.3f} s, one at a time {seq['seconds']:.3f} s")
     torch.cuda.empty_cache()
-    torch.cuda.synchronize()
-    t = time.time()
-    seq_ok, seq_res = True, 0.0
-    for U, b, m0 in probs64:
-        x, st, rc1 = lq.gmres_solve(U, b, m0, layout=lq.LAYOUT2, use_graph=True, **kw)
-        seq_ok &= bool(st["converged"].all())
-        seq_res = max(seq_res, float(st["true_relres"].max()))
-        del x
-    torch.cuda.synchronize()
-    t_ss = time.time() - t
-    out["gmres_ir_f32"] = {"batched": rec, "one_lattice_at_a_time": {"seconds": round(t_ss, 3), "converged": seq_ok,
-                                                                       "max_true_relres": seq_res},
-                           "speedup_batched": round(t_ss / t_bs, 3), "restart": 30, "tol": 1e-10}
-    log(f"batch GMRES ir-f32: batched {t_bs:.3f} s, one at a time {t_ss:.3f} s")
+    out["gmres_ir_f32"] = dict(res, restart=30, tol=1e-10)
     return out
 
 

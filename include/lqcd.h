@@ -239,8 +239,9 @@ int lqcd_set_batch_grid(int blocks);
 int lqcd_set_batch_kernel(int kind);
 
 /* Autotuner for the batch launch: times both kernels with their default
- * grid and persistent grids of 1, 2, 4, 8 and 16 workgroups per CU (eta
- * overwritten), keeps the fastest grid (lqcd_set_batch_grid) and kernel
+ * grid and persistent grids of 1, 2, 4, 8 and 16 workgroups per CU, the
+ * pencil kernel also with its residency capped at 1 or 2 workgroups per CU
+ * (eta overwritten), keeps the fastest grid (lqcd_set_batch_grid), cap and kernel
  * (lqcd_set_batch_kernel: 1 if the one-site kernel wins, else the automatic
  * choice) and returns the winner in best_kernel, best_grid (either may be
  * NULL). */

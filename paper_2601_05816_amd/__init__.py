@@ -79,6 +79,13 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing; build it with `python -m paper_2601_05816_amd.build`")
+    # torch first: the library then binds to the HIP runtime torch loaded, so
+    # device pointers, streams and events are shared by one runtime whatever
+    # order the caller imports them in
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     vp, i32, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
     lp = ctypes.POINTER(Lattice)

@@ -34,6 +34,8 @@ struct batch_desc {
 geo4 make_geo4(const lqcd_lattice* lat);
 hipError_t wilson_batch(batch_desc& d, int prec, bool dagger, hipStream_t s);
 void set_batch_grid(int blocks);
+// Residency cap of the pencil batch launch (workgroups per CU, 0 = none).
+void set_batch_occupancy(int occ);
 // Kernel of the batch launch: 0 automatic (pencils for full-lattice
 // applies, one (site, rhs) per work item for odd-even passes), 1 one
 // (site, rhs) per work item, 2 time-streaming pencils.

@@ -82,8 +82,10 @@ __global__ __launch_bounds__(256) void k_wilson_batch_p(batch_desc d) {
 
 static int g_batch_grid = 0;  // persistent grid size (0 = residency of the chip)
 static int g_batch_kind = 0;
+static int g_batch_occ = 0;   // pencil launch: at most this many workgroups per CU (0 = no cap)
 
 void set_batch_grid(int blocks) { g_batch_grid = blocks > 0 ? blocks : 0; }
+void set_batch_occupancy(int occ) { g_batch_occ = occ > 0 ? occ : 0; }
 void set_batch_kernel(int kind) { g_batch_kind = kind; }
 int batch_kernel() { return g_batch_kind; }
 
@@ -139,7 +141,9 @@ hipError_t wilson_batch(batch_desc& din, int prec, bool dagger, hipStream_t s) {
   if (pencil) grid = g_batch_grid ? (g_batch_grid < 8 ? 8u : (unsigned)g_batch_grid & ~7u) : (unsigned)units;
   else grid = g_batch_grid ? (unsigned)g_batch_grid : batch_grid_default();
   if (grid > units) grid = (unsigned)units;
-#define BL(K, P, SGN) hipLaunchKernelGGL((K<P, SGN>), dim3(grid), dim3(256), 0, s, d)
+  size_t dyn = 0;  // residency cap of the pencil launch through its LDS request
+  if (pencil && !occupancy_lds(g_batch_occ, 0, &dyn)) dyn = 0;
+#define BL(K, P, SGN) hipLaunchKernelGGL((K<P, SGN>), dim3(grid), dim3(256), pencil ? dyn : 0, s, d)
 #define BL_ALL(K)                                         \
   switch (prec * 2 + (dagger ? 1 : 0)) {                  \
     case LQCD_F64 * 2: BL(K, LQCD_F64, 1); break;         \

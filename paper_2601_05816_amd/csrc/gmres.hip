@@ -24,6 +24,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <map>
+#include <tuple>
 #include <vector>
 
 #include "blas.h"
@@ -596,46 +598,63 @@ struct Task {
 // All lattices of one solve, advanced in lock-step on one stream.  With
 // `graph`, the kernels of Arnoldi step j (for every lattice) are captured
 // into a HIP graph the first time they run and replayed in later cycles.
+// With several lattices, each lattice's Gram-Schmidt and Givens kernels of a
+// step run on a stream of its own (forked from and joined back to the
+// group's stream around the one batched Wilson launch), so the small
+// kernels of different lattices overlap, and lattices with no rhs left in
+// the cycle are left out of the launches; captured step graphs are keyed by
+// the set of lattices they launch.
 struct Group {
   std::vector<Task> T;
   hipStream_t s;
   int m;
   bool graph;
-  std::vector<hipGraphExec_t> exec[3];  // per precision, per step j
+  std::map<std::tuple<int, int, unsigned>, hipGraphExec_t> exec;  // (precision, step j, lattice mask)
+  std::map<std::tuple<int, int, unsigned>, int> seen;              // occurrences of uncaptured keys
   int* pinned;                          // 2 ints per lattice
   hipEvent_t ev[2];
   bool block = false;                   // block GMRES (one lattice) instead of batched
+  std::vector<hipStream_t> ts;          // per-lattice streams (several lattices only)
+  std::vector<hipEvent_t> tev;          // per-lattice join events
+  hipEvent_t fork = nullptr;
 };
+
+static unsigned mask_of(const std::vector<int>& act) {
+  unsigned m = 0;
+  for (int k : act) m |= 1u << k;
+  return m;
+}
 
 // out = A in for every lattice, in precision prec (in/out chosen per task)
 template <class In, class Out>
-static hipError_t apply_all(Group& G, int prec, In in_of, Out out_of, bool masked) {
+static hipError_t apply_all(Group& G, int prec, In in_of, Out out_of, bool masked, const std::vector<int>& act) {
   if (G.T.size() == 1) {
     Solver& S = G.T[0].S;
     return S.apply(prec, in_of(G.T[0]), out_of(G.T[0]), masked ? S.live : nullptr);
   }
   batch_desc d;
-  d.n = (int)G.T.size();
+  d.n = (int)act.size();
+  if (d.n == 0) return hipSuccess;
   const bool eo = G.T[0].S.eo;
   const bool dag = G.T[0].S.dag;
-  for (int k = 0; k < d.n; ++k) {
-    Solver& S = G.T[k].S;
-    batch_prob& b = d.p[k];
+  for (int i = 0; i < d.n; ++i) {
+    Solver& S = G.T[act[i]].S;
+    batch_prob& b = d.p[i];
     b.g = make_geo4(&S.lat);
     b.U = prec == LQCD_F64 ? S.U64 : S.Ulo;
     b.live = masked ? S.live : nullptr;
     b.nrhs = S.nrhs;
     if (eo) {  // first hop pass: tmp_o = H_oe in
-      b.in = in_of(G.T[k]);
+      b.in = in_of(G.T[act[i]]);
       b.xin = nullptr;
       b.out = prec == LQCD_F64 ? S.tmp64 : S.tmplo;
       b.parity = 1;
       b.alpha = 0.0;
       b.beta = 1.0;
     } else {
-      b.in = in_of(G.T[k]);
+      b.in = in_of(G.T[act[i]]);
       b.xin = nullptr;
-      b.out = out_of(G.T[k]);
+      b.out = out_of(G.T[act[i]]);
       b.parity = -1;
       b.alpha = S.d;
       b.beta = -0.5;
@@ -643,12 +662,12 @@ static hipError_t apply_all(Group& G, int prec, In in_of, Out out_of, bool maske
   }
   hipError_t e = wilson_batch(d, prec, dag, G.s);
   if (e != hipSuccess || !eo) return e;
-  for (int k = 0; k < d.n; ++k) {  // second pass: out_e = d in - H_eo tmp_o / (4 d)
-    Solver& S = G.T[k].S;
-    batch_prob& b = d.p[k];
+  for (int i = 0; i < d.n; ++i) {  // second pass: out_e = d in - H_eo tmp_o / (4 d)
+    Solver& S = G.T[act[i]].S;
+    batch_prob& b = d.p[i];
     b.in = prec == LQCD_F64 ? S.tmp64 : S.tmplo;
-    b.xin = in_of(G.T[k]);
-    b.out = out_of(G.T[k]);
+    b.xin = in_of(G.T[act[i]]);
+    b.out = out_of(G.T[act[i]]);
     b.parity = 0;
     b.alpha = S.d;
     b.beta = -0.25 / S.d;
@@ -656,79 +675,100 @@ static hipError_t apply_all(Group& G, int prec, In in_of, Out out_of, bool maske
   return wilson_batch(d, prec, dag, G.s);
 }
 
-// The kernels of Arnoldi step j for every lattice (w = A v_j, CGS, Givens,
-// normalisation).
-static hipError_t arnoldi_step(Group& G, int prec, int j, double sc, double tol, int fixed) {
+// The kernels of Arnoldi step j for the lattices in `act` (w = A v_j, CGS,
+// Givens, normalisation).
+static hipError_t gs_step(Task& t, int prec, int j, int m, double sc, double tol, int fixed, hipStream_t s) {
+  Solver& S = t.S;
+  hipError_t e;
+  const size_t nel = S.nelem;
+  void* w = S.Vk(prec, j + 1);
+  const int nc = (j + 1) * S.nrhs;
+  if (S.gs == 2) {
+    // modified Gram-Schmidt: d_k = <u_k, w> against the vector already
+    // orthogonalised to u_0 .. u_{k-1}, then w -= sk[k]^2 d_k u_k
+    for (int k = 0; k <= j; ++k) {
+      if ((e = dot_parts(prec, S.basis, nel, k, 1, w, nel, S.nrhs, S.live, S.part, S.nblk, s)) != hipSuccess) return e;
+      if ((e = reduce_parts(S.part, S.nblk, 1, S.nrhs, sc, S.hcol + (size_t)k * S.nrhs, s)) != hipSuccess) return e;
+      hipLaunchKernelGGL(k_cgs_coef, dim3(((k + 1) * S.nrhs + 255) / 256), dim3(256), 0, s, k + 1, S.nrhs, S.hcol,
+                         S.sk, S.coef);
+      if ((e = cgs_update(prec, S.Vk(prec, k), nel, 1, S.coef + (size_t)k * S.nrhs, w, nel, S.nrhs, S.live, S.part,
+                          S.nblk, s)) != hipSuccess)
+        return e;
+    }
+  } else {
+    // classical Gram-Schmidt: all dots against the same w, one fused update;
+    // CGS2 repeats the pass on the updated vector and adds its dots
+    for (int pass = 0; pass < (S.gs == 1 ? 2 : 1); ++pass) {
+      zd* hc = pass == 0 ? S.hcol : S.hcol2;
+      for (int k0 = 0; k0 <= j; k0 += DOT_KB) {
+        const int K = (j + 1 - k0) < DOT_KB ? (j + 1 - k0) : DOT_KB;
+        if ((e = dot_parts(prec, S.basis, nel, k0, K, w, nel, S.nrhs, S.live, S.part, S.nblk, s)) != hipSuccess)
+          return e;
+        if ((e = reduce_parts(S.part, S.nblk, K, S.nrhs, sc, hc + (size_t)k0 * S.nrhs, s)) != hipSuccess) return e;
+      }
+      hipLaunchKernelGGL(k_cgs_coef, dim3((nc + 255) / 256), dim3(256), 0, s, j + 1, S.nrhs, hc, S.sk, S.coef);
+      if ((e = cgs_update(prec, S.basis, nel, j + 1, S.coef, w, nel, S.nrhs, S.live, S.part, S.nblk, s)) !=
+          hipSuccess)
+        return e;
+      if (pass == 1) hipLaunchKernelGGL(k_add_zd, dim3((nc + 255) / 256), dim3(256), 0, s, nc, S.hcol2, S.hcol);
+    }
+  }
+  if ((e = reduce_parts(S.part, (int)cgs_update_parts(prec, nel, S.nrhs, S.nblk), 1, S.nrhs, sc, S.nrm, s)) !=
+      hipSuccess)
+    return e;
+  const int lazy = prec == LQCD_F64;
+  hipLaunchKernelGGL(k_arnoldi_col, dim3(S.small_grid()), dim3(64), 0, s, j, m, S.nrhs, S.hcol, S.nrm, S.H, S.cs,
+                     S.sn, S.g, t.bref, tol, fixed, lazy, S.live, S.steps, S.est, S.sk, S.scl);
+  if (!lazy && (e = scale_rhs(prec, w, nel, S.nrhs, S.scl, S.live, s)) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+static hipError_t arnoldi_step(Group& G, int prec, int j, double sc, double tol, int fixed,
+                               const std::vector<int>& act) {
   hipStream_t s = G.s;
   const int m = G.m;
   hipError_t e = apply_all(
       G, prec, [&](Task& t) -> const void* { return t.S.Vk(prec, j); }, [&](Task& t) -> void* { return t.S.Vk(prec, j + 1); },
-      true);
+      true, act);
   if (e != hipSuccess) return e;
-  for (Task& t : G.T) {
-    Solver& S = t.S;
-    const size_t nel = S.nelem;
-    void* w = S.Vk(prec, j + 1);
-    const int nc = (j + 1) * S.nrhs;
-    if (S.gs == 2) {
-      // modified Gram-Schmidt: d_k = <u_k, w> against the vector already
-      // orthogonalised to u_0 .. u_{k-1}, then w -= sk[k]^2 d_k u_k
-      for (int k = 0; k <= j; ++k) {
-        if ((e = dot_parts(prec, S.basis, nel, k, 1, w, nel, S.nrhs, S.live, S.part, S.nblk, s)) != hipSuccess)
-          return e;
-        if ((e = reduce_parts(S.part, S.nblk, 1, S.nrhs, sc, S.hcol + (size_t)k * S.nrhs, s)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_cgs_coef, dim3(((k + 1) * S.nrhs + 255) / 256), dim3(256), 0, s, k + 1, S.nrhs, S.hcol,
-                           S.sk, S.coef);
-        if ((e = cgs_update(prec, S.Vk(prec, k), nel, 1, S.coef + (size_t)k * S.nrhs, w, nel, S.nrhs, S.live, S.part,
-                            S.nblk, s)) != hipSuccess)
-          return e;
-      }
-    } else {
-      // classical Gram-Schmidt: all dots against the same w, one fused update;
-      // CGS2 repeats the pass on the updated vector and adds its dots
-      for (int pass = 0; pass < (S.gs == 1 ? 2 : 1); ++pass) {
-        zd* hc = pass == 0 ? S.hcol : S.hcol2;
-        for (int k0 = 0; k0 <= j; k0 += DOT_KB) {
-          const int K = (j + 1 - k0) < DOT_KB ? (j + 1 - k0) : DOT_KB;
-          if ((e = dot_parts(prec, S.basis, nel, k0, K, w, nel, S.nrhs, S.live, S.part, S.nblk, s)) != hipSuccess)
-            return e;
-          if ((e = reduce_parts(S.part, S.nblk, K, S.nrhs, sc, hc + (size_t)k0 * S.nrhs, s)) != hipSuccess) return e;
-        }
-        hipLaunchKernelGGL(k_cgs_coef, dim3((nc + 255) / 256), dim3(256), 0, s, j + 1, S.nrhs, hc, S.sk, S.coef);
-        if ((e = cgs_update(prec, S.basis, nel, j + 1, S.coef, w, nel, S.nrhs, S.live, S.part, S.nblk, s)) !=
-            hipSuccess)
-          return e;
-        if (pass == 1) hipLaunchKernelGGL(k_add_zd, dim3((nc + 255) / 256), dim3(256), 0, s, nc, S.hcol2, S.hcol);
-      }
-    }
-    if ((e = reduce_parts(S.part, (int)cgs_update_parts(prec, nel, S.nrhs, S.nblk), 1, S.nrhs, sc, S.nrm, s)) !=
-        hipSuccess)
-      return e;
-    const int lazy = prec == LQCD_F64;
-    hipLaunchKernelGGL(k_arnoldi_col, dim3(S.small_grid()), dim3(64), 0, s, j, m, S.nrhs, S.hcol, S.nrm, S.H, S.cs,
-                       S.sn, S.g, t.bref, tol, fixed, lazy, S.live, S.steps, S.est, S.sk, S.scl);
-    if (!lazy && (e = scale_rhs(prec, w, nel, S.nrhs, S.scl, S.live, s)) != hipSuccess) return e;
+  if (G.ts.empty()) {
+    for (int k : act)
+      if ((e = gs_step(G.T[k], prec, j, m, sc, tol, fixed, s)) != hipSuccess) return e;
+    return hipGetLastError();
+  }
+  // fork: every lattice's kernels on its own stream after the batched apply; join
+  if ((e = hipEventRecord(G.fork, s)) != hipSuccess) return e;
+  for (int k : act) {
+    if ((e = hipStreamWaitEvent(G.ts[k], G.fork, 0)) != hipSuccess) return e;
+    if ((e = gs_step(G.T[k], prec, j, m, sc, tol, fixed, G.ts[k])) != hipSuccess) return e;
+    if ((e = hipEventRecord(G.tev[k], G.ts[k])) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(s, G.tev[k], 0)) != hipSuccess) return e;
   }
   return hipGetLastError();
 }
 
-static hipError_t run_step(Group& G, int prec, int j, double sc, double tol, int fixed) {
-  if (!G.graph) return arnoldi_step(G, prec, j, sc, tol, fixed);
-  std::vector<hipGraphExec_t>& ex = G.exec[prec];
-  if (ex.size() < (size_t)G.m) ex.assign(G.m, nullptr);
-  if (!ex[j]) {
+// With graphs, a step is captured the second time its (precision, step,
+// lattice set) occurs and replayed from then on; a set that occurs once (a
+// lattice dropping out at some step of some cycle) runs eagerly instead of
+// paying for a capture it would never reuse.
+static hipError_t run_step(Group& G, int prec, int j, double sc, double tol, int fixed, const std::vector<int>& act) {
+  if (!G.graph) return arnoldi_step(G, prec, j, sc, tol, fixed, act);
+  const auto key = std::make_tuple(prec, j, mask_of(act));
+  if (!G.exec.count(key) && ++G.seen[key] < 2) return arnoldi_step(G, prec, j, sc, tol, fixed, act);
+  hipGraphExec_t& ex = G.exec[key];
+  if (!ex) {
     hipError_t e = hipStreamBeginCapture(G.s, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
-    hipError_t e2 = arnoldi_step(G, prec, j, sc, tol, fixed);
+    hipError_t e2 = arnoldi_step(G, prec, j, sc, tol, fixed, act);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(G.s, &g);
     if (e2 != hipSuccess) return e2;
     if (e != hipSuccess) return e;
-    e = hipGraphInstantiate(&ex[j], g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return e;
   }
-  return hipGraphLaunch(ex[j], G.s);
+  return hipGraphLaunch(ex, G.s);
 }
 
 // One batched GMRES(m) run of A x = b for every lattice, in precision `prec`,
@@ -739,24 +779,30 @@ static int run_gmres(Group& G, int prec, double tol, int max_cycles, int fixed, 
   hipStream_t s = G.s;
   const int m = G.m;
   const int nt = (int)G.T.size();
-  for (int cycle = 0; cycle < max_cycles; ++cycle) {
+  // lattices that may still have work: one whose every rhs is at tolerance at
+  // a cycle start keeps its x and takes no further part in this run
+  std::vector<int> open(nt);
+  for (int k = 0; k < nt; ++k) open[k] = k;
+  for (int cycle = 0; cycle < max_cycles && !open.empty(); ++cycle) {
     // true residual r = b - A x into v_0, |r| per rhs
     if (cycle == 0 && x_zero) {
-      for (Task& t : G.T) {
+      for (int k : open) {
+        Task& t = G.T[k];
         HIPCHK(convert(prec, t.b, prec, t.S.Vk(prec, 0), t.S.nelem, t.S.nrhs, nullptr, s));
         HIPCHK(t.S.norms(prec, t.S.Vk(prec, 0), sc, nullptr));
       }
     } else {
       HIPCHK(apply_all(
           G, prec, [&](Task& t) -> const void* { return t.x; }, [&](Task& t) -> void* { return t.S.Vk(prec, 0); },
-          false));
-      for (Task& t : G.T) {
+          false, open));
+      for (int k : open) {
+        Task& t = G.T[k];
         HIPCHK(b_minus_y(prec, t.b, t.S.Vk(prec, 0), t.S.nelem, t.S.nrhs, nullptr, t.S.part, t.S.nblk, s));
         HIPCHK(reduce_parts(t.S.part, t.S.nblk, 1, t.S.nrhs, sc, t.S.nrm, s));
       }
     }
-    std::vector<int> fl(2 * nt);
-    for (int k = 0; k < nt; ++k) {
+    std::vector<int> fl(2 * nt, 0);
+    for (int k : open) {
       Solver& S = G.T[k].S;
       HIPCHK(hipMemsetAsync(S.flags, 0, 2 * sizeof(int), s));
       hipLaunchKernelGGL(k_cycle_start, dim3(S.small_grid()), dim3(64), 0, s, S.nrhs, m, S.nrm, G.T[k].bref, tol,
@@ -764,23 +810,26 @@ static int run_gmres(Group& G, int prec, double tol, int max_cycles, int fixed, 
       HIPCHK(hipMemcpyAsync(&fl[2 * k], S.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
     }
     HIPCHK(hipStreamSynchronize(s));
-    int active = 0;
-    for (int k = 0; k < nt; ++k) {
+    std::vector<int> act;
+    for (int k : open) {
       if (fl[2 * k + 1]) return fail(LQCD_ERR_NONFINITE, "gmres: non-finite residual norm");
-      active += fl[2 * k];
+      if (fl[2 * k]) act.push_back(k);
     }
-    if (active == 0) break;
-    for (Task& t : G.T) {
+    open = act;
+    if (act.empty()) break;
+    for (int k : act) {
+      Task& t = G.T[k];
       std::vector<int> lv(t.S.nrhs);
       HIPCHK(hipMemcpy(lv.data(), t.S.live, t.S.nrhs * sizeof(int), hipMemcpyDeviceToHost));
       for (int r = 0; r < t.S.nrhs; ++r) t.hs.restarts[r] += lv[r];
       if (prec != LQCD_F64) HIPCHK(scale_rhs(prec, t.S.Vk(prec, 0), t.S.nelem, t.S.nrhs, t.S.scl, t.S.live, s));
     }
+    std::vector<int> step_act = act;  // lattices with live rhs in this cycle's steps
     for (int j = 0; j < m; ++j) {
-      HIPCHK(run_step(G, prec, j, sc, tol, fixed));
+      HIPCHK(run_step(G, prec, j, sc, tol, fixed, step_act));
       // pipelined exit test: read the live counts of the previous step while
-      // this one runs
-      for (int k = 0; k < nt; ++k) {
+      // this one runs; a lattice with none left drops out of the next steps
+      for (int k : step_act) {
         Solver& S = G.T[k].S;
         hipLaunchKernelGGL(k_count_live, dim3(1), dim3(1), 0, s, S.nrhs, S.live, S.nlive + (j & 1));
         HIPCHK(hipMemcpyAsync(G.pinned + 2 * k + (j & 1), S.nlive + (j & 1), sizeof(int), hipMemcpyDeviceToHost,
@@ -789,14 +838,16 @@ static int run_gmres(Group& G, int prec, double tol, int max_cycles, int fixed, 
       HIPCHK(hipEventRecord(G.ev[j & 1], s));
       if (j >= 1) {
         HIPCHK(hipEventSynchronize(G.ev[(j - 1) & 1]));
-        int live = 0;
-        for (int k = 0; k < nt; ++k) live += G.pinned[2 * k + ((j - 1) & 1)];
-        if (live == 0) break;
+        std::vector<int> still;
+        for (int k : step_act)
+          if (G.pinned[2 * k + ((j - 1) & 1)]) still.push_back(k);
+        if (still.empty()) break;
+        step_act = still;
       }
     }
     std::vector<std::vector<int>> steps_h(nt);
     std::vector<std::vector<double>> est_h(nt);
-    for (int k = 0; k < nt; ++k) {
+    for (int k : act) {
       Task& t = G.T[k];
       Solver& S = t.S;
       hipLaunchKernelGGL(k_lsq, dim3(S.small_grid()), dim3(64), 0, s, m, S.nrhs, S.H, S.g, S.steps, S.sk, S.y);
@@ -807,7 +858,7 @@ static int run_gmres(Group& G, int prec, double tol, int max_cycles, int fixed, 
       HIPCHK(hipMemcpyAsync(est_h[k].data(), S.est, S.nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
     }
     HIPCHK(hipStreamSynchronize(s));
-    for (int k = 0; k < nt; ++k)
+    for (int k : act)
       for (int r = 0; r < G.T[k].S.nrhs; ++r) {
         G.T[k].hs.iters[r] += steps_h[k][r];
         if (steps_h[k][r]) G.T[k].hs.est[r] = est_h[k][r];
@@ -1048,9 +1099,11 @@ static int solve_group(Group& G, const lqcd_solver_params* params, lqcd_rhs_stat
           HIPCHK(t.S.norms(LQCD_F64, t.S.r64, 1.0, nullptr));
         }
       } else {
+        std::vector<int> all(G.T.size());
+        for (size_t k = 0; k < all.size(); ++k) all[k] = (int)k;
         HIPCHK(apply_all(
             G, LQCD_F64, [&](Task& t) -> const void* { return t.S.xe; }, [&](Task& t) -> void* { return t.S.r64; },
-            false));
+            false, all));
         for (Task& t : G.T) {
           HIPCHK(b_minus_y(LQCD_F64, t.S.bp, t.S.r64, t.S.nelem, t.S.nrhs, nullptr, t.S.part, t.S.nblk, s));
           HIPCHK(reduce_parts(t.S.part, t.S.nblk, 1, t.S.nrhs, 1.0, t.S.nrm, s));
@@ -1185,11 +1238,36 @@ static int run_group(Group& G, const lqcd_solver_params* params, lqcd_rhs_stats*
     (void)hipHostFree(G.pinned);
     return fail(LQCD_ERR_HIP, "gmres: event creation failed");
   }
-  int rc = solve_group(G, params, stats);
+  int rc = LQCD_OK;
+  if (G.T.size() > 1 && !G.block) {  // per-lattice streams for the Gram-Schmidt kernels of a step
+    if (hipEventCreateWithFlags(&G.fork, hipEventDisableTiming) != hipSuccess)
+      rc = fail(LQCD_ERR_HIP, "gmres: event creation failed");
+    for (size_t k = 0; k < G.T.size() && !rc; ++k) {
+      hipStream_t ts = nullptr;
+      hipEvent_t te = nullptr;
+      if (hipStreamCreateWithFlags(&ts, hipStreamNonBlocking) != hipSuccess) {
+        rc = fail(LQCD_ERR_HIP, "gmres: stream creation failed");
+        break;
+      }
+      G.ts.push_back(ts);
+      if (hipEventCreateWithFlags(&te, hipEventDisableTiming) != hipSuccess) {
+        rc = fail(LQCD_ERR_HIP, "gmres: event creation failed");
+        break;
+      }
+      G.tev.push_back(te);
+    }
+    if (rc || G.ts.size() != G.T.size() || G.tev.size() != G.T.size()) {
+      if (!rc) rc = fail(LQCD_ERR_HIP, "gmres: stream setup failed");
+    }
+  }
+  if (!rc) rc = solve_group(G, params, stats);
   (void)hipStreamSynchronize(G.s);
-  for (auto& v : G.exec)
-    for (hipGraphExec_t x : v)
-      if (x) (void)hipGraphExecDestroy(x);
+  for (hipStream_t ts : G.ts) (void)hipStreamSynchronize(ts);
+  for (auto& kv : G.exec)
+    if (kv.second) (void)hipGraphExecDestroy(kv.second);
+  for (hipEvent_t te : G.tev) (void)hipEventDestroy(te);
+  for (hipStream_t ts : G.ts) (void)hipStreamDestroy(ts);
+  if (G.fork) (void)hipEventDestroy(G.fork);
   (void)hipEventDestroy(G.ev[0]);
   (void)hipEventDestroy(G.ev[1]);
   (void)hipHostFree(G.pinned);

@@ -291,27 +291,34 @@ int lqcd_autotune_batch(int nprob, const lqcd_problem* probs, int prec, int reps
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return fail(LQCD_ERR_HIP, "lqcd_autotune_batch: event creation failed");
   double best_ms = 1e300;
-  int best = 0, bestk = 0;
+  int best = 0, bestk = 0, besto = 0;
   int rc = LQCD_OK;
   for (int kind : {1, 2}) {
     if ((rc = lqcd_set_batch_kernel(kind))) break;
-    for (int per_cu : {0, 1, 2, 4, 8, 16}) {  // 0: default grid of the kernel
-      if ((rc = lqcd_set_batch_grid(per_cu * ncu))) break;
-      if ((rc = dirac_apply_batch(nprob, probs, prec, 0, stream))) break;
-      (void)hipEventRecord(e0, (hipStream_t)stream);
-      for (int r = 0; r < reps; ++r) (void)dirac_apply_batch(nprob, probs, prec, 0, stream);
-      (void)hipEventRecord(e1, (hipStream_t)stream);
-      (void)hipEventSynchronize(e1);
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      if (ms / reps < best_ms) {
-        best_ms = ms / reps;
-        best = per_cu * ncu;
-        bestk = kind;
+    for (int occ : {0, 1, 2}) {  // residency cap of the pencil launch
+      if (kind == 1 && occ) continue;
+      set_batch_occupancy(occ);
+      for (int per_cu : {0, 1, 2, 4, 8, 16}) {  // 0: default grid of the kernel
+        if ((rc = lqcd_set_batch_grid(per_cu * ncu))) break;
+        if ((rc = dirac_apply_batch(nprob, probs, prec, 0, stream))) break;
+        (void)hipEventRecord(e0, (hipStream_t)stream);
+        for (int r = 0; r < reps; ++r) (void)dirac_apply_batch(nprob, probs, prec, 0, stream);
+        (void)hipEventRecord(e1, (hipStream_t)stream);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms / reps < best_ms) {
+          best_ms = ms / reps;
+          best = per_cu * ncu;
+          bestk = kind;
+          besto = occ;
+        }
       }
+      if (rc) break;
     }
     if (rc) break;
   }
+  set_batch_occupancy(besto);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc) return rc;
