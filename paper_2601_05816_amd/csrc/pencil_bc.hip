@@ -233,6 +233,18 @@ __global__ __launch_bounds__(256) void k_wilson_eo_pb(const typename prec_traits
   };
   S lr[5], ln[5];
   fetch(t0, lr);
+  // FP64: the -t neighbour in(t-1) of step t was the +t neighbour of step
+  // t-2 in this compact column, so its -t projection is formed then and
+  // carried (qm: for step t, qn: for step t+1), one spinor load less per
+  // step (measured faster; in FP32 / FP16 the carried registers cost more
+  // than the load, which is reloaded there)
+  constexpr bool CARRY = PREC == LQCD_F64;
+  half_spinor<R> qm, qn;
+  if (CARRY) {
+    const int tm = t0 > 0 ? t0 - 1 : T - 1;
+    qm = project<0, SG>(load_spinor<S, R>(in, blk<LAYOUT>::base((size_t)tm * H0 + hc, rhs, Vh, nrhs), cs));
+    qn = project<0, SG>(load_spinor<S, R>(in, blk<LAYOUT>::base((size_t)t0 * H0 + hc, rhs, Vh, nrhs), cs));
+  }
   for (int it = 0; it < pg.Lt; ++it) {
     const int t = t0 + it;
     const int x = 2 * j + ((par0 + t) & 1);
@@ -245,9 +257,15 @@ __global__ __launch_bounds__(256) void k_wilson_eo_pb(const typename prec_traits
     {
       const int tm = t > 0 ? t - 1 : T - 1, t1 = t + 1 < T ? t + 1 : 0;
       spinor<R> pf = load_spinor<S, R>(in, blk<LAYOUT>::base((size_t)t1 * H0 + hc, rhs, Vh, nrhs), cs);
-      spinor<R> pb = load_spinor<S, R>(in, blk<LAYOUT>::base((size_t)tm * H0 + hc, rhs, Vh, nrhs), cs);
       reconstruct<0, -SG>(acc, colour_mul_r<false>(bc_link<0, S, R>(lr), project<0, -SG>(pf)));
-      reconstruct<0, SG>(acc, colour_mul_r<true>(bc_link<1, S, R>(lr), project<0, SG>(pb)));
+      if (CARRY) {
+        reconstruct<0, SG>(acc, colour_mul_r<true>(bc_link<1, S, R>(lr), qm));
+        qm = qn;
+        qn = project<0, SG>(pf);
+      } else {
+        spinor<R> pb = load_spinor<S, R>(in, blk<LAYOUT>::base((size_t)tm * H0 + hc, rhs, Vh, nrhs), cs);
+        reconstruct<0, SG>(acc, colour_mul_r<true>(bc_link<1, S, R>(lr), project<0, SG>(pb)));
+      }
     }
     {
       const int xf = x + 1 < NX ? x + 1 : 0, xb = x > 0 ? x - 1 : NX - 1;
