@@ -91,7 +91,11 @@ int lqcd_lattice_tables(const lqcd_lattice* lat, int32_t* nbr, int32_t* eo_site)
  * FP64, LQCD_LAYOUT2, nrhs >= 11; otherwise as 3), 6 = pencils whose
  * links reach the 16 rhs lanes of a column by row broadcasts, one load per
  * link element and row (LQCD_LAYOUT1 / LQCD_LAYOUT2, nrhs a multiple of 16,
- * any precision, full operator and odd-even hops; otherwise as 3).
+ * any precision, full operator and odd-even hops; otherwise as 3),
+ * 7 = variant 6 whose workgroups (256 / nrhs consecutive x columns) pass
+ * their streamed spinors through LDS so that the inner columns read their
+ * +-x neighbours there (full operator; odd-even hops run as 6; lattices
+ * whose x extent does not hold whole workgroups run as 6).
  * pencil (may be NULL) = {tile Y, tile Z,
  * number of t segments} for variants 2 and 3; 0 entries are chosen automatically, values
  * that do not divide the lattice fall back to automatic.  Every choice
@@ -101,7 +105,7 @@ int lqcd_set_kernel_variant(int variant, const int32_t* pencil);
 
 /* Full kernel configuration (for tuning and tests; process-wide).
  * variant: 0 automatic (the autotuner's entry for the arguments, else the
- * default), 1 to 6 as above; tile_y, tile_z, segments: pencil tile and t
+ * default), 1 to 7 as above; tile_y, tile_z, segments: pencil tile and t
  * segments (0 = automatic); nontemporal: 1 = output stores bypass L2
  * allocation; wg_per_cu (0..8): pencil variants run at most this many
  * workgroups per compute unit at a time (0 = no cap; the cap is imposed

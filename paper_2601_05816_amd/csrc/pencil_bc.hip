@@ -62,7 +62,15 @@ __device__ __forceinline__ void add_hop_r(spinor<R>& acc, const spinor<R>& p, co
 // ---------------------------------------------------------- full lattice
 // Link slots of a step: 0 U_0(x), 1..3 U_mu(x) (mu = 1 z, 2 y, 3 x),
 // 4..6 U_mu(x - mu); 63 elements, four per lane.
-template <int PREC, int LAYOUT, int SG>
+//
+// XL (variant 7): the workgroup's 256 / nrhs columns are consecutive x of
+// one row, so the +-x neighbours of all but the two end columns are the
+// spinors the neighbouring columns of the same workgroup stream along t.
+// Each column puts the spinor it loads for t+1 into LDS (one slot per
+// column, rhs fastest), and at step t the inner columns read their x
+// neighbours there; two barriers per step (before the reads, before the
+// slot is overwritten).
+template <int PREC, int LAYOUT, int SG, bool XL>
 __global__ __launch_bounds__(256) void k_wilson_full_pb(const typename prec_traits<PREC>::store* __restrict__ U,
                                                         const typename prec_traits<PREC>::store* __restrict__ psi,
                                                         typename prec_traits<PREC>::store* __restrict__ eta,
@@ -71,9 +79,25 @@ __global__ __launch_bounds__(256) void k_wilson_full_pb(const typename prec_trai
                                                         typename prec_traits<PREC>::real hopc) {
   typedef typename prec_traits<PREC>::store S;
   typedef typename prec_traits<PREC>::real R;
+  __shared__ S xs[XL ? 256 * 12 : 1];  // the workgroup's columns at one t, [column][12][rhs]
   int x, y, z, rhs, t0;
-  // nrhs % 16 == 0: a row of 16 lanes is idle or busy as a whole
+  // nrhs % 16 == 0: a row of 16 lanes is idle or busy as a whole (with XL the
+  // launch guarantees whole workgroups)
   if (!pencil_item<LAYOUT>(pg, nrhs, x, y, z, rhs, t0, blockIdx.x)) return;
+  const int lc = (int)threadIdx.x / nrhs, ncw = 256 / nrhs;  // column within the workgroup (XL)
+  auto put = [&](const spinor<R>& v) {
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+      const cx<R> c = v.c[i / 3][i % 3];
+      st(xs + ((size_t)lc * 12 + i) * nrhs + rhs, c);
+    }
+  };
+  auto get = [&](int col) {
+    spinor<R> v;
+#pragma unroll
+    for (int i = 0; i < 12; ++i) v.c[i / 3][i % 3] = ld(xs + ((size_t)col * 12 + i) * nrhs + rhs);
+    return v;
+  };
   const int T = pg.n[0], NZ = pg.n[1], NY = pg.n[2], NX = pg.n[3];
   const size_t V = pg.V, S0 = (size_t)NZ * NY * NX;
   const int cs = blk<LAYOUT>::cstride(nrhs);
@@ -117,6 +141,7 @@ __global__ __launch_bounds__(256) void k_wilson_full_pb(const typename prec_trai
       acc.c[i / 3][i % 3] = {fma(diag, b.re, a.re), fma(diag, b.im, a.im)};
     }
     hplus = project<0, SG>(p0);
+    if (XL) put(p0);
   }
   for (int it = 0; it < pg.Lt; ++it) {
     const int t = t0 + it;
@@ -126,12 +151,17 @@ __global__ __launch_bounds__(256) void k_wilson_full_pb(const typename prec_trai
 #pragma unroll
       for (int j = 0; j < 4; ++j) ln[j] = U[goff[j] + (size_t)(t + 1) * step9];
     }
+    if (XL) __syncthreads();  // every column's spinor at t is in LDS
     {
-      spinor<R> p = load_spinor<S, R>(psi, blk<LAYOUT>::base(toff + cxf, rhs, V, nrhs), cs);
+      spinor<R> p;
+      if (XL && lc + 1 < ncw) p = get(lc + 1);
+      else p = load_spinor<S, R>(psi, blk<LAYOUT>::base(toff + cxf, rhs, V, nrhs), cs);
       add_hop_r<3, -SG, false, R>(acc, p, bc_link<3, S, R>(lr), hopc);
     }
     {
-      spinor<R> p = load_spinor<S, R>(psi, blk<LAYOUT>::base(toff + cxb, rhs, V, nrhs), cs);
+      spinor<R> p;
+      if (XL && lc > 0) p = get(lc - 1);
+      else p = load_spinor<S, R>(psi, blk<LAYOUT>::base(toff + cxb, rhs, V, nrhs), cs);
       add_hop_r<3, SG, true, R>(acc, p, bc_link<6, S, R>(lr), hopc);
     }
     {
@@ -164,6 +194,10 @@ __global__ __launch_bounds__(256) void k_wilson_full_pb(const typename prec_trai
       hplus = project<0, SG>(p1);
 #pragma unroll
       for (int j = 0; j < 4; ++j) lr[j] = ln[j];
+      if (XL) {
+        __syncthreads();  // every column has read its neighbours at t
+        put(p1);
+      }
     }
   }
 }
@@ -310,6 +344,15 @@ __global__ __launch_bounds__(256) void k_wilson_eo_pb(const typename prec_traits
 }
 
 // ------------------------------------------------------------- launchers
+// x neighbours through LDS (variant 7): the workgroup's columns are whole
+// and consecutive in x (256 / nrhs of them within one tile row of x)
+static bool xl_fits(const pencil_geo& pg, int nrhs) {
+  if (256 % nrhs) return false;
+  const int ncw = 256 / nrhs;
+  const size_t items = (size_t)pg.TX * pg.TY * pg.TZ * nrhs;
+  return ncw >= 2 && pg.TX % ncw == 0 && items % 256 == 0;
+}
+
 template <int PREC, int LAYOUT, int SG>
 static hipError_t go_full(const lqcd_lattice* lat, const void* U, const void* psi, void* eta, int nrhs, double diag,
                           double hopc, const kcfg& c, hipStream_t s) {
@@ -317,9 +360,15 @@ static hipError_t go_full(const lqcd_lattice* lat, const void* U, const void* ps
   typedef typename prec_traits<PREC>::real R;
   pencil_geo pg = make_pencil(lat, nrhs, false, c);
   size_t dyn = 0;
+  if (c.variant == 7 && xl_fits(pg, nrhs)) {
+    if (!occupancy_lds(c.occ, 256 * 12 * sizeof(S), &dyn)) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((k_wilson_full_pb<PREC, LAYOUT, SG, true>), dim3(pencil_blocks(pg)), dim3(256), dyn, s,
+                       (const S*)U, (const S*)psi, (S*)eta, pg, nrhs, (R)diag, (R)hopc);
+    return hipSuccess;
+  }
   if (!occupancy_lds(c.occ, 0, &dyn)) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((k_wilson_full_pb<PREC, LAYOUT, SG>), dim3(pencil_blocks(pg)), dim3(256), dyn, s, (const S*)U,
-                     (const S*)psi, (S*)eta, pg, nrhs, (R)diag, (R)hopc);
+  hipLaunchKernelGGL((k_wilson_full_pb<PREC, LAYOUT, SG, false>), dim3(pencil_blocks(pg)), dim3(256), dyn, s,
+                     (const S*)U, (const S*)psi, (S*)eta, pg, nrhs, (R)diag, (R)hopc);
   return hipSuccess;
 }
 

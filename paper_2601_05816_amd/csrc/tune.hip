@@ -89,7 +89,10 @@ static std::vector<kcfg> candidates(const lqcd_lattice* lat, int layout, int pre
         if (layout != LQCD_RHS_OUTER && t[0] == 0 && sg == 0) out.push_back({3, 0, 0, 0, nt, 0});
         if (nr_supported(prec, layout, nrhs)) out.push_back({4, t[0], t[1], sg, nt, 0});
         if (!eo && dma_supported(prec, layout, nrhs)) out.push_back({5, t[0], t[1], sg, nt, 0});
-        if (bc_supported(layout, nrhs)) out.push_back({6, t[0], t[1], sg, nt, 0});
+        if (bc_supported(layout, nrhs)) {
+          out.push_back({6, t[0], t[1], sg, nt, 0});
+          if (!eo) out.push_back({7, t[0], t[1], sg, nt, 0});
+        }
       }
   return out;
 }
@@ -108,7 +111,10 @@ static std::vector<kcfg> capped_candidates(const lqcd_lattice* lat, int layout, 
         out.push_back({2, t[0], t[1], sg, w.nt, occ});
         if (layout != LQCD_RHS_OUTER) out.push_back({3, t[0], t[1], sg, w.nt, occ});
         if (nr_supported(prec, layout, nrhs)) out.push_back({4, t[0], t[1], sg, w.nt, occ});
-        if (bc_supported(layout, nrhs)) out.push_back({6, t[0], t[1], sg, w.nt, occ});
+        if (bc_supported(layout, nrhs)) {
+          out.push_back({6, t[0], t[1], sg, w.nt, occ});
+          out.push_back({7, t[0], t[1], sg, w.nt, occ});
+        }
       }
   return out;
 }
@@ -120,7 +126,7 @@ using namespace lq;
 extern "C" {
 
 int lqcd_set_kernel_variant(int variant, const int32_t* pencil) {
-  if (variant < 0 || variant > 6) return fail(LQCD_ERR_ARG, "unknown kernel variant %d", variant);
+  if (variant < 0 || variant > 7) return fail(LQCD_ERR_ARG, "unknown kernel variant %d", variant);
   int p[3] = {0, 0, 0};
   if (pencil)
     for (int i = 0; i < 3; ++i) {
@@ -136,7 +142,7 @@ int lqcd_set_kernel_config(const lqcd_kernel_config* c) {
     set_forced(kcfg{0, 0, 0, 0, 0, 0});
     return LQCD_OK;
   }
-  if (c->variant < 0 || c->variant > 6) return fail(LQCD_ERR_ARG, "unknown kernel variant %d", c->variant);
+  if (c->variant < 0 || c->variant > 7) return fail(LQCD_ERR_ARG, "unknown kernel variant %d", c->variant);
   if (c->tile_y < 0 || c->tile_z < 0 || c->segments < 0 || c->wg_per_cu < 0 || c->wg_per_cu > 8)
     return fail(LQCD_ERR_ARG, "kernel parameter out of range");
   set_forced(kcfg{c->variant, c->tile_y, c->tile_z, c->segments, c->nontemporal ? 1 : 0, c->wg_per_cu});
@@ -266,7 +272,7 @@ int lqcd_tune_load(const char* path) {
     if (!ints) continue;
     if (nv == 6) c[5] = 0;
     const double ms = val[nv - 1];
-    if (c[0] < 1 || c[0] > 6 || c[5] < 0 || c[5] > 8) continue;
+    if (c[0] < 1 || c[0] > 7 || c[5] < 0 || c[5] > 8) continue;
     g_table[tkey(k[0], k[1], k[2], k[3], k[4], k[5], k[6], k[7])] =
         std::make_pair(kcfg{c[0], c[1], c[2], c[3], c[4], c[5]}, ms);
     ++n;

@@ -118,7 +118,7 @@ def test_shipped_tune_table_loads_completely():
         assert lq.tune_load(path) == len(entries)
         for l in entries:
             cfg = l.split(":")[1].split()
-            assert 1 <= int(cfg[0]) <= 6 and 0 <= int(cfg[5]) <= 8 and float(cfg[6]) > 0
+            assert 1 <= int(cfg[0]) <= 7 and 0 <= int(cfg[5]) <= 8 and float(cfg[6]) > 0
     finally:
         lq.tune_clear()
 

@@ -189,3 +189,25 @@ def test_row_broadcast_link_kernels_in_solves(gpu_lib):
         res = dirac.apply_dw(U, xs, m0) - b
         rel = np.linalg.norm(res.reshape(16, -1), axis=1) / np.linalg.norm(b.reshape(16, -1), axis=1)
         assert np.all(rel <= 1e-10), (mode, rel)
+
+
+@pytest.mark.parametrize("prec", [lq.F64, lq.F32, lq.F16])
+@pytest.mark.parametrize("dims,nrhs", [((4, 4, 2, 16), 16), ((4, 2, 4, 8), 32), ((6, 4, 2, 4), 64)])
+@pytest.mark.parametrize("pencil", [(0, 0, 0, 1), (1, 2, 2, 0), (2, 1, 4, 1)])
+def test_x_neighbours_through_lds(gpu_lib, prec, dims, nrhs, pencil):
+    """Variant 7 (row-broadcast links and the +-x neighbours of the inner
+    columns of a workgroup read from LDS, 256 / nrhs consecutive columns per
+    workgroup, end columns from memory): full apply D and D^dagger in both
+    rhs-fastest layouts on lattices whose x extent holds whole workgroups;
+    the odd-even apply runs variant 6."""
+    gpu_lib.set_kernel_config(7, pencil[0], pencil[1], pencil[2], pencil[3])
+    U = rounded(syn.gauge_field(dims, "haar", config=16), prec)
+    psi = rounded(syn.spinor_block(dims, nrhs, config=16), prec)
+    for layout in (lq.LAYOUT1, lq.LAYOUT2):
+        for dagger in (False, True):
+            want = (dirac.apply_dw_dagger if dagger else dirac.apply_dw)(U, psi, 0.3)
+            got = _apply_gpu(U, psi, 0.3, layout, prec, dagger)
+            assert np.all(rel_err_per_rhs(got, want) <= TOL[prec])
+    psi_e = geometry.to_half(psi, dims, 0)
+    got = _apply_eo_gpu(U, psi_e, 0.3, lq.LAYOUT2, prec)
+    assert np.all(rel_err_per_rhs(got, evenodd.apply_schur(U, psi_e, 0.3)) <= TOL[prec] * 2)
