@@ -590,6 +590,10 @@ def profile_only(args):
     lq.load()
     if os.path.exists(args.tune_file):
         lq.tune_load(args.tune_file)
+    if args.variant or args.pencil:
+        pv = [int(v) for v in args.pencil.split(",")] if args.pencil else [0, 0, 0, 0]
+        pv += [0] * (5 - len(pv))
+        lq.set_kernel_config(args.variant or 2, *pv)
     dev = torch.device("cuda:0")
     g = torch.Generator(device=dev).manual_seed(CONFIG)
     v = int(np.prod(DIMS))
@@ -616,6 +620,8 @@ def profile_only(args):
             wk = torch.empty(lq.dirac_apply_eo_workspace_bytes(DIMS, n, prec), dtype=torch.uint8, device=dev)
             fn = lambda: lq.dirac_apply_eo_ws(Up, x, M0, wk, layout=lq.LAYOUT2, out=y)
             alg = bytes_schur_two_pass(v, n, {lq.F64: 16, lq.F32: 8, lq.F16: 4}[prec])
+            # one pass over links, input and output: what a fused apply must move
+            out["fused_minimum_bytes"] = (72 + 24 * n) * {lq.F64: 16, lq.F32: 8, lq.F16: 4}[prec] * (v // 2)
         ms = timed(fn, args.steps, args.warmup)
         out.update(prec=args.prec, kind=args.kind, nrhs=n, ms=round(ms, 4), algorithmic_bytes=alg,
                    gbs_algorithmic=round(alg / ms / 1e6, 1))
@@ -725,9 +731,11 @@ def main():
     ap.add_argument("--no-small", action="store_true", help="skip the 4^4 and 16^3 x 32 workloads")
     ap.add_argument("--no-autograd", action="store_true", help="skip the differentiation timing")
     ap.add_argument("--gmres-nrhs", type=int, default=NRHS)
-    ap.add_argument("--variant", type=int, default=0, help="Wilson kernel: 0 auto, 1 site, 2 pencil")
+    ap.add_argument("--variant", type=int, default=0,
+                    help="force a Wilson kernel variant (0 automatic; 1-8 as lqcd_set_kernel_config, 8 = the fused "
+                         "Schur apply)")
     ap.add_argument("--pencil", type=str, default="",
-                    help="tile Y,tile Z,t segments[,nontemporal[,workgroups per CU]] for the pencil kernels")
+                    help="tile Y,tile Z,t segments[,nontemporal[,workgroups per CU]] for the forced variant")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 2 GiB device copy (for scaling HBM byte counters)")
     ap.add_argument("--tune-file", default=TUNE_FILE,

@@ -95,7 +95,15 @@ int lqcd_lattice_tables(const lqcd_lattice* lat, int32_t* nbr, int32_t* eo_site)
  * 7 = variant 6 whose workgroups (256 / nrhs consecutive x columns) pass
  * their streamed spinors through LDS so that the inner columns read their
  * +-x neighbours there (full operator; odd-even hops run as 6; lattices
- * whose x extent does not hold whole workgroups run as 6).
+ * whose x extent does not hold whole workgroups run as 6),
+ * 8 = the Schur apply of dirac_apply_eo(_ws/_noalloc) and of the odd-even
+ * solvers in one kernel (Sec. III-A.2): a workgroup computes the odd field
+ * H_oe psi_e for its tile of (y, z) rows and the rows around it into LDS,
+ * one time slice at a time, and applies H_eo there, so the odd field never
+ * reaches memory (any layout and precision; tile_y, tile_z: interior tile,
+ * wg_per_cu 1 or 2: the LDS share a workgroup may use; a lattice whose x
+ * rows do not fit a workgroup runs the two hop passes; the full operator
+ * runs as 7, single odd-even hop passes as 6).
  * pencil (may be NULL) = {tile Y, tile Z,
  * number of t segments} for variants 2 and 3; 0 entries are chosen automatically, values
  * that do not divide the lattice fall back to automatic.  Every choice
@@ -105,7 +113,7 @@ int lqcd_set_kernel_variant(int variant, const int32_t* pencil);
 
 /* Full kernel configuration (for tuning and tests; process-wide).
  * variant: 0 automatic (the autotuner's entry for the arguments, else the
- * default), 1 to 7 as above; tile_y, tile_z, segments: pencil tile and t
+ * default), 1 to 8 as above; tile_y, tile_z, segments: pencil tile and t
  * segments (0 = automatic); nontemporal: 1 = output stores bypass L2
  * allocation; wg_per_cu (0..8): pencil variants run at most this many
  * workgroups per compute unit at a time (0 = no cap; the cap is imposed
@@ -119,11 +127,14 @@ int lqcd_set_kernel_config(const lqcd_kernel_config* cfg);
 
 /* Autotuner: times every candidate kernel configuration for this apply
  * (eo = 0: the full operator, eo = 1: one odd-even hop pass, the kernel a
- * Schur apply runs twice) on the caller's buffers (eta is overwritten; for
- * eo, psi and eta are half-lattice blocks), reps launches each, and records
- * the fastest for automatic selection by every later apply with the same
- * lattice, nrhs, precision and layout.  Synchronises `stream`.  best (may be
- * NULL) receives the winner and its time per launch. */
+ * two-pass Schur apply runs twice) on the caller's buffers (eta is
+ * overwritten; for eo, psi and eta are half-lattice blocks), reps launches
+ * each, and records the fastest for automatic selection by every later apply
+ * with the same lattice, nrhs, precision and layout.  With eo it then times
+ * the whole Schur apply, the two passes against the fused kernel (variant 8),
+ * and records that choice too (a temporary odd block is allocated for it).
+ * Synchronises `stream`.  best (may be NULL) receives the hop-pass winner and
+ * its time per launch. */
 int lqcd_autotune(const lqcd_lattice* lat, const void* U, const void* psi, void* eta, int nrhs, int prec,
                   int layout, int eo, int reps, lqcd_kernel_config* best, void* stream);
 /* Write / read the autotuner's table (text, one entry per line).  Load
@@ -144,15 +155,17 @@ int dirac_apply(const lqcd_lattice* lat, const void* U, const void* psi, void* e
 /* eta_e = S psi_e with S = D_ee - D_eo D_oo^{-1} D_oe, the even-site Schur
  * complement (Sec. III-A.2, odd-even preconditioning); with LQCD_DAGGER,
  * S^dagger.  psi_e, eta_e: even half-lattice blocks.  Needs 4 + m0 != 0
- * (else LQCD_ERR_SINGULAR).  Uses a temporary odd half-lattice block that the
- * library allocates with hipMallocAsync on `stream`. */
+ * (else LQCD_ERR_SINGULAR).  Two hop passes through a temporary odd
+ * half-lattice block that the library allocates with hipMallocAsync on
+ * `stream`, or the fused kernel (variant 8) where the tuner or the forced
+ * configuration selects it. */
 int dirac_apply_eo(const lqcd_lattice* lat, const void* U, const void* psi_e, void* eta_e,
                    int nrhs, double m0, int layout, int prec, int flags, void* stream);
 
 /* dirac_apply_eo with the odd temporary in a caller workspace (device, at
  * least dirac_apply_eo_workspace_bytes() = V/2 x 12 x nrhs complex numbers
- * of `prec`; LQCD_ERR_WORKSPACE if smaller): no allocation, the same two hop
- * passes.  The workspace size is 0 for invalid arguments. */
+ * of `prec`; LQCD_ERR_WORKSPACE if smaller): no allocation, the same
+ * kernels.  The workspace size is 0 for invalid arguments. */
 size_t dirac_apply_eo_workspace_bytes(const lqcd_lattice* lat, int nrhs, int prec);
 int dirac_apply_eo_ws(const lqcd_lattice* lat, const void* U, const void* psi_e, void* eta_e,
                       int nrhs, double m0, int layout, int prec, int flags, void* work,

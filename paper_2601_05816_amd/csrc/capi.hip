@@ -120,8 +120,7 @@ int dirac_apply_eo_ws(const lqcd_lattice* lat, const void* U, const void* psi_e,
     return fail(LQCD_ERR_WORKSPACE, "dirac_apply_eo_ws: workspace of %zu bytes given, %zu needed", work_bytes, need);
   hipStream_t s = (hipStream_t)stream;
   const bool dag = (flags & LQCD_DAGGER) != 0;
-  hipError_t e = wilson_eo(lat, U, psi_e, nullptr, work, 1, nrhs, 0.0, 1.0, layout, prec, dag, nullptr, s);
-  if (e == hipSuccess) e = wilson_eo(lat, U, work, psi_e, eta_e, 0, nrhs, d, -0.25 / d, layout, prec, dag, nullptr, s);
+  hipError_t e = schur_apply(lat, U, psi_e, eta_e, work, nrhs, d, layout, prec, dag, nullptr, s);
   return hip_status(e, "dirac_apply_eo_ws launch");
 }
 
@@ -142,9 +141,7 @@ int dirac_apply_eo(const lqcd_lattice* lat, const void* U, const void* psi_e, vo
   if (e != hipSuccess) return hip_status(e, "dirac_apply_eo: temporary odd block");
   const bool dag = (flags & LQCD_DAGGER) != 0;
   // S psi_e = (4+m0) psi_e - (1/4) H_eo H_oe psi_e / (4+m0), with D_eo = -H_eo / 2
-  e = wilson_eo(lat, U, psi_e, nullptr, tmp, 1, nrhs, 0.0, 1.0, layout, prec, dag, nullptr, s);
-  if (e == hipSuccess)
-    e = wilson_eo(lat, U, tmp, psi_e, eta_e, 0, nrhs, d, -0.25 / d, layout, prec, dag, nullptr, s);
+  e = schur_apply(lat, U, psi_e, eta_e, tmp, nrhs, d, layout, prec, dag, nullptr, s);
   hipError_t e2 = hipFreeAsync(tmp, s);
   if (e != hipSuccess) return hip_status(e, "dirac_apply_eo launch");
   return hip_status(e2, "dirac_apply_eo: free temporary");

@@ -554,9 +554,7 @@ struct Solver {
     }
     if (eo) {
       void* t = prec == LQCD_F64 ? tmp64 : tmplo;
-      hipError_t e = wilson_eo(&lat, U, in, nullptr, t, 1, nrhs, 0.0, 1.0, LQCD_LAYOUT2, prec, dag, lv, s);
-      if (e != hipSuccess) return e;
-      return wilson_eo(&lat, U, t, in, out, 0, nrhs, d, -0.25 / d, LQCD_LAYOUT2, prec, dag, lv, s);
+      return schur_apply(&lat, U, in, out, t, nrhs, d, LQCD_LAYOUT2, prec, dag, lv, s);
     }
     return wilson_full(&lat, U, in, out, nrhs, d, -0.5, LQCD_LAYOUT2, prec, dag, s);
   }

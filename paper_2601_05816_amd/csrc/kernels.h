@@ -25,13 +25,16 @@ hipError_t wilson_eo(const lqcd_lattice* lat, const void* U, const void* in, con
 // (FP64, rhs-innermost, nrhs >= 11, full operator; otherwise treated as 3), 6 pencils whose links
 // reach the rhs lanes of a column by row broadcasts (rhs-fastest layouts, nrhs % 16 == 0; otherwise
 // treated as 3), 7 as 6 with the +-x neighbours of a workgroup's inner columns read from LDS (full
-// operator; otherwise treated as 6); ty, tz, nseg: pencil tile and t segments
+// operator; otherwise treated as 6), 8 the Schur complement in one kernel (schur.hip; selects
+// that kernel for a whole Schur apply, is treated as 7 by the full operator and as 6 by a single
+// odd-even hop pass); ty, tz, nseg: pencil tile and t segments
 // (0 = automatic); nt: non-temporal output stores; occ: at most this many
 // workgroups per compute unit (0 = no cap), enforced through the LDS request.
 struct kcfg {
   int variant, ty, tz, nseg, nt, occ;
 };
-enum { KIND_FULL = 0, KIND_EO = 1 };
+// Tuning kinds: a full-operator apply, one odd-even hop pass, a whole Schur apply.
+enum { KIND_FULL = 0, KIND_EO = 1, KIND_SCHUR = 2 };
 
 // Time-streaming ("pencil") variants of the two kernels above (pencil.hip).
 hipError_t wilson_full_pencil(const lqcd_lattice* lat, const void* U, const void* psi, void* eta, int nrhs,
@@ -68,6 +71,16 @@ hipError_t wilson_full_bc(const lqcd_lattice* lat, const void* U, const void* ps
 hipError_t wilson_eo_bc(const lqcd_lattice* lat, const void* U, const void* in, const void* xin, void* out, int p,
                         int nrhs, double alpha, double beta, int layout, int prec, bool dagger, const int* live,
                         const kcfg& c, hipStream_t s);
+
+// The Schur complement eta_e = d in - (1/4d) H_eo H_oe in (schur.hip).
+// schur_apply runs the fused kernel when the configuration for KIND_SCHUR
+// selects it (variant 8) and the lattice fits, else the two hop passes
+// through tmp (an odd block of nrhs spinors; untouched by the fused kernel).
+bool schur_fused_supported(const lqcd_lattice* lat, int nrhs, int prec, const kcfg& c);
+hipError_t schur_fused(const lqcd_lattice* lat, const void* U, const void* in, void* out, int nrhs, double d,
+                       int layout, int prec, bool dagger, const int* live, const kcfg& c, hipStream_t s);
+hipError_t schur_apply(const lqcd_lattice* lat, const void* U, const void* in, void* out, void* tmp, int nrhs,
+                       double d, int layout, int prec, bool dagger, const int* live, hipStream_t s);
 
 // The clover-improved operator (clover.hip): one (site, rhs) per work item.
 // Full: eta = diag psi - C psi + hopc hop(psi).  Odd-even half (out on

@@ -69,10 +69,10 @@ int dirac_apply_eo_noalloc(const lqcd_lattice* lat, const void* U, const void* p
   if ((rc = scratch_address(&tmp))) return rc;
   hipStream_t s = (hipStream_t)stream;
   const bool dag = (flags & LQCD_DAGGER) != 0;
-  // the same two hop passes as dirac_apply_eo; the first writes every entry
-  // of the odd block before the second reads it, so nothing is cleared
-  hipError_t e = wilson_eo(lat, U, psi_e, nullptr, tmp, 1, nrhs, 0.0, 1.0, layout, prec, dag, nullptr, s);
-  if (e == hipSuccess) e = wilson_eo(lat, U, tmp, psi_e, eta_e, 0, nrhs, d, -0.25 / d, layout, prec, dag, nullptr, s);
+  // the same apply as dirac_apply_eo; with two hop passes the first writes
+  // every entry of the odd block before the second reads it, so nothing is
+  // cleared (the fused kernel does not use the array)
+  hipError_t e = schur_apply(lat, U, psi_e, eta_e, tmp, nrhs, d, layout, prec, dag, nullptr, s);
   return hip_status(e, "dirac_apply_eo_noalloc launch");
 }
 

@@ -7,12 +7,15 @@
 // site, time-streaming pencils with and without LDS-staged links, several
 // tile shapes and segment counts, with and without non-temporal output
 // stores) on the caller's buffers with HIP events and records the fastest.
+// For the odd-even operator it also times the whole Schur apply, two hop
+// passes against the fused kernel, and records that choice separately.
 // The table can be saved to and loaded from a text file.
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -71,6 +74,8 @@ bool tuned_time(int kind, const lqcd_lattice* lat, int nrhs, int prec, int layou
 }
 
 static const int kTiles[][2] = {{0, 0}, {2, 1}, {2, 2}, {4, 2}, {4, 4}, {8, 2}, {8, 4}};
+// interior tiles of the fused Schur kernel (tile_y, tile_z)
+static const int kSchurTiles[][2] = {{4, 4}, {4, 2}, {2, 4}, {2, 2}, {2, 1}, {1, 1}};
 
 static bool tile_ok(const lqcd_lattice* lat, const int* t, int sg) {
   return !((t[0] && lat->dims[2] % t[0]) || (t[1] && lat->dims[1] % t[1]) || (sg && lat->dims[0] % sg));
@@ -126,7 +131,7 @@ using namespace lq;
 extern "C" {
 
 int lqcd_set_kernel_variant(int variant, const int32_t* pencil) {
-  if (variant < 0 || variant > 7) return fail(LQCD_ERR_ARG, "unknown kernel variant %d", variant);
+  if (variant < 0 || variant > 8) return fail(LQCD_ERR_ARG, "unknown kernel variant %d", variant);
   int p[3] = {0, 0, 0};
   if (pencil)
     for (int i = 0; i < 3; ++i) {
@@ -142,7 +147,7 @@ int lqcd_set_kernel_config(const lqcd_kernel_config* c) {
     set_forced(kcfg{0, 0, 0, 0, 0, 0});
     return LQCD_OK;
   }
-  if (c->variant < 0 || c->variant > 7) return fail(LQCD_ERR_ARG, "unknown kernel variant %d", c->variant);
+  if (c->variant < 0 || c->variant > 8) return fail(LQCD_ERR_ARG, "unknown kernel variant %d", c->variant);
   if (c->tile_y < 0 || c->tile_z < 0 || c->segments < 0 || c->wg_per_cu < 0 || c->wg_per_cu > 8)
     return fail(LQCD_ERR_ARG, "kernel parameter out of range");
   set_forced(kcfg{c->variant, c->tile_y, c->tile_z, c->segments, c->nontemporal ? 1 : 0, c->wg_per_cu});
@@ -169,7 +174,7 @@ int lqcd_autotune(const lqcd_lattice* lat, const void* U, const void* psi, void*
   double best_ms = 1e300;
   kcfg best_c = kDefault;
   // one hop pass of the Schur operator (the kernel a Schur apply runs twice)
-  auto run = [&]() -> hipError_t {
+  std::function<hipError_t()> run = [&]() -> hipError_t {
     if (eo) return wilson_eo(lat, U, psi, nullptr, eta, 1, nrhs, 0.0, 1.0, layout, prec, false, nullptr, s);
     return wilson_full(lat, U, psi, eta, nrhs, 3.95, -0.5, layout, prec, false, s);
   };
@@ -198,10 +203,44 @@ int lqcd_autotune(const lqcd_lattice* lat, const void* U, const void* psi, void*
   };
   int err = time_all(candidates(lat, layout, prec, nrhs, eo != 0));
   if (!err) err = time_all(capped_candidates(lat, layout, prec, nrhs, best_c));
+  const kcfg hop_c = best_c;
+  const double hop_ms = best_ms;
+  // odd-even: the whole Schur apply, two hop passes with the configuration
+  // just chosen against the fused kernel's candidates
+  if (!err && eo) {
+    const size_t V = (size_t)lat->dims[0] * lat->dims[1] * lat->dims[2] * lat->dims[3];
+    const size_t esz = prec == LQCD_F64 ? 16 : prec == LQCD_F32 ? 8 : 4;
+    void* tmp = nullptr;
+    hipError_t e = hipMalloc(&tmp, V / 2 * 12 * (size_t)nrhs * esz);
+    if (e != hipSuccess) {
+      err = hip_status(e, "lqcd_autotune: odd temporary");
+    } else {
+      run = [&]() -> hipError_t {
+        return schur_apply(lat, U, psi, eta, tmp, nrhs, 4.0, layout, prec, false, nullptr, s);
+      };
+      best_ms = 1e300;
+      err = time_all({hop_c});
+      std::vector<kcfg> fused;
+      for (auto& t : kSchurTiles)
+        for (int occ = 1; occ <= 2; ++occ)
+          for (int nt = 0; nt <= 1; ++nt) {
+            const kcfg c{8, t[0], t[1], 0, nt, occ};
+            if (schur_fused_supported(lat, nrhs, prec, c)) fused.push_back(c);
+          }
+      if (!err) err = time_all(fused);
+      (void)hipFree(tmp);
+      if (!err) {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_table[key_of(KIND_SCHUR, lat, nrhs, prec, layout)] = std::make_pair(best_c, best_ms);
+      }
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   set_forced(saved);
   if (err) return err;
+  best_c = hop_c;
+  best_ms = hop_ms;
   {
     std::lock_guard<std::mutex> lk(g_mu);
     g_table[key_of(kind, lat, nrhs, prec, layout)] = std::make_pair(best_c, best_ms);
@@ -272,7 +311,7 @@ int lqcd_tune_load(const char* path) {
     if (!ints) continue;
     if (nv == 6) c[5] = 0;
     const double ms = val[nv - 1];
-    if (c[0] < 1 || c[0] > 7 || c[5] < 0 || c[5] > 8) continue;
+    if (c[0] < 1 || c[0] > 8 || c[5] < 0 || c[5] > 8) continue;
     g_table[tkey(k[0], k[1], k[2], k[3], k[4], k[5], k[6], k[7])] =
         std::make_pair(kcfg{c[0], c[1], c[2], c[3], c[4], c[5]}, ms);
     ++n;

@@ -71,7 +71,7 @@ def test_tune_table_roundtrip(tmp_path):
     lq.tune_clear()
     lq.set_kernel_config(0)
     with pytest.raises(lq.LqcdError):
-        lq.set_kernel_config(8)
+        lq.set_kernel_config(9)
     with pytest.raises(lq.LqcdError):
         lq.set_kernel_config(2, wg_per_cu=9)
     with pytest.raises(lq.LqcdError):

@@ -72,9 +72,15 @@ def test_nontemporal_stores_and_autotuned_choice(gpu_lib, kernel_variant, nt):
     Ud = to_dev(U, lq.F64)
     pd = to_dev(to_layout_np(psi, lq.LAYOUT2), lq.F64)
     best = gpu_lib.autotune(Ud, pd, torch.empty_like(pd), layout=lq.LAYOUT2, reps=1)
-    assert best["variant"] in (1, 2, 3, 5, 6) and best["ms"] > 0
+    assert best["variant"] in (1, 2, 3, 5, 6, 7) and best["ms"] > 0
     got = from_layout_np(from_dev(lq.dirac_apply(Ud, pd, -0.05, layout=lq.LAYOUT2), lq.F64), lq.LAYOUT2, 4)
     assert np.all(rel_err_per_rhs(got, want) <= TOL[lq.F64])
+    # odd-even: the hop pass and the whole Schur apply (two passes or fused)
+    pe = to_dev(to_layout_np(psi_e, lq.LAYOUT2), lq.F64)
+    best = gpu_lib.autotune(Ud, pe, torch.empty_like(pe), layout=lq.LAYOUT2, eo=True, reps=1)
+    assert best["variant"] in (1, 2, 3, 6) and best["ms"] > 0
+    got = from_layout_np(from_dev(lq.dirac_apply_eo(Ud, pe, -0.05, layout=lq.LAYOUT2), lq.F64), lq.LAYOUT2, 1)
+    assert np.all(rel_err_per_rhs(got, evenodd.apply_schur(U, psi_e, -0.05)) <= TOL[lq.F64])
     gpu_lib.tune_clear()
 
 
