@@ -680,10 +680,10 @@ def profile_only(args):
         import lqcd_synth as syn
 
         U = torch.from_numpy(syn.gauge_field(DIMS, "near_identity", config=CONFIG, eps=EPS)).to(dev)
-        b = torch.randn(DIMS + (4, 3, NRHS), dtype=torch.complex128, device=dev, generator=g)
+        b = torch.randn(DIMS + (4, 3, args.nrhs), dtype=torch.complex128, device=dev, generator=g)
         for mode in ("ir-f16", "ir-f32"):
             kw = dict(restart=30, eo=True, mode=mode, tol=1e-10, max_restarts=400, max_outer=60)
-            work = torch.empty(lq.gmres_workspace_bytes(DIMS, NRHS, lq.solver_params(**kw)), dtype=torch.uint8,
+            work = torch.empty(lq.gmres_workspace_bytes(DIMS, args.nrhs, lq.solver_params(**kw)), dtype=torch.uint8,
                                device=dev)
             out[mode] = []
             for i in range(args.warmup + args.steps):
@@ -749,7 +749,7 @@ def main():
                          "gmres-ir, tune file), print its times")
     ap.add_argument("--prec", choices=["f64", "f32", "f16"], default="f64", help="--only apply: storage precision")
     ap.add_argument("--kind", choices=["full", "schur"], default="full", help="--only apply: full D_W or Schur S")
-    ap.add_argument("--nrhs", type=int, default=NRHS, help="--only apply: rhs count")
+    ap.add_argument("--nrhs", type=int, default=NRHS, help="--only apply / gmres-ir: rhs count")
     ap.add_argument("--calibrate", action="store_true",
                     help="--only apply: also run the HBM probe's plain copy (for scaling byte counters)")
     ap.add_argument("--no-counters", action="store_true",
