@@ -14,7 +14,7 @@ multi-lattice batch, differentiation, small lattices) and the oracle's CPU
 throughput on a sample of the same apply (two of the 16 rhs).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-sweep] [--no-cpu] [--no-counters]
-    python bench.py --only {apply,sweep-f64,schur-f64,clover-f64,gmres-fixed,block-fixed,gmres-ir}
+    python bench.py --only {apply,sweep-f64,schur-f64,schur-sizes,clover-f64,gmres-fixed,block-fixed,gmres-ir}
                     [--prec f64|f32|f16] [--kind full|schur] [--nrhs N] [--calibrate]
                                     (one workload, for profilers)
 
@@ -650,6 +650,34 @@ def profile_only(args):
         wk = torch.empty(lq.dirac_apply_eo_workspace_bytes(DIMS, NRHS, lq.F64), dtype=torch.uint8, device=dev)
         ms = timed(lambda: lq.dirac_apply_eo_ws(U, xe, M0, wk, layout=lq.LAYOUT2, out=ye), args.steps, args.warmup)
         out.update(nrhs=NRHS, schur_ms=round(ms, 4))
+    elif args.only == "schur-sizes":
+        # the tuned Schur apply at 16 rhs on 2L x L^3 lattices whose working set
+        # (links, input, output, odd temporary) fits the 256 MB Infinity Cache
+        # or not: time per even site and rhs
+        pts = []
+        for L in (16, 20, 24, 32):
+            dims = (2 * L, L, L, L)
+            vol = 2 * L ** 4
+            for pn, prec, esz in (("f16", lq.F16, 4), ("f32", lq.F32, 8), ("f64", lq.F64, 16)):
+                def conv(x):
+                    if prec == lq.F64:
+                        return x
+                    return x.to(torch.complex64) if prec == lq.F32 else to_f16(x)
+
+                Ul = conv(torch.randn((4,) + dims + (3, 3), dtype=torch.complex128, device=dev, generator=g))
+                xe = conv(torch.randn((vol // 2, 4, 3, NRHS), dtype=torch.complex128, device=dev, generator=g))
+                ye = torch.empty_like(xe)
+                wk = torch.empty(lq.dirac_apply_eo_workspace_bytes(dims, NRHS, prec), dtype=torch.uint8, device=dev)
+                lq.autotune(Ul, xe, ye, layout=lq.LAYOUT2, eo=True, reps=3)
+                ms = timed(lambda: lq.dirac_apply_eo_ws(Ul, xe, M0, wk, layout=lq.LAYOUT2, out=ye), args.steps,
+                           args.warmup)
+                foot = (4 * vol * 9 + 3 * (vol // 2) * 12 * NRHS) * esz  # links, input, output, odd temporary
+                pts.append({"lattice": list(dims), "prec": pn, "ms": round(ms, 4), "working_set_mb": round(foot / 2**20),
+                            "ns_per_even_site_rhs": round(ms * 1e6 / (vol // 2 * NRHS), 4)})
+                log(f"schur-sizes: {json.dumps(pts[-1])}")
+                del Ul, xe, ye, wk
+                torch.cuda.empty_cache()
+        out["points"] = pts
     elif args.only == "clover-f64":  # D = D_W - C: full apply, then the Schur apply (two passes)
         C = 0.1 * torch.randn(DIMS + (42,), dtype=torch.complex128, device=dev, generator=g)
         Ci = 0.1 * torch.randn(DIMS + (42,), dtype=torch.complex128, device=dev, generator=g)
@@ -742,8 +770,8 @@ def main():
                     help="kernel configurations measured by the autotuner on MI355X (used when present)")
     ap.add_argument("--retune", action="store_true", help="ignore the tune file and autotune every apply")
     ap.add_argument("--save-tune", default="", help="write the autotuner's table here at the end")
-    ap.add_argument("--only", choices=["apply", "sweep-f64", "schur-f64", "clover-f64", "gmres-fixed", "block-fixed",
-                                       "gmres-ir"],
+    ap.add_argument("--only", choices=["apply", "sweep-f64", "schur-f64", "schur-sizes", "clover-f64", "gmres-fixed",
+                                       "block-fixed", "gmres-ir"],
                     default="",
                     help="profiling mode: run one workload only (GPU-drawn inputs except the near-identity links of "
                          "gmres-ir, tune file), print its times")

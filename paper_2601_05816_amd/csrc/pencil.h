@@ -1,6 +1,8 @@
 // Shared pieces of the time-streaming ("pencil") Wilson kernels.
 #pragma once
 
+#include <type_traits>
+
 #include "kernels.h"
 #include "wilson.h"
 
@@ -15,6 +17,7 @@ struct pencil_geo {
   int bpt;           // workgroups per tile and segment
   int ntiles;
   int nt;            // non-temporal output stores
+  float one;         // 1, as a run-time value (the FMA form of load_project)
 };
 
 // (column coordinates, rhs, t0) of work item threadIdx.x of block b of the
@@ -60,6 +63,44 @@ template <int MU, int T, bool ADJ, typename S, typename R>
 __device__ __forceinline__ void add_hop(spinor<R>& acc, const spinor<R>& p, const S* __restrict__ u, R c) {
   half_spinor<R> h = project<MU, T>(p);
   reconstruct<MU, T>(acc, hscale(c, colour_mul<ADJ>(u, h)));
+}
+
+// The same for the neighbour stored at p[base + i cs] (i = 0..11).  FP16
+// storage projects the loaded values directly (load_project, no separate
+// conversions); FP32 / FP64 widen the spinor first, the form their kernels
+// were tuned with.
+template <int MU, int T, bool ADJ, typename S, typename R>
+__device__ __forceinline__ void add_hop_at(spinor<R>& acc, const S* p, size_t base, int cs, const S* u, R c, R one) {
+  if constexpr (std::is_same<S, h2_t>::value) {
+    reconstruct<MU, T>(acc, hscale(c, colour_mul<ADJ>(u, load_project<MU, T>(p, base, cs, one))));
+  } else {
+    spinor<R> v = load_spinor<S, R>(p, base, cs);
+    add_hop<MU, T, ADJ, S, R>(acc, v, u, c);
+  }
+}
+
+// acc += both hop terms of direction MU (sign SG): the forward neighbour at
+// in[fb + i cs] with U_MU(x) at uf and the backward one at in[bb + i cs]
+// with U_MU(x - MU)^dagger at ub; both neighbours and links are loaded
+// before either term is accumulated.  FP16 storage projects as add_hop_at.
+template <int MU, int SG, typename S, typename R>
+__device__ __forceinline__ void add_hop_pair(spinor<R>& acc, const S* in, size_t fb, size_t bb, int cs, const S* uf,
+                                             const S* ub, R one) {
+  if constexpr (std::is_same<S, h2_t>::value) {
+    half_spinor<R> hf = load_project<MU, -SG>(in, fb, cs, one);
+    su3<R> mf = load_link<S, R>(uf);
+    half_spinor<R> hb = load_project<MU, SG>(in, bb, cs, one);
+    su3<R> mb = load_link<S, R>(ub);
+    reconstruct<MU, -SG>(acc, colour_mul_r<false>(mf, hf));
+    reconstruct<MU, SG>(acc, colour_mul_r<true>(mb, hb));
+  } else {
+    spinor<R> pf = load_spinor<S, R>(in, fb, cs);
+    su3<R> mf = load_link<S, R>(uf);
+    spinor<R> pb = load_spinor<S, R>(in, bb, cs);
+    su3<R> mb = load_link<S, R>(ub);
+    reconstruct<MU, -SG>(acc, colour_mul_r<false>(mf, project<MU, -SG>(pf)));
+    reconstruct<MU, SG>(acc, colour_mul_r<true>(mb, project<MU, SG>(pb)));
+  }
 }
 
 inline int largest_divisor_at_most(int n, int cap) {
@@ -116,6 +157,7 @@ inline pencil_geo make_pencil(const lqcd_lattice* lat, int nrhs, bool eo, const 
   const size_t items = (size_t)pg.TX * TY * TZ * nrhs;
   pg.bpt = (int)((items + 255) / 256);
   pg.nt = c.nt;
+  pg.one = 1.0f;
   return pg;
 }
 

@@ -12,6 +12,7 @@
 // pencil.hip (Algorithm 1's projected hops, the time-direction reuse of the
 // streamed spinor), so results agree with the other pencil kernels bit for
 // bit.  The loads of step t+1's elements are issued at the top of step t.
+#include <type_traits>
 #include <utility>
 
 #include "pencil_kernels.h"
@@ -59,6 +60,41 @@ __device__ __forceinline__ void add_hop_r(spinor<R>& acc, const spinor<R>& p, co
   reconstruct<MU, T>(acc, hscale(c, colour_mul_r<ADJ>(m, project<MU, T>(p))));
 }
 
+// the same for the neighbour stored at p[base + i cs] (i = 0..11) with the
+// link of slot SLOT; FP16 storage projects the loaded values directly
+// (load_project, no separate conversions), FP32 / FP64 widen the spinor
+// first, the form their kernels were tuned with
+template <int MU, int T, bool ADJ, int SLOT, typename S, typename R>
+__device__ __forceinline__ void add_hop_bc(spinor<R>& acc, const S* __restrict__ p, size_t base, int cs,
+                                           const S* lr, R c, R one) {
+  if constexpr (std::is_same<S, h2_t>::value) {
+    const half_spinor<R> h = load_project<MU, T>(p, base, cs, one);
+    reconstruct<MU, T>(acc, hscale(c, colour_mul_r<ADJ>(bc_link<SLOT, S, R>(lr), h)));
+  } else {
+    const spinor<R> v = load_spinor<S, R>(p, base, cs);
+    add_hop_r<MU, T, ADJ, R>(acc, v, bc_link<SLOT, S, R>(lr), c);
+  }
+}
+
+// acc += both hop terms of direction MU (sign SG): forward neighbour at
+// in[fb + i cs] with the link of slot SF, backward one at in[bb + i cs] with
+// the adjoint of the link of slot SB; both loaded before either is used
+template <int MU, int SG, int SF, int SB, typename S, typename R>
+__device__ __forceinline__ void add_hop_pair_bc(spinor<R>& acc, const S* __restrict__ in, size_t fb, size_t bb,
+                                                int cs, const S* lr, R one) {
+  if constexpr (std::is_same<S, h2_t>::value) {
+    const half_spinor<R> hf = load_project<MU, -SG>(in, fb, cs, one);
+    const half_spinor<R> hb = load_project<MU, SG>(in, bb, cs, one);
+    reconstruct<MU, -SG>(acc, colour_mul_r<false>(bc_link<SF, S, R>(lr), hf));
+    reconstruct<MU, SG>(acc, colour_mul_r<true>(bc_link<SB, S, R>(lr), hb));
+  } else {
+    const spinor<R> pf = load_spinor<S, R>(in, fb, cs);
+    const spinor<R> pb = load_spinor<S, R>(in, bb, cs);
+    reconstruct<MU, -SG>(acc, colour_mul_r<false>(bc_link<SF, S, R>(lr), project<MU, -SG>(pf)));
+    reconstruct<MU, SG>(acc, colour_mul_r<true>(bc_link<SB, S, R>(lr), project<MU, SG>(pb)));
+  }
+}
+
 // ---------------------------------------------------------- full lattice
 // Link slots of a step: 0 U_0(x), 1..3 U_mu(x) (mu = 1 z, 2 y, 3 x),
 // 4..6 U_mu(x - mu); 63 elements, four per lane.
@@ -79,6 +115,7 @@ __global__ __launch_bounds__(256) void k_wilson_full_pb(const typename prec_trai
                                                         typename prec_traits<PREC>::real hopc) {
   typedef typename prec_traits<PREC>::store S;
   typedef typename prec_traits<PREC>::real R;
+  const R one = (R)pg.one;
   __shared__ S xs[XL ? 256 * 12 : 1];  // the workgroup's columns at one t, [column][12][rhs]
   int x, y, z, rhs, t0;
   // nrhs % 16 == 0: a row of 16 lanes is idle or busy as a whole (with XL the
@@ -152,34 +189,33 @@ __global__ __launch_bounds__(256) void k_wilson_full_pb(const typename prec_trai
       for (int j = 0; j < 4; ++j) ln[j] = U[goff[j] + (size_t)(t + 1) * step9];
     }
     if (XL) __syncthreads();  // every column's spinor at t is in LDS
-    {
-      spinor<R> p;
-      if (XL && lc + 1 < ncw) p = get(lc + 1);
-      else p = load_spinor<S, R>(psi, blk<LAYOUT>::base(toff + cxf, rhs, V, nrhs), cs);
-      add_hop_r<3, -SG, false, R>(acc, p, bc_link<3, S, R>(lr), hopc);
+    if constexpr (std::is_same<S, h2_t>::value) {  // FP16: project the loaded values directly
+      const size_t lb = ((size_t)lc * 12) * nrhs + rhs;  // this column's slot in LDS
+      half_spinor<R> h;
+      if (XL && lc + 1 < ncw) h = load_project<3, -SG>(xs, lb + 12 * (size_t)nrhs, nrhs, one);
+      else h = load_project<3, -SG>(psi, blk<LAYOUT>::base(toff + cxf, rhs, V, nrhs), cs, one);
+      reconstruct<3, -SG>(acc, hscale(hopc, colour_mul_r<false>(bc_link<3, S, R>(lr), h)));
+      if (XL && lc > 0) h = load_project<3, SG>(xs, lb - 12 * (size_t)nrhs, nrhs, one);
+      else h = load_project<3, SG>(psi, blk<LAYOUT>::base(toff + cxb, rhs, V, nrhs), cs, one);
+      reconstruct<3, SG>(acc, hscale(hopc, colour_mul_r<true>(bc_link<6, S, R>(lr), h)));
+    } else {
+      {
+        spinor<R> p;
+        if (XL && lc + 1 < ncw) p = get(lc + 1);
+        else p = load_spinor<S, R>(psi, blk<LAYOUT>::base(toff + cxf, rhs, V, nrhs), cs);
+        add_hop_r<3, -SG, false, R>(acc, p, bc_link<3, S, R>(lr), hopc);
+      }
+      {
+        spinor<R> p;
+        if (XL && lc > 0) p = get(lc - 1);
+        else p = load_spinor<S, R>(psi, blk<LAYOUT>::base(toff + cxb, rhs, V, nrhs), cs);
+        add_hop_r<3, SG, true, R>(acc, p, bc_link<6, S, R>(lr), hopc);
+      }
     }
-    {
-      spinor<R> p;
-      if (XL && lc > 0) p = get(lc - 1);
-      else p = load_spinor<S, R>(psi, blk<LAYOUT>::base(toff + cxb, rhs, V, nrhs), cs);
-      add_hop_r<3, SG, true, R>(acc, p, bc_link<6, S, R>(lr), hopc);
-    }
-    {
-      spinor<R> p = load_spinor<S, R>(psi, blk<LAYOUT>::base(toff + cyf, rhs, V, nrhs), cs);
-      add_hop_r<2, -SG, false, R>(acc, p, bc_link<2, S, R>(lr), hopc);
-    }
-    {
-      spinor<R> p = load_spinor<S, R>(psi, blk<LAYOUT>::base(toff + cyb, rhs, V, nrhs), cs);
-      add_hop_r<2, SG, true, R>(acc, p, bc_link<5, S, R>(lr), hopc);
-    }
-    {
-      spinor<R> p = load_spinor<S, R>(psi, blk<LAYOUT>::base(toff + czf, rhs, V, nrhs), cs);
-      add_hop_r<1, -SG, false, R>(acc, p, bc_link<1, S, R>(lr), hopc);
-    }
-    {
-      spinor<R> p = load_spinor<S, R>(psi, blk<LAYOUT>::base(toff + czb, rhs, V, nrhs), cs);
-      add_hop_r<1, SG, true, R>(acc, p, bc_link<4, S, R>(lr), hopc);
-    }
+    add_hop_bc<2, -SG, false, 2>(acc, psi, blk<LAYOUT>::base(toff + cyf, rhs, V, nrhs), cs, lr, hopc, one);
+    add_hop_bc<2, SG, true, 5>(acc, psi, blk<LAYOUT>::base(toff + cyb, rhs, V, nrhs), cs, lr, hopc, one);
+    add_hop_bc<1, -SG, false, 1>(acc, psi, blk<LAYOUT>::base(toff + czf, rhs, V, nrhs), cs, lr, hopc, one);
+    add_hop_bc<1, SG, true, 4>(acc, psi, blk<LAYOUT>::base(toff + czb, rhs, V, nrhs), cs, lr, hopc, one);
     const int t1 = t + 1 < T ? t + 1 : 0;
     const size_t s1 = (size_t)t1 * S0 + c0;
     spinor<R> p1 = load_spinor<S, R>(psi, blk<LAYOUT>::base(s1, rhs, V, nrhs), cs);
@@ -224,6 +260,7 @@ __global__ __launch_bounds__(256) void k_wilson_eo_pb(const typename prec_traits
   if (!pencil_item<LAYOUT>(pg, nrhs, j, y, z, rhs, t0, blockIdx.x)) return;
   const bool store_me = !live || live[rhs];
   const int T = pg.n[0], NZ = pg.n[1], NY = pg.n[2], NX = pg.n[3];
+  const R one = (R)pg.one;
   const int NXh = NX >> 1;
   const size_t V = pg.V, Vh = V / 2;
   const size_t S0 = (size_t)NZ * NY * NX, H0 = S0 / 2;
@@ -303,22 +340,16 @@ __global__ __launch_bounds__(256) void k_wilson_eo_pb(const typename prec_traits
     }
     {
       const int xf = x + 1 < NX ? x + 1 : 0, xb = x > 0 ? x - 1 : NX - 1;
-      spinor<R> pf = load_spinor<S, R>(in, blk<LAYOUT>::base(toffh + row * NXh + (xf >> 1), rhs, Vh, nrhs), cs);
-      spinor<R> pb = load_spinor<S, R>(in, blk<LAYOUT>::base(toffh + row * NXh + (xb >> 1), rhs, Vh, nrhs), cs);
-      reconstruct<3, -SG>(acc, colour_mul_r<false>(bc_link<2, S, R>(lr), project<3, -SG>(pf)));
-      reconstruct<3, SG>(acc, colour_mul_r<true>(bc_link<3, S, R>(lr), project<3, SG>(pb)));
+      add_hop_pair_bc<3, SG, 2, 3>(acc, in, blk<LAYOUT>::base(toffh + row * NXh + (xf >> 1), rhs, Vh, nrhs),
+                                        blk<LAYOUT>::base(toffh + row * NXh + (xb >> 1), rhs, Vh, nrhs), cs, lr, one);
     }
     {
-      spinor<R> pf = load_spinor<S, R>(in, blk<LAYOUT>::base(toffh + hyf, rhs, Vh, nrhs), cs);
-      spinor<R> pb = load_spinor<S, R>(in, blk<LAYOUT>::base(toffh + hyb, rhs, Vh, nrhs), cs);
-      reconstruct<2, -SG>(acc, colour_mul_r<false>(bc_link<4, S, R>(lr), project<2, -SG>(pf)));
-      reconstruct<2, SG>(acc, colour_mul_r<true>(bc_link<5, S, R>(lr), project<2, SG>(pb)));
+      add_hop_pair_bc<2, SG, 4, 5>(acc, in, blk<LAYOUT>::base(toffh + hyf, rhs, Vh, nrhs),
+                                        blk<LAYOUT>::base(toffh + hyb, rhs, Vh, nrhs), cs, lr, one);
     }
     {
-      spinor<R> pf = load_spinor<S, R>(in, blk<LAYOUT>::base(toffh + hzf, rhs, Vh, nrhs), cs);
-      spinor<R> pb = load_spinor<S, R>(in, blk<LAYOUT>::base(toffh + hzb, rhs, Vh, nrhs), cs);
-      reconstruct<1, -SG>(acc, colour_mul_r<false>(bc_link<6, S, R>(lr), project<1, -SG>(pf)));
-      reconstruct<1, SG>(acc, colour_mul_r<true>(bc_link<7, S, R>(lr), project<1, SG>(pb)));
+      add_hop_pair_bc<1, SG, 6, 7>(acc, in, blk<LAYOUT>::base(toffh + hzf, rhs, Vh, nrhs),
+                                        blk<LAYOUT>::base(toffh + hzb, rhs, Vh, nrhs), cs, lr, one);
     }
     const size_t me = blk<LAYOUT>::base(hh, rhs, Vh, nrhs);
     if (xin) {

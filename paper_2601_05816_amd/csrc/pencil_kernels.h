@@ -28,6 +28,7 @@ __device__ __forceinline__ void wilson_full_p_body(const typename prec_traits<PR
   const int T = pg.n[0], NZ = pg.n[1], NY = pg.n[2], NX = pg.n[3];
   const size_t V = pg.V, S0 = (size_t)NZ * NY * NX;
   const int cs = blk<LAYOUT>::cstride(nrhs);
+  const R one = (R)pg.one;
   // column bases (site number at t = 0) of this column and its spatial neighbours
   const size_t c0 = ((size_t)z * NY + y) * NX + x;
   const size_t cxf = c0 - x + (x + 1 < NX ? x + 1 : 0), cxb = c0 - x + (x > 0 ? x - 1 : NX - 1);
@@ -68,30 +69,46 @@ __device__ __forceinline__ void wilson_full_p_body(const typename prec_traits<PR
     const int t = t0 + it;
     const size_t toff = (size_t)t * S0;
     const size_t site = toff + c0;
-    // spatial hops (directions 3 = x, 2 = y, 1 = z)
-    {
-      spinor<R> p = load_spinor<S, R>(psi, blk<LAYOUT>::base(toff + cxf, rhs, V, nrhs), cs);
-      add_hop<3, -SG, false, S, R>(acc, p, U3 + site * 9, hopc);
-    }
-    {
-      spinor<R> p = load_spinor<S, R>(psi, blk<LAYOUT>::base(toff + cxb, rhs, V, nrhs), cs);
-      add_hop<3, SG, true, S, R>(acc, p, U3 + (toff + cxb) * 9, hopc);
-    }
-    {
-      spinor<R> p = load_spinor<S, R>(psi, blk<LAYOUT>::base(toff + cyf, rhs, V, nrhs), cs);
-      add_hop<2, -SG, false, S, R>(acc, p, U2 + site * 9, hopc);
-    }
-    {
-      spinor<R> p = load_spinor<S, R>(psi, blk<LAYOUT>::base(toff + cyb, rhs, V, nrhs), cs);
-      add_hop<2, SG, true, S, R>(acc, p, U2 + (toff + cyb) * 9, hopc);
-    }
-    {
-      spinor<R> p = load_spinor<S, R>(psi, blk<LAYOUT>::base(toff + czf, rhs, V, nrhs), cs);
-      add_hop<1, -SG, false, S, R>(acc, p, U1 + site * 9, hopc);
-    }
-    {
-      spinor<R> p = load_spinor<S, R>(psi, blk<LAYOUT>::base(toff + czb, rhs, V, nrhs), cs);
-      add_hop<1, SG, true, S, R>(acc, p, U1 + (toff + czb) * 9, hopc);
+    // spatial hops (directions 3 = x, 2 = y, 1 = z); FP16 storage projects
+    // the loaded values directly (add_hop_at)
+    if constexpr (std::is_same<S, h2_t>::value) {
+      add_hop_at<3, -SG, false, S, R>(acc, psi, blk<LAYOUT>::base(toff + cxf, rhs, V, nrhs), cs,
+          U3 + site * 9, hopc, one);
+      add_hop_at<3, SG, true, S, R>(acc, psi, blk<LAYOUT>::base(toff + cxb, rhs, V, nrhs), cs,
+          U3 + (toff + cxb) * 9, hopc, one);
+      add_hop_at<2, -SG, false, S, R>(acc, psi, blk<LAYOUT>::base(toff + cyf, rhs, V, nrhs), cs,
+          U2 + site * 9, hopc, one);
+      add_hop_at<2, SG, true, S, R>(acc, psi, blk<LAYOUT>::base(toff + cyb, rhs, V, nrhs), cs,
+          U2 + (toff + cyb) * 9, hopc, one);
+      add_hop_at<1, -SG, false, S, R>(acc, psi, blk<LAYOUT>::base(toff + czf, rhs, V, nrhs), cs,
+          U1 + site * 9, hopc, one);
+      add_hop_at<1, SG, true, S, R>(acc, psi, blk<LAYOUT>::base(toff + czb, rhs, V, nrhs), cs,
+          U1 + (toff + czb) * 9, hopc, one);
+    } else {
+      {
+        spinor<R> p = load_spinor<S, R>(psi, blk<LAYOUT>::base(toff + cxf, rhs, V, nrhs), cs);
+        add_hop<3, -SG, false, S, R>(acc, p, U3 + site * 9, hopc);
+      }
+      {
+        spinor<R> p = load_spinor<S, R>(psi, blk<LAYOUT>::base(toff + cxb, rhs, V, nrhs), cs);
+        add_hop<3, SG, true, S, R>(acc, p, U3 + (toff + cxb) * 9, hopc);
+      }
+      {
+        spinor<R> p = load_spinor<S, R>(psi, blk<LAYOUT>::base(toff + cyf, rhs, V, nrhs), cs);
+        add_hop<2, -SG, false, S, R>(acc, p, U2 + site * 9, hopc);
+      }
+      {
+        spinor<R> p = load_spinor<S, R>(psi, blk<LAYOUT>::base(toff + cyb, rhs, V, nrhs), cs);
+        add_hop<2, SG, true, S, R>(acc, p, U2 + (toff + cyb) * 9, hopc);
+      }
+      {
+        spinor<R> p = load_spinor<S, R>(psi, blk<LAYOUT>::base(toff + czf, rhs, V, nrhs), cs);
+        add_hop<1, -SG, false, S, R>(acc, p, U1 + site * 9, hopc);
+      }
+      {
+        spinor<R> p = load_spinor<S, R>(psi, blk<LAYOUT>::base(toff + czb, rhs, V, nrhs), cs);
+        add_hop<1, SG, true, S, R>(acc, p, U1 + (toff + czb) * 9, hopc);
+      }
     }
     // time direction: psi(t+1) gives the +t hop of t, and the centre and the
     // -t hop (through U_0(t)^dagger and the carried projection of psi(t)) of t+1
@@ -153,6 +170,7 @@ __device__ __forceinline__ void wilson_eo_p_body(const typename prec_traits<PREC
   const S* U2 = U + 2 * V * 9;
   const S* U3 = U + 3 * V * 9;
   const int par0 = (p + z + y) & 1;  // x parity offset at t = 0
+  const R one = (R)pg.one;
 
   // One direction per phase: both neighbours and both links are loaded
   // before either term is accumulated, so a wavefront has two hops' loads
@@ -171,38 +189,22 @@ __device__ __forceinline__ void wilson_eo_p_body(const typename prec_traits<PREC
     for (int i = 0; i < 12; ++i) acc.c[i / 3][i % 3] = {R(0), R(0)};
     {
       const int tm = t > 0 ? t - 1 : T - 1, t1 = t + 1 < T ? t + 1 : 0;
-      spinor<R> pf = load_spinor<S, R>(in, blk<LAYOUT>::base((size_t)t1 * H0 + hc, rhs, Vh, nrhs), cs);
-      su3<R> uf = load_link<S, R>(U0 + site * 9);
-      spinor<R> pb = load_spinor<S, R>(in, blk<LAYOUT>::base((size_t)tm * H0 + hc, rhs, Vh, nrhs), cs);
-      su3<R> ub = load_link<S, R>(U0 + ((size_t)tm * S0 + lrow + x) * 9);
-      reconstruct<0, -SG>(acc, colour_mul_r<false>(uf, project<0, -SG>(pf)));
-      reconstruct<0, SG>(acc, colour_mul_r<true>(ub, project<0, SG>(pb)));
+      add_hop_pair<0, SG, S, R>(acc, in, blk<LAYOUT>::base((size_t)t1 * H0 + hc, rhs, Vh, nrhs),
+                                blk<LAYOUT>::base((size_t)tm * H0 + hc, rhs, Vh, nrhs), cs, U0 + site * 9,
+                                U0 + ((size_t)tm * S0 + lrow + x) * 9, one);
     }
     {
       const int xf = x + 1 < NX ? x + 1 : 0, xb = x > 0 ? x - 1 : NX - 1;
-      spinor<R> pf = load_spinor<S, R>(in, blk<LAYOUT>::base(toffh + row * NXh + (xf >> 1), rhs, Vh, nrhs), cs);
-      su3<R> uf = load_link<S, R>(U3 + site * 9);
-      spinor<R> pb = load_spinor<S, R>(in, blk<LAYOUT>::base(toffh + row * NXh + (xb >> 1), rhs, Vh, nrhs), cs);
-      su3<R> ub = load_link<S, R>(U3 + ((size_t)t * S0 + lrow + xb) * 9);
-      reconstruct<3, -SG>(acc, colour_mul_r<false>(uf, project<3, -SG>(pf)));
-      reconstruct<3, SG>(acc, colour_mul_r<true>(ub, project<3, SG>(pb)));
+      add_hop_pair<3, SG, S, R>(acc, in, blk<LAYOUT>::base(toffh + row * NXh + (xf >> 1), rhs, Vh, nrhs),
+                                blk<LAYOUT>::base(toffh + row * NXh + (xb >> 1), rhs, Vh, nrhs), cs, U3 + site * 9,
+                                U3 + ((size_t)t * S0 + lrow + xb) * 9, one);
     }
-    {
-      spinor<R> pf = load_spinor<S, R>(in, blk<LAYOUT>::base(toffh + hyf, rhs, Vh, nrhs), cs);
-      su3<R> uf = load_link<S, R>(U2 + site * 9);
-      spinor<R> pb = load_spinor<S, R>(in, blk<LAYOUT>::base(toffh + hyb, rhs, Vh, nrhs), cs);
-      su3<R> ub = load_link<S, R>(U2 + ((size_t)t * S0 + lyb + x) * 9);
-      reconstruct<2, -SG>(acc, colour_mul_r<false>(uf, project<2, -SG>(pf)));
-      reconstruct<2, SG>(acc, colour_mul_r<true>(ub, project<2, SG>(pb)));
-    }
-    {
-      spinor<R> pf = load_spinor<S, R>(in, blk<LAYOUT>::base(toffh + hzf, rhs, Vh, nrhs), cs);
-      su3<R> uf = load_link<S, R>(U1 + site * 9);
-      spinor<R> pb = load_spinor<S, R>(in, blk<LAYOUT>::base(toffh + hzb, rhs, Vh, nrhs), cs);
-      su3<R> ub = load_link<S, R>(U1 + ((size_t)t * S0 + lzb + x) * 9);
-      reconstruct<1, -SG>(acc, colour_mul_r<false>(uf, project<1, -SG>(pf)));
-      reconstruct<1, SG>(acc, colour_mul_r<true>(ub, project<1, SG>(pb)));
-    }
+    add_hop_pair<2, SG, S, R>(acc, in, blk<LAYOUT>::base(toffh + hyf, rhs, Vh, nrhs),
+                              blk<LAYOUT>::base(toffh + hyb, rhs, Vh, nrhs), cs, U2 + site * 9,
+                              U2 + ((size_t)t * S0 + lyb + x) * 9, one);
+    add_hop_pair<1, SG, S, R>(acc, in, blk<LAYOUT>::base(toffh + hzf, rhs, Vh, nrhs),
+                              blk<LAYOUT>::base(toffh + hzb, rhs, Vh, nrhs), cs, U1 + site * 9,
+                              U1 + ((size_t)t * S0 + lzb + x) * 9, one);
     const size_t me = blk<LAYOUT>::base(hh, rhs, Vh, nrhs);
     if (xin) {
       spinor<R> xv = load_spinor<S, R>(xin, me, cs);

@@ -161,12 +161,10 @@ struct schur_max_items {
 };
 
 template <int PREC, int LAYOUT, int SG>
-__global__ __launch_bounds__(schur_max_items<PREC>::value) void k_schur_fused(const typename prec_traits<PREC>::store* __restrict__ U,
-                                                     const typename prec_traits<PREC>::store* __restrict__ in,
-                                                     typename prec_traits<PREC>::store* __restrict__ out,
-                                                     schur_geo g, int nrhs, typename prec_traits<PREC>::real d,
-                                                     typename prec_traits<PREC>::real c,
-                                                     const int* __restrict__ live) {
+__global__ __launch_bounds__(schur_max_items<PREC>::value) void k_schur_fused(
+    const typename prec_traits<PREC>::store* __restrict__ U, const typename prec_traits<PREC>::store* __restrict__ in,
+    typename prec_traits<PREC>::store* __restrict__ out, schur_geo g, int nrhs, typename prec_traits<PREC>::real d,
+    typename prec_traits<PREC>::real c, const int* __restrict__ live) {
   typedef typename prec_traits<PREC>::store S;
   typedef typename prec_traits<PREC>::real R;
   extern __shared__ unsigned char schur_lds[];

@@ -126,6 +126,68 @@ __device__ __forceinline__ spinor<R> load_spinor(const S* __restrict__ p, size_t
   return v;
 }
 
+// A spinor as stored (12 storage elements, not yet widened), so that a
+// kernel can issue its loads early and project it later.
+template <typename S>
+struct raw_spinor {
+  S c[12];
+};
+template <typename S>
+__device__ __forceinline__ raw_spinor<S> load_raw(const S* __restrict__ p, size_t base, int cs) {
+  raw_spinor<S> v;
+#pragma unroll
+  for (int i = 0; i < 12; ++i) v.c[i] = p[base + (size_t)i * cs];
+  return v;
+}
+
+// Half spinor h = u + t B_mu d of a stored spinor (project<MU, T> of the
+// widened values).  `one` must be 1: for FP16 storage each entry of h is
+// then one mixed-precision FMA, fma(d, +-one, u), on the FP16 values as
+// loaded, which rounds exactly as the FP32 sum of the widened values but
+// needs no conversions first (a run-time 1 keeps the compiler from folding
+// the FMA back into an add of converted values).
+template <int MU, int T, typename S, typename R>
+__device__ __forceinline__ half_spinor<R> project_raw(const raw_spinor<S>& v, R one) {
+  (void)one;
+  spinor<R> w;
+#pragma unroll
+  for (int i = 0; i < 12; ++i) w.c[i / 3][i % 3] = widen(v.c[i]);
+  return project<MU, T>(w);
+}
+template <int MU, int T>
+__device__ __forceinline__ half_spinor<float> project_raw(const raw_spinor<h2_t>& v, float one) {
+  const float s = T > 0 ? one : -one;
+  auto mix = [](_Float16 a, float f, _Float16 b) { return __builtin_fmaf((float)a, f, (float)b); };
+  half_spinor<float> h;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const h2_t u0 = v.c[a], u1 = v.c[3 + a], d0 = v.c[6 + a], d1 = v.c[9 + a];
+    if (MU == 0) {  // B_0 d = (d0, d1)
+      h.c[0][a] = {mix(d0.x, s, u0.x), mix(d0.y, s, u0.y)};
+      h.c[1][a] = {mix(d1.x, s, u1.x), mix(d1.y, s, u1.y)};
+    }
+    if (MU == 1) {  // B_1 d = (-i d1, -i d0)
+      h.c[0][a] = {mix(d1.y, s, u0.x), mix(d1.x, -s, u0.y)};
+      h.c[1][a] = {mix(d0.y, s, u1.x), mix(d0.x, -s, u1.y)};
+    }
+    if (MU == 2) {  // B_2 d = (-d1, d0)
+      h.c[0][a] = {mix(d1.x, -s, u0.x), mix(d1.y, -s, u0.y)};
+      h.c[1][a] = {mix(d0.x, s, u1.x), mix(d0.y, s, u1.y)};
+    }
+    if (MU == 3) {  // B_3 d = (-i d0, i d1)
+      h.c[0][a] = {mix(d0.y, s, u0.x), mix(d0.x, -s, u0.y)};
+      h.c[1][a] = {mix(d1.y, -s, u1.x), mix(d1.x, s, u1.y)};
+    }
+  }
+  return h;
+}
+
+// the projected neighbour straight from storage
+template <int MU, int T, typename S, typename R>
+__device__ __forceinline__ half_spinor<R> load_project(const S* __restrict__ p, size_t base, int cs, R one) {
+  return project_raw<MU, T>(load_raw(p, base, cs), one);
+}
+
 template <typename S, typename R>
 __device__ __forceinline__ void store_spinor(S* __restrict__ p, size_t base, int cs, const spinor<R>& v) {
 #pragma unroll
