@@ -55,6 +55,29 @@ __device__ __forceinline__ void block_combine(cx<double> (&val)[KB], int K, int 
   const int tid = threadIdx.x;
   const int bt = blockDim.x;
   const size_t base = (size_t)blockIdx.x * K * nrhs;
+  if (nrhs <= 8 && (nrhs & (nrhs - 1)) == 0 && bt % 64 == 0) {
+    // few rhs (a power of two): thread t of the block owns rhs t % nrhs
+    // (the block size is a multiple of nrhs), so a butterfly within each
+    // wavefront sums its lanes of one rhs, and one thread per rhs adds the
+    // wavefronts' sums
+    const int lane = tid & 63, wave = tid >> 6, nw = bt >> 6;
+    for (int k = 0; k < K; ++k) {
+      cx<double> v = {0.0, 0.0};
+#pragma unroll
+      for (int q = 0; q < KB; ++q)
+        if (q == k) v = val[q];
+      v = wave_group_sum(active ? v : cx<double>{0.0, 0.0}, nrhs);
+      if (lane < nrhs) sh[wave * 8 + lane] = v;
+      __syncthreads();
+      if (tid < nrhs) {
+        cx<double> acc = {0.0, 0.0};
+        for (int w = 0; w < nw; ++w) acc = acc + sh[w * 8 + tid];
+        part[base + (size_t)k * nrhs + tid] = acc;
+      }
+      __syncthreads();
+    }
+    return;
+  }
   for (int k = 0; k < K; ++k) {
     cx<double> v = {0.0, 0.0};
 #pragma unroll

@@ -87,6 +87,31 @@ __device__ __forceinline__ void vblock_combine(A (&re)[KB][VW], A (&im)[KB][VW],
   const int G = nrhs / VW;
   const size_t base = (size_t)blockIdx.x * K * nrhs;
   const size_t t0 = (size_t)blockIdx.x * bt;
+  if (G <= 8 && (G & (G - 1)) == 0 && bt % 64 == 0) {
+    // few rhs groups (a power of two): thread t owns group t % G, so a
+    // butterfly within each wavefront sums its lanes of one group, and one
+    // thread per group adds the wavefronts' sums
+    const int lane = tid & 63, wave = tid >> 6, nw = bt >> 6;
+    for (int k = 0; k < K; ++k) {
+#pragma unroll
+      for (int v = 0; v < VW; ++v) {
+        cx<double> x = {0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < KB; ++q)
+          if (q == k) x = {(double)re[q][v], (double)im[q][v]};
+        x = wave_group_sum(active ? x : cx<double>{0.0, 0.0}, G);
+        if (lane < G) sh[wave * 8 + lane] = x;
+        __syncthreads();
+        if (tid < G) {
+          cx<double> a = {0.0, 0.0};
+          for (int w = 0; w < nw; ++w) a = a + sh[w * 8 + tid];
+          part[base + (size_t)k * nrhs + (size_t)tid * VW + v] = a;
+        }
+        __syncthreads();
+      }
+    }
+    return;
+  }
   for (int k = 0; k < K; ++k) {
 #pragma unroll
     for (int v = 0; v < VW; ++v) {

@@ -207,6 +207,17 @@ __device__ __forceinline__ unsigned xcd_block(unsigned bid, unsigned nblk) {
   return k * q + (k < r ? k : r) + i;
 }
 
+// Sum of x over the lanes of this wavefront that hold the same rhs group
+// (lanes congruent modulo G, G a power of two dividing 64), left in lanes
+// 0..G-1: a butterfly over lane distances 32, 16, ..., G, in a fixed order.
+__device__ __forceinline__ cx<double> wave_group_sum(cx<double> x, int G) {
+  for (int s = 32; s >= G; s >>= 1) {
+    x.re += __shfl_xor(x.re, s);
+    x.im += __shfl_xor(x.im, s);
+  }
+  return x;
+}
+
 // True when an activity mask is given and no rhs of the block is active (a
 // lattice of a lock-step batch whose rhs have all converged): the BLAS
 // kernels then return at once; their partial sums are only read for active
