@@ -14,7 +14,8 @@ multi-lattice batch, differentiation, small lattices) and the oracle's CPU
 throughput on a sample of the same apply (two of the 16 rhs).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-sweep] [--no-cpu] [--no-counters]
-    python bench.py --only {apply,sweep-f64,schur-f64,schur-sizes,clover-f64,gmres-fixed,block-fixed,gmres-ir}
+    python bench.py --only {apply,sweep-f64,schur-f64,schur-sizes,clover-f64,gmres-fixed,block-fixed,block-hard,
+                            gmres-ir}
                     [--prec f64|f32|f16] [--kind full|schur] [--nrhs N] [--calibrate]
                                     (one workload, for profilers)
 
@@ -678,6 +679,32 @@ def profile_only(args):
                 del Ul, xe, ye, wk
                 torch.cuda.empty_cache()
         out["points"] = pts
+    elif args.only == "block-hard":
+        # block against batched GMRES(30), odd-even, 16 rhs, to a true 1e-10 on
+        # 16^3 x 32 near-identity links (eps 0.3) as m0 moves towards the
+        # critical mass: steps and seconds of each
+        import lqcd_synth as syn
+
+        dims = (32, 16, 16, 16)
+        Uh = torch.from_numpy(syn.gauge_field(dims, "near_identity", config=CONFIG, eps=EPS)).to(dev)
+        bh = torch.randn(dims + (4, 3, NRHS), dtype=torch.complex128, device=dev, generator=g)
+        pts = []
+        for m0 in (-0.05, -0.15, -0.25, -0.35):
+            kw = dict(restart=30, eo=True, tol=1e-10, max_restarts=2000)
+            rec = {"lattice": list(dims), "nrhs": NRHS, "m0": m0}
+            for name, fn in (("batched", lq.gmres_solve), ("block", lq.block_gmres_solve)):
+                fn(Uh, bh, m0, layout=lq.LAYOUT2, **dict(kw, max_restarts=1))  # warm-up
+                torch.cuda.synchronize()
+                t = time.time()
+                _, st, rc = fn(Uh, bh, m0, layout=lq.LAYOUT2, **kw)
+                torch.cuda.synchronize()
+                dt = time.time() - t
+                steps = int(st["iters"].max())
+                rec[name] = {"seconds": round(dt, 3), "steps": steps, "ms_per_step": round(dt * 1e3 / steps, 3),
+                             "status": int(rc), "max_true_relres": float(st["true_relres"].max())}
+            log(f"block-hard: {json.dumps(rec)}")
+            pts.append(rec)
+        out["points"] = pts
     elif args.only == "clover-f64":  # D = D_W - C: full apply, then the Schur apply (two passes)
         C = 0.1 * torch.randn(DIMS + (42,), dtype=torch.complex128, device=dev, generator=g)
         Ci = 0.1 * torch.randn(DIMS + (42,), dtype=torch.complex128, device=dev, generator=g)
@@ -771,7 +798,7 @@ def main():
     ap.add_argument("--retune", action="store_true", help="ignore the tune file and autotune every apply")
     ap.add_argument("--save-tune", default="", help="write the autotuner's table here at the end")
     ap.add_argument("--only", choices=["apply", "sweep-f64", "schur-f64", "schur-sizes", "clover-f64", "gmres-fixed",
-                                       "block-fixed", "gmres-ir"],
+                                       "block-fixed", "block-hard", "gmres-ir"],
                     default="",
                     help="profiling mode: run one workload only (GPU-drawn inputs except the near-identity links of "
                          "gmres-ir, tune file), print its times")
