@@ -92,10 +92,10 @@ int lqcd_lattice_tables(const lqcd_lattice* lat, int32_t* nbr, int32_t* eo_site)
  * links reach the 16 rhs lanes of a column by row broadcasts, one load per
  * link element and row (LQCD_LAYOUT1 / LQCD_LAYOUT2, nrhs a multiple of 16,
  * any precision, full operator and odd-even hops; otherwise as 3),
- * 7 = variant 6 whose workgroups (256 / nrhs consecutive x columns) pass
- * their streamed spinors through LDS so that the inner columns read their
- * +-x neighbours there (full operator; odd-even hops run as 6; lattices
- * whose x extent does not hold whole workgroups run as 6),
+ * 7 = variant 6 whose workgroups (256 / nrhs consecutive x columns, compact
+ * columns for the odd-even hops) pass their streamed spinors through LDS so
+ * that the inner columns read their +-x neighbours there (lattices whose x
+ * extent does not hold whole workgroups run as 6),
  * 8 = the Schur apply of dirac_apply_eo(_ws/_noalloc) and of the odd-even
  * solvers in one kernel (Sec. III-A.2): a workgroup computes the odd field
  * H_oe psi_e for its tile of (y, z) rows and the rows around it into LDS,
@@ -103,7 +103,7 @@ int lqcd_lattice_tables(const lqcd_lattice* lat, int32_t* nbr, int32_t* eo_site)
  * reaches memory (any layout and precision; tile_y, tile_z: interior tile,
  * wg_per_cu 1 or 2: the LDS share a workgroup may use; a lattice whose x
  * rows do not fit a workgroup runs the two hop passes; the full operator
- * runs as 7, single odd-even hop passes as 6).
+ * and single odd-even hop passes run as 7).
  * pencil (may be NULL) = {tile Y, tile Z,
  * number of t segments} for variants 2 and 3; 0 entries are chosen automatically, values
  * that do not divide the lattice fall back to automatic.  Every choice

@@ -119,8 +119,8 @@ hipError_t wilson_eo(const lqcd_lattice* lat, const void* U, const void* in, con
                      int nrhs, double alpha, double beta, int layout, int prec, bool dagger, const int* live,
                      hipStream_t s) {
   kcfg c = choose_cfg(KIND_EO, lat, nrhs, prec, layout);
-  if (c.variant == 7 || c.variant == 8) c.variant = 6;
-  if (c.variant == 6) {
+  if (c.variant == 8) c.variant = 7;
+  if (c.variant == 6 || c.variant == 7) {
     if (bc_supported(layout, nrhs))
       return wilson_eo_bc(lat, U, in, xin, out, p, nrhs, alpha, beta, layout, prec, dagger, live, c, s);
     c.variant = 3;

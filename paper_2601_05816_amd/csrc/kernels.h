@@ -24,10 +24,10 @@ hipError_t wilson_eo(const lqcd_lattice* lat, const void* U, const void* in, con
 // even nrhs; otherwise treated as 3), 5 pencils fed by global-to-LDS loads
 // (FP64, rhs-innermost, nrhs >= 11, full operator; otherwise treated as 3), 6 pencils whose links
 // reach the rhs lanes of a column by row broadcasts (rhs-fastest layouts, nrhs % 16 == 0; otherwise
-// treated as 3), 7 as 6 with the +-x neighbours of a workgroup's inner columns read from LDS (full
-// operator; otherwise treated as 6), 8 the Schur complement in one kernel (schur.hip; selects
-// that kernel for a whole Schur apply, is treated as 7 by the full operator and as 6 by a single
-// odd-even hop pass); ty, tz, nseg: pencil tile and t segments
+// treated as 3), 7 as 6 with the +-x neighbours of a workgroup's inner columns read from LDS
+// (lattices whose x rows hold whole workgroups; otherwise treated as 6), 8 the Schur complement in
+// one kernel (schur.hip; selects that kernel for a whole Schur apply, is treated as 7 by the full
+// operator and by a single odd-even hop pass); ty, tz, nseg: pencil tile and t segments
 // (0 = automatic); nt: non-temporal output stores; occ: at most this many
 // workgroups per compute unit (0 = no cap), enforced through the LDS request.
 struct kcfg {

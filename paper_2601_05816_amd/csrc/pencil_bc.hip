@@ -245,7 +245,7 @@ __global__ __launch_bounds__(256) void k_wilson_full_pb(const typename prec_trai
 // elements, five per lane (the output site's x alternates with t, so the
 // element addresses are formed per step).  Lanes of converged rhs (`live`)
 // take part in the loads and broadcasts and skip only their store.
-template <int PREC, int LAYOUT, int SG>
+template <int PREC, int LAYOUT, int SG, bool XL>
 __global__ __launch_bounds__(256) void k_wilson_eo_pb(const typename prec_traits<PREC>::store* __restrict__ U,
                                                       const typename prec_traits<PREC>::store* __restrict__ in,
                                                       const typename prec_traits<PREC>::store* __restrict__ xin,
@@ -256,9 +256,17 @@ __global__ __launch_bounds__(256) void k_wilson_eo_pb(const typename prec_traits
                                                       const int* __restrict__ live) {
   typedef typename prec_traits<PREC>::store S;
   typedef typename prec_traits<PREC>::real R;
+  // XL: the workgroup's columns at one t, [column][12][rhs] (see the kernel's comment)
+  __shared__ S xs[XL ? 256 * 12 : 1];
   int j, y, z, rhs, t0;
   if (!pencil_item<LAYOUT>(pg, nrhs, j, y, z, rhs, t0, blockIdx.x)) return;
   const bool store_me = !live || live[rhs];
+  const int lc = (int)threadIdx.x / nrhs, ncw = 256 / nrhs;  // column within the workgroup (XL)
+  const int jbase = j - lc;                                  // the workgroup's first compact column
+  auto put = [&](const spinor<R>& v) {
+#pragma unroll
+    for (int i = 0; i < 12; ++i) st(xs + ((size_t)lc * 12 + i) * nrhs + rhs, v.c[i / 3][i % 3]);
+  };
   const int T = pg.n[0], NZ = pg.n[1], NY = pg.n[2], NX = pg.n[3];
   const R one = (R)pg.one;
   const int NXh = NX >> 1;
@@ -314,7 +322,11 @@ __global__ __launch_bounds__(256) void k_wilson_eo_pb(const typename prec_traits
   if (CARRY) {
     const int tm = t0 > 0 ? t0 - 1 : T - 1;
     qm = project<0, SG>(load_spinor<S, R>(in, blk<LAYOUT>::base((size_t)tm * H0 + hc, rhs, Vh, nrhs), cs));
-    qn = project<0, SG>(load_spinor<S, R>(in, blk<LAYOUT>::base((size_t)t0 * H0 + hc, rhs, Vh, nrhs), cs));
+    const spinor<R> p0 = load_spinor<S, R>(in, blk<LAYOUT>::base((size_t)t0 * H0 + hc, rhs, Vh, nrhs), cs);
+    qn = project<0, SG>(p0);
+    if (XL) put(p0);
+  } else if (XL) {
+    put(load_spinor<S, R>(in, blk<LAYOUT>::base((size_t)t0 * H0 + hc, rhs, Vh, nrhs), cs));
   }
   for (int it = 0; it < pg.Lt; ++it) {
     const int t = t0 + it;
@@ -325,7 +337,10 @@ __global__ __launch_bounds__(256) void k_wilson_eo_pb(const typename prec_traits
     spinor<R> acc;
 #pragma unroll
     for (int i = 0; i < 12; ++i) acc.c[i / 3][i % 3] = {R(0), R(0)};
-    {
+    // time direction: the +t neighbour in(t+1) of this compact column (with
+    // XL at the end of the step: it is the spinor this column puts into LDS
+    // for the next step's x neighbours)
+    if constexpr (!XL) {
       const int tm = t > 0 ? t - 1 : T - 1, t1 = t + 1 < T ? t + 1 : 0;
       spinor<R> pf = load_spinor<S, R>(in, blk<LAYOUT>::base((size_t)t1 * H0 + hc, rhs, Vh, nrhs), cs);
       reconstruct<0, -SG>(acc, colour_mul_r<false>(bc_link<0, S, R>(lr), project<0, -SG>(pf)));
@@ -340,8 +355,23 @@ __global__ __launch_bounds__(256) void k_wilson_eo_pb(const typename prec_traits
     }
     {
       const int xf = x + 1 < NX ? x + 1 : 0, xb = x > 0 ? x - 1 : NX - 1;
-      add_hop_pair_bc<3, SG, 2, 3>(acc, in, blk<LAYOUT>::base(toffh + row * NXh + (xf >> 1), rhs, Vh, nrhs),
-                                        blk<LAYOUT>::base(toffh + row * NXh + (xb >> 1), rhs, Vh, nrhs), cs, lr, one);
+      const int jf = xf >> 1, jb = xb >> 1;
+      if constexpr (XL) {
+        // in(t) of the x neighbours' compact columns: LDS when they belong
+        // to this workgroup, else memory
+        __syncthreads();  // every column's in(t) is in LDS
+        const int cf = jf - jbase, cb = jb - jbase;
+        spinor<R> pf, pb;
+        if (cf >= 0 && cf < ncw) pf = load_spinor<S, R>(xs, ((size_t)cf * 12) * nrhs + rhs, nrhs);
+        else pf = load_spinor<S, R>(in, blk<LAYOUT>::base(toffh + row * NXh + jf, rhs, Vh, nrhs), cs);
+        if (cb >= 0 && cb < ncw) pb = load_spinor<S, R>(xs, ((size_t)cb * 12) * nrhs + rhs, nrhs);
+        else pb = load_spinor<S, R>(in, blk<LAYOUT>::base(toffh + row * NXh + jb, rhs, Vh, nrhs), cs);
+        reconstruct<3, -SG>(acc, colour_mul_r<false>(bc_link<2, S, R>(lr), project<3, -SG>(pf)));
+        reconstruct<3, SG>(acc, colour_mul_r<true>(bc_link<3, S, R>(lr), project<3, SG>(pb)));
+      } else {
+        add_hop_pair_bc<3, SG, 2, 3>(acc, in, blk<LAYOUT>::base(toffh + row * NXh + jf, rhs, Vh, nrhs),
+                                     blk<LAYOUT>::base(toffh + row * NXh + jb, rhs, Vh, nrhs), cs, lr, one);
+      }
     }
     {
       add_hop_pair_bc<2, SG, 4, 5>(acc, in, blk<LAYOUT>::base(toffh + hyf, rhs, Vh, nrhs),
@@ -350,6 +380,20 @@ __global__ __launch_bounds__(256) void k_wilson_eo_pb(const typename prec_traits
     {
       add_hop_pair_bc<1, SG, 6, 7>(acc, in, blk<LAYOUT>::base(toffh + hzf, rhs, Vh, nrhs),
                                         blk<LAYOUT>::base(toffh + hzb, rhs, Vh, nrhs), cs, lr, one);
+    }
+    spinor<R> pnext;  // XL: this column's in(t+1)
+    if constexpr (XL) {
+      const int tm = t > 0 ? t - 1 : T - 1, t1 = t + 1 < T ? t + 1 : 0;
+      pnext = load_spinor<S, R>(in, blk<LAYOUT>::base((size_t)t1 * H0 + hc, rhs, Vh, nrhs), cs);
+      reconstruct<0, -SG>(acc, colour_mul_r<false>(bc_link<0, S, R>(lr), project<0, -SG>(pnext)));
+      if (CARRY) {
+        reconstruct<0, SG>(acc, colour_mul_r<true>(bc_link<1, S, R>(lr), qm));
+        qm = qn;
+        qn = project<0, SG>(pnext);
+      } else {
+        spinor<R> pb = load_spinor<S, R>(in, blk<LAYOUT>::base((size_t)tm * H0 + hc, rhs, Vh, nrhs), cs);
+        reconstruct<0, SG>(acc, colour_mul_r<true>(bc_link<1, S, R>(lr), project<0, SG>(pb)));
+      }
     }
     const size_t me = blk<LAYOUT>::base(hh, rhs, Vh, nrhs);
     if (xin) {
@@ -370,6 +414,10 @@ __global__ __launch_bounds__(256) void k_wilson_eo_pb(const typename prec_traits
     if (it + 1 < pg.Lt) {
 #pragma unroll
       for (int q = 0; q < 5; ++q) lr[q] = ln[q];
+      if constexpr (XL) {
+        __syncthreads();  // every column has read its x neighbours at t
+        put(pnext);
+      }
     }
   }
 }
@@ -410,9 +458,15 @@ static hipError_t go_eo(const lqcd_lattice* lat, const void* U, const void* in, 
   typedef typename prec_traits<PREC>::real R;
   pencil_geo pg = make_pencil(lat, nrhs, true, c);
   size_t dyn = 0;
+  if (c.variant == 7 && xl_fits(pg, nrhs)) {
+    if (!occupancy_lds(c.occ, 256 * 12 * sizeof(S), &dyn)) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((k_wilson_eo_pb<PREC, LAYOUT, SG, true>), dim3(pencil_blocks(pg)), dim3(256), dyn, s,
+                       (const S*)U, (const S*)in, (const S*)xin, (S*)out, pg, p, nrhs, (R)alpha, (R)beta, live);
+    return hipSuccess;
+  }
   if (!occupancy_lds(c.occ, 0, &dyn)) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((k_wilson_eo_pb<PREC, LAYOUT, SG>), dim3(pencil_blocks(pg)), dim3(256), dyn, s, (const S*)U,
-                     (const S*)in, (const S*)xin, (S*)out, pg, p, nrhs, (R)alpha, (R)beta, live);
+  hipLaunchKernelGGL((k_wilson_eo_pb<PREC, LAYOUT, SG, false>), dim3(pencil_blocks(pg)), dim3(256), dyn, s,
+                     (const S*)U, (const S*)in, (const S*)xin, (S*)out, pg, p, nrhs, (R)alpha, (R)beta, live);
   return hipSuccess;
 }
 

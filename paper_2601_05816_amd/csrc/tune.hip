@@ -96,7 +96,7 @@ static std::vector<kcfg> candidates(const lqcd_lattice* lat, int layout, int pre
         if (!eo && dma_supported(prec, layout, nrhs)) out.push_back({5, t[0], t[1], sg, nt, 0});
         if (bc_supported(layout, nrhs)) {
           out.push_back({6, t[0], t[1], sg, nt, 0});
-          if (!eo) out.push_back({7, t[0], t[1], sg, nt, 0});
+          out.push_back({7, t[0], t[1], sg, nt, 0});
         }
       }
   return out;

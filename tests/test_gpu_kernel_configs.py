@@ -205,7 +205,8 @@ def test_x_neighbours_through_lds(gpu_lib, prec, dims, nrhs, pencil):
     columns of a workgroup read from LDS, 256 / nrhs consecutive columns per
     workgroup, end columns from memory): full apply D and D^dagger in both
     rhs-fastest layouts on lattices whose x extent holds whole workgroups;
-    the odd-even apply runs variant 6."""
+    the odd-even apply (compact x rows of half the length) falls back to
+    variant 6 on these lattices."""
     gpu_lib.set_kernel_config(7, pencil[0], pencil[1], pencil[2], pencil[3])
     U = rounded(syn.gauge_field(dims, "haar", config=16), prec)
     psi = rounded(syn.spinor_block(dims, nrhs, config=16), prec)
@@ -217,3 +218,46 @@ def test_x_neighbours_through_lds(gpu_lib, prec, dims, nrhs, pencil):
     psi_e = geometry.to_half(psi, dims, 0)
     got = _apply_eo_gpu(U, psi_e, 0.3, lq.LAYOUT2, prec)
     assert np.all(rel_err_per_rhs(got, evenodd.apply_schur(U, psi_e, 0.3)) <= TOL[prec] * 2)
+
+
+@pytest.mark.parametrize("prec", [lq.F64, lq.F32, lq.F16])
+@pytest.mark.parametrize("dims,nrhs", [((4, 2, 2, 32), 16), ((4, 2, 4, 16), 32), ((2, 2, 2, 8), 64)])
+@pytest.mark.parametrize("pencil", [(0, 0, 0, 1), (1, 2, 2, 0), (2, 1, 1, 1)])
+def test_x_neighbours_through_lds_odd_even(gpu_lib, prec, dims, nrhs, pencil):
+    """Variant 7 in the odd-even hop passes (the workgroup's 256 / nrhs
+    consecutive compact columns put their streamed +t spinor into LDS, the
+    next step's x neighbours of the inner columns are read there): the
+    Schur apply S and S^dagger in both rhs-fastest layouts against the
+    oracle, on lattices whose compact x rows hold whole workgroups."""
+    gpu_lib.set_kernel_config(7, pencil[0], pencil[1], pencil[2], pencil[3])
+    U = rounded(syn.gauge_field(dims, "haar", config=17), prec)
+    psi_e = geometry.to_half(rounded(syn.spinor_block(dims, nrhs, config=17), prec), dims, 0)
+    for layout in (lq.LAYOUT1, lq.LAYOUT2):
+        for dagger in (False, True):
+            if dagger:  # S^dagger = gamma5 S gamma5
+                want = _g5h(evenodd.apply_schur(U, _g5h(psi_e), -0.15))
+            else:
+                want = evenodd.apply_schur(U, psi_e, -0.15)
+            got = _apply_eo_gpu(U, psi_e, -0.15, layout, prec, dagger)
+            assert np.all(rel_err_per_rhs(got, want) <= TOL[prec] * 2), (layout, dagger)
+
+
+def test_x_neighbours_through_lds_odd_even_in_solves(gpu_lib):
+    """The odd-even variant 7 inside GMRES (converged rhs keep taking part in
+    the loads, LDS exchange and barriers and skip their stores): all three
+    modes reach a true 1e-10 on every rhs, checked with the oracle's D_W."""
+    gpu_lib.set_kernel_config(7, 0, 0, 0, 1)
+    dims = (8, 2, 2, 32)
+    m0 = -0.05
+    U = syn.gauge_field(dims, "near_identity", config=18, eps=0.3)
+    b = syn.spinor_block(dims, 16, config=18)
+    b[5] *= 1e-3  # rhs with different iteration counts
+    Ud = to_dev(U, lq.F64)
+    bd = to_dev(to_layout_np(b, lq.LAYOUT2), lq.F64)
+    for mode in ("f64", "ir-f32", "ir-f16"):
+        x, st, rc = lq.gmres_solve(Ud, bd, m0, layout=lq.LAYOUT2, eo=True, mode=mode, tol=1e-10)
+        assert rc == lq.OK, mode
+        xs = from_layout_np(from_dev(x, lq.F64), lq.LAYOUT2, 4)
+        res = dirac.apply_dw(U, xs, m0) - b
+        rel = np.linalg.norm(res.reshape(16, -1), axis=1) / np.linalg.norm(b.reshape(16, -1), axis=1)
+        assert np.all(rel <= 1e-10), (mode, rel)
