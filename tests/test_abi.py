@@ -147,9 +147,19 @@ def test_rhs_block_choice_on_host(tmp_path):
     tune = os.path.join(os.path.dirname(HEADER), "..", "paper_2601_05816_amd", "tune_mi355x.txt")
     assert lq.tune_load(tune) > 0
     try:
-        # FP64 odd-even hop pass per launch: 32 rhs 4.86 ms, 16 rhs 2.54 ms, 8 rhs 1.50 ms:
-        # two chunks of 32 cost least
-        assert lq.gmres_rhs_block(dims, 64, p, ws[32]) == 32
+        # the width with the least table time per rhs among those the
+        # workspace holds (FP64 odd-even hop pass entries of the table)
+        times = {}
+        for line in open(tune):
+            if line.startswith("#") or ":" not in line:
+                continue
+            k, v = line.split(":")
+            k = [int(f) for f in k.split()]
+            if k[0] == 1 and tuple(k[1:5]) == dims and k[6] == lq.F64 and k[7] == lq.LAYOUT2:
+                times[k[5]] = float(v.split()[-1])
+        cand = [w for w in (48, 32, 24, 16, 12, 8, 4, 2, 1) if w in times and ws.get(w, 0) <= ws[32]]
+        want = min(cand, key=lambda w: (times[w] * ((64 + w - 1) // w), -w))
+        assert lq.gmres_rhs_block(dims, 64, p, ws[32]) == want
     finally:
         lq.tune_clear()
     # a smaller chunk shrinks the workspace in proportion to its rhs
