@@ -239,6 +239,8 @@ __global__ void k_bstart(int b, const zd* __restrict__ nrm, const double* __rest
   flags[1] = bad;
 }
 
+constexpr int BMX = LQCD_BLOCK_MAX_RHS;  // widest block of the block solver
+
 // G = R^H R for the Gram block G of the active columns (R upper triangular,
 // unit rows and columns for the inactive ones) and Rinv = R^-1.  A pivot at
 // or below 1e-12 of the largest diagonal entry of G (a diagonal entry of R
@@ -249,62 +251,80 @@ __global__ void k_bstart(int b, const zd* __restrict__ nrm, const double* __rest
 // With deflate (the residual block at a restart) the first such column is
 // instead taken out of the cycle (act = 0, f = 0) and *bad = 2: the caller
 // zeroes it and factorises again.
-__global__ void k_bchol(int b, int* __restrict__ act, const zd* __restrict__ G, zd* __restrict__ R,
-                        zd* __restrict__ Rinv, int* __restrict__ bad, int deflate, double* __restrict__ f) {
-  if (threadIdx.x || blockIdx.x) return;
+__global__ __launch_bounds__(64) void k_bchol(int b, int* __restrict__ act, const zd* __restrict__ G,
+                                              zd* __restrict__ R, zd* __restrict__ Rinv, int* __restrict__ bad,
+                                              int deflate, double* __restrict__ f) {
+  // G and R in LDS; the entries of a row of R right of its pivot are
+  // computed in parallel (thread c: column c), columns of R^-1 likewise.
+  // Every thread reads the same pivots, so the branches are uniform.
+  __shared__ zd g[BMX * BMX], r[BMX * BMX];
+  __shared__ int ac[BMX];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < b * b; i += blockDim.x) {
+    g[i] = G[i];
+    r[i] = {0.0, 0.0};
+  }
+  if (tid < b) ac[tid] = act[tid];
+  __syncthreads();
   double gmax = 0.0;
   for (int q = 0; q < b; ++q)
-    if (act[q] && G[q * b + q].re > gmax) gmax = G[q * b + q].re;
-  for (int i = 0; i < b * b; ++i) R[i] = {0.0, 0.0};
+    if (ac[q] && g[q * b + q].re > gmax) gmax = g[q * b + q].re;
   int deficient = 0;
   for (int q = 0; q < b; ++q) {
-    if (!act[q]) {
-      R[q * b + q] = {1.0, 0.0};
+    if (!ac[q]) {  // row q of R stays a unit row
+      if (tid == 0) r[q * b + q] = {1.0, 0.0};
       continue;
     }
-    double d = G[q * b + q].re;
-    for (int p = 0; p < q; ++p) d -= R[p * b + q].re * R[p * b + q].re + R[p * b + q].im * R[p * b + q].im;
+    double d = g[q * b + q].re;
+    for (int p = 0; p < q; ++p) d -= r[p * b + q].re * r[p * b + q].re + r[p * b + q].im * r[p * b + q].im;
     if (!(d > 1e-12 * gmax)) {
       if (deflate) {
-        act[q] = 0;
-        f[q] = 0.0;
-        *bad = 2;
+        if (tid == 0) {
+          act[q] = 0;
+          f[q] = 0.0;
+          *bad = 2;
+        }
         return;
       }
       deficient = 1;
-      R[q * b + q] = {d > 0.0 ? sqrt(d) : 0.0, 0.0};
+      if (tid == 0) r[q * b + q] = {d > 0.0 ? sqrt(d) : 0.0, 0.0};
       continue;
     }
     const double rq = sqrt(d);
-    R[q * b + q] = {rq, 0.0};
-    for (int c = q + 1; c < b; ++c) {
-      if (!act[c]) continue;
-      zd z = G[q * b + c];
+    if (tid == 0) r[q * b + q] = {rq, 0.0};
+    const int c = tid;
+    if (c > q && c < b && ac[c]) {
+      zd z = g[q * b + c];
       for (int p = 0; p < q; ++p) {  // z -= conj(R[p][q]) R[p][c]
-        const zd u = R[p * b + q], v = R[p * b + c];
+        const zd u = r[p * b + q], v = r[p * b + c];
         z.re -= u.re * v.re + u.im * v.im;
         z.im -= u.re * v.im - u.im * v.re;
       }
-      R[q * b + c] = {z.re / rq, z.im / rq};
+      r[q * b + c] = {z.re / rq, z.im / rq};
     }
+    __syncthreads();
   }
-  *bad = deficient;
+  __syncthreads();
+  for (int i = tid; i < b * b; i += blockDim.x) R[i] = r[i];
+  if (tid == 0) *bad = deficient;
   if (deficient) return;
-  for (int i = 0; i < b * b; ++i) Rinv[i] = {0.0, 0.0};
-  for (int c = 0; c < b; ++c) {  // column c of R^-1 by back substitution
-    const double dc = R[c * b + c].re;
-    Rinv[c * b + c] = {1.0 / dc, 0.0};
+  if (tid < b) {  // column c of R^-1 by back substitution, into g
+    const int c = tid;
+    for (int i = 0; i < b; ++i) g[i * b + c] = {0.0, 0.0};
+    g[c * b + c] = {1.0 / r[c * b + c].re, 0.0};
     for (int i = c - 1; i >= 0; --i) {
       zd z = {0.0, 0.0};
       for (int k = i + 1; k <= c; ++k) {
-        const zd u = R[i * b + k], v = Rinv[k * b + c];
+        const zd u = r[i * b + k], v = g[k * b + c];
         z.re += u.re * v.re - u.im * v.im;
         z.im += u.re * v.im + u.im * v.re;
       }
-      const double di = R[i * b + i].re;
-      Rinv[i * b + c] = {-z.re / di, -z.im / di};
+      const double di = r[i * b + i].re;
+      g[i * b + c] = {-z.re / di, -z.im / di};
     }
   }
+  __syncthreads();
+  for (int i = tid; i < b * b; i += blockDim.x) Rinv[i] = g[i];
 }
 
 // rotated right-hand side of the cycle's least-squares problem: [S; 0]
@@ -328,72 +348,163 @@ __device__ __forceinline__ void brot(zd& x, zd& y, double c, zd s) {
 // rotations, zero its b subdiagonals with b rotations per column, rotate the
 // right-hand side and read the per-rhs residual estimates off the last b
 // rows.  flags[0] counts the active columns that are still above tolerance.
-__global__ __launch_bounds__(64) void k_bhess(int j, int m, int b, const zd* __restrict__ Hc,
-                                              const zd* __restrict__ R, zd* __restrict__ H, double* __restrict__ cs,
-                                              zd* __restrict__ sn, zd* __restrict__ G, const int* __restrict__ act,
-                                              const double* __restrict__ bref, double tol, int fixed,
-                                              double* __restrict__ est, int* __restrict__ flags) {
+//
+// Layout of the work: lane q of the first wavefront owns column c0 + q and
+// carries the b + 1 rows an earlier rotation step cp touches (rows cp ..
+// cp + b) in registers, so the cp-loop is a register chain; the other
+// wavefronts stage the rotations and the incoming rows of the next
+// BH_CH steps in LDS meanwhile.  The new rotations of the 2b x b diagonal
+// block are formed in parallel: the rotation that zeroes subdiagonal entry t
+// of a column leaves the pivot with the norm r_t of the pivot and entries
+// 0..t, so cosine r_{t-1} / r_t and sine u conj(y_t) / r_t (u the pivot's
+// phase) follow from running sums of |y|^2.
+constexpr int BH_CH = 32;
+
+// n earlier rotation steps applied to one column of the incoming block:
+// x = row cp, w[t] = row cp + 1 + t (t < B) in registers; row cp is final
+// after step cp and goes to hcol, row cp + 1 + B enters from lr.  B is a
+// template argument so that every index into w is a constant.
+template <int B>
+__device__ __forceinline__ void bhess_rows(zd& x, zd (&w)[BMX], const double* lc, const zd* ls, const zd* lr, int n,
+                                           zd* hcol, size_t mb, int q) {
+  for (int i = 0; i < n; ++i) {
+#pragma unroll
+    for (int t = 0; t < B; ++t) brot(x, w[t], lc[i * B + t], ls[i * B + t]);
+    hcol[(size_t)i * mb] = x;
+    x = w[0];
+#pragma unroll
+    for (int t = 0; t < B - 1; ++t) w[t] = w[t + 1];
+    w[B - 1] = lr[i * B + q];
+  }
+}
+
+
+__global__ __launch_bounds__(256) void k_bhess(int j, int m, int b, const zd* __restrict__ Hc,
+                                               const zd* __restrict__ R, zd* __restrict__ H, double* __restrict__ cs,
+                                               zd* __restrict__ sn, zd* __restrict__ G, const int* __restrict__ act,
+                                               const double* __restrict__ bref, double tol, int fixed,
+                                               double* __restrict__ est, int* __restrict__ flags) {
+  __shared__ double lcs[2][BH_CH * BMX];
+  __shared__ zd lsn[2][BH_CH * BMX], lrow[2][BH_CH * BMX];
+  __shared__ zd hb[2 * BMX * BMX], gb[2 * BMX * BMX];
+  __shared__ double rcs[BMX], ry2[BMX];
+  __shared__ zd rsn[BMX];
   const int tid = threadIdx.x;
   const size_t mb = (size_t)m * b;
-  const int c0 = j * b, nrow = (j + 2) * b;
-  for (int idx = tid; idx < nrow * b; idx += blockDim.x) {
-    const int row = idx / b, q = idx % b;
-    H[(size_t)row * mb + c0 + q] = row < (j + 1) * b ? Hc[(size_t)(row / b) * b * b + (size_t)(row % b) * b + q]
-                                                     : R[(size_t)(row - (j + 1) * b) * b + q];
-  }
-  __syncthreads();
+  const int c0 = j * b, nr = (j + 1) * b;
+  // row `row` of the incoming column block, column q: a Gram block above
+  // row nr, the factor R below
+  auto src = [&](int row, int q) -> zd {
+    return row < nr ? Hc[(size_t)(row / b) * b * b + (size_t)(row % b) * b + q] : R[(size_t)(row - nr) * b + q];
+  };
+  // rotations of steps k*BH_CH .. and the rows entering after them
+  auto stage = [&](int k, int buf) {
+    const int k0 = k * BH_CH, n = min(BH_CH, c0 - k0) * b;
+    for (int i = tid - 64; i < n; i += blockDim.x - 64) {
+      lcs[buf][i] = cs[(size_t)k0 * b + i];
+      lsn[buf][i] = sn[(size_t)k0 * b + i];
+      lrow[buf][i] = src(k0 + i / b + 1 + b, i % b);
+    }
+  };
+  zd x = {0.0, 0.0}, w[BMX];
   if (tid < b) {
-    const int c = c0 + tid;
-    for (int cp = 0; cp < c0; ++cp)
-      for (int t = 0; t < b; ++t)
-        brot(H[(size_t)cp * mb + c], H[(size_t)(cp + 1 + t) * mb + c], cs[(size_t)cp * b + t], sn[(size_t)cp * b + t]);
+    x = src(0, tid);
+#pragma unroll
+    for (int t = 0; t < BMX; ++t) w[t] = t < b ? src(1 + t, tid) : zd{0.0, 0.0};
   }
+  const int nch = (c0 + BH_CH - 1) / BH_CH;
+  if (tid >= 64 && nch > 0) stage(0, 0);
+  for (int i = tid; i < 2 * b * b; i += blockDim.x) gb[i] = G[(size_t)c0 * b + i];
   __syncthreads();
-  for (int q = 0; q < b; ++q) {
-    const int c = c0 + q;
-    if (tid == 0) {
-      for (int t = 0; t < b; ++t) {
-        zd& a = H[(size_t)c * mb + c];
-        zd& y = H[(size_t)(c + 1 + t) * mb + c];
-        const double aa = hypot(a.re, a.im), yy = hypot(y.re, y.im);
-        double cc;
-        zd ss;
-        if (yy == 0.0) {  // nothing to eliminate (also a decoupled inactive column)
-          cc = 1.0;
-          ss = {0.0, 0.0};
-        } else if (aa == 0.0) {
-          cc = 0.0;
-          ss = {y.re / yy, -y.im / yy};  // conj(y) / |y|
-        } else {
-          const double rr = hypot(aa, yy);
-          cc = aa / rr;
-          // (a / |a|) conj(y) / r
-          const zd u = {a.re / aa, a.im / aa};
-          ss = {(u.re * y.re + u.im * y.im) / rr, (u.im * y.re - u.re * y.im) / rr};
-        }
-        cs[(size_t)c * b + t] = cc;
-        sn[(size_t)c * b + t] = ss;
-        brot(a, y, cc, ss);
-        y = {0.0, 0.0};
+  for (int k = 0; k < nch; ++k) {
+    if (tid >= 64 && k + 1 < nch) stage(k + 1, (k + 1) & 1);
+    if (tid < b) {
+      const int buf = k & 1, k0 = k * BH_CH, n = min(BH_CH, c0 - k0);
+      zd* hcol = H + (size_t)k0 * mb + c0 + tid;
+      switch (b) {
+#define BH_CASE(B)                                                                               \
+  case B:                                                                                        \
+    bhess_rows<B>(x, w, lcs[buf], lsn[buf], lrow[buf], n, hcol, mb, tid);                        \
+    break;
+        BH_CASE(1) BH_CASE(2) BH_CASE(3) BH_CASE(4) BH_CASE(5) BH_CASE(6) BH_CASE(7) BH_CASE(8)
+        BH_CASE(9) BH_CASE(10) BH_CASE(11) BH_CASE(12) BH_CASE(13) BH_CASE(14) BH_CASE(15) BH_CASE(16)
+#undef BH_CASE
       }
     }
     __syncthreads();
+  }
+  // the 2b x b diagonal block: rows c0 .. c0 + 2b - 1
+  if (tid < b) {
+    hb[tid] = x;
+#pragma unroll
+    for (int t = 0; t < BMX; ++t)
+      if (t < b) hb[(1 + t) * b + tid] = w[t];
+    for (int r = b + 1; r < 2 * b; ++r) hb[r * b + tid] = src(c0 + r, tid);
+  }
+  __syncthreads();
+  for (int q = 0; q < b; ++q) {
+    const zd a = hb[q * b + q];
+    const double aa2 = a.re * a.re + a.im * a.im;
+    zd y = {0.0, 0.0};
     if (tid < b) {
-      if (tid > q)
-        for (int t = 0; t < b; ++t)
-          brot(H[(size_t)c * mb + c0 + tid], H[(size_t)(c + 1 + t) * mb + c0 + tid], cs[(size_t)c * b + t],
-               sn[(size_t)c * b + t]);
-      for (int t = 0; t < b; ++t)
-        brot(G[(size_t)c * b + tid], G[(size_t)(c + 1 + t) * b + tid], cs[(size_t)c * b + t], sn[(size_t)c * b + t]);
+      y = hb[(q + 1 + tid) * b + q];
+      ry2[tid] = y.re * y.re + y.im * y.im;
     }
     __syncthreads();
+    if (tid < b) {
+      double p0 = aa2;  // |pivot|^2 + sum_{s < t} |y_s|^2, the same sums in every lane
+      for (int s2 = 0; s2 < tid; ++s2) p0 += ry2[s2];
+      const double p1 = p0 + ry2[tid];
+      const double r0 = sqrt(p0), r1 = sqrt(p1), aa = sqrt(aa2);
+      const zd u = aa > 0.0 ? zd{a.re / aa, a.im / aa} : zd{1.0, 0.0};
+      double cc = 1.0;  // nothing to eliminate (also a decoupled inactive column)
+      zd ss = {0.0, 0.0};
+      if (r1 > 0.0) {
+        cc = r0 / r1;
+        ss = {(u.re * y.re + u.im * y.im) / r1, (u.im * y.re - u.re * y.im) / r1};
+      }
+      rcs[tid] = cc;
+      rsn[tid] = ss;
+      cs[(size_t)(c0 + q) * b + tid] = cc;
+      sn[(size_t)(c0 + q) * b + tid] = ss;
+      hb[(q + 1 + tid) * b + q] = {0.0, 0.0};
+      if (tid == b - 1) hb[q * b + q] = {u.re * r1, u.im * r1};
+    }
+    __syncthreads();
+    if (tid < b && tid > q) {  // later columns of the block
+      zd xx = hb[q * b + tid];
+#pragma unroll
+      for (int t = 0; t < BMX; ++t)
+        if (t < b) {
+          zd yv = hb[(q + 1 + t) * b + tid];
+          brot(xx, yv, rcs[t], rsn[t]);
+          hb[(q + 1 + t) * b + tid] = yv;
+        }
+      hb[q * b + tid] = xx;
+    } else if (tid >= 64 && tid < 64 + b) {  // right-hand side
+      const int qq = tid - 64;
+      zd xx = gb[q * b + qq];
+#pragma unroll
+      for (int t = 0; t < BMX; ++t)
+        if (t < b) {
+          zd yv = gb[(q + 1 + t) * b + qq];
+          brot(xx, yv, rcs[t], rsn[t]);
+          gb[(q + 1 + t) * b + qq] = yv;
+        }
+      gb[q * b + qq] = xx;
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < 2 * b * b; i += blockDim.x) {
+    H[(size_t)(c0 + i / b) * mb + c0 + i % b] = hb[i];
+    G[(size_t)c0 * b + i] = gb[i];
   }
   if (tid == 0) flags[0] = 0;
   __syncthreads();
   if (tid < b) {
     double e2 = 0.0;
-    for (int r = (j + 1) * b; r < (j + 2) * b; ++r) {
-      const zd g = G[(size_t)r * b + tid];
+    for (int r = b; r < 2 * b; ++r) {
+      const zd g = gb[r * b + tid];
       e2 += g.re * g.re + g.im * g.im;
     }
     const double e = sqrt(e2);
@@ -404,25 +515,69 @@ __global__ __launch_bounds__(64) void k_bhess(int j, int m, int b, const zd* __r
   }
 }
 
-// Y = T^-1 G on the rotated upper triangle T of the first n column blocks
-// (one thread per rhs column); Y row-major [n b][b].
-__global__ __launch_bounds__(64) void k_bsolve(int n, int m, int b, const zd* __restrict__ H, const zd* __restrict__ G,
-                                               zd* __restrict__ Y) {
-  const int q = threadIdx.x;
-  if (q >= b) return;
+// Y = T^-1 G on the rotated upper triangle T of the first n column blocks;
+// Y row-major [n b][b].  Column-oriented back substitution: thread k holds
+// row k of the right-hand side (all b columns) in registers; once row i is
+// solved (by thread i, into LDS) every thread k < i subtracts T[k][i] Y[i].
+// Each thread streams its own row of T, BS_PF entries ahead.
+constexpr int BS_PF = 4;
+
+__global__ __launch_bounds__(1024) void k_bsolve(int n, int m, int b, const zd* __restrict__ H,
+                                                 const zd* __restrict__ G, zd* __restrict__ Y) {
+  __shared__ zd ys[2][BMX];
+  const int k = threadIdx.x;
   const size_t mb = (size_t)m * b;
   const int nb = n * b;
-  for (int i = nb - 1; i >= 0; --i) {
-    zd z = G[(size_t)i * b + q];
-    for (int k = i + 1; k < nb; ++k) {
-      const zd h = H[(size_t)i * mb + k], y = Y[(size_t)k * b + q];
-      z.re -= h.re * y.re - h.im * y.im;
-      z.im -= h.re * y.im + h.im * y.re;
-    }
-    const zd d = H[(size_t)i * mb + i];
+  zd a[BMX];
+  double rden = 0.0;
+  zd d = {0.0, 0.0};
+  if (k < nb) {
+#pragma unroll
+    for (int q = 0; q < BMX; ++q) a[q] = q < b ? G[(size_t)k * b + q] : zd{0.0, 0.0};
+    d = H[(size_t)k * mb + k];
     const double den = d.re * d.re + d.im * d.im;
-    Y[(size_t)i * b + q] = den > 0.0 ? zd{(z.re * d.re + z.im * d.im) / den, (z.im * d.re - z.re * d.im) / den}
-                                     : zd{0.0, 0.0};
+    rden = den > 0.0 ? 1.0 / den : 0.0;
+  }
+  auto fetch = [&](int g0, zd* dst) {  // T[k][g0 .. g0 + BS_PF - 1]
+#pragma unroll
+    for (int p = 0; p < BS_PF; ++p) {
+      const int i = g0 + p;
+      dst[p] = (k < i && i < nb) ? H[(size_t)k * mb + i] : zd{0.0, 0.0};
+    }
+  };
+  const int top = (nb + BS_PF - 1) / BS_PF * BS_PF;
+  zd hc[BS_PF], hn[BS_PF] = {};
+  fetch(top - BS_PF, hc);
+  for (int g0 = top - BS_PF; g0 >= 0; g0 -= BS_PF) {
+    if (g0 >= BS_PF) fetch(g0 - BS_PF, hn);
+#pragma unroll
+    for (int p = BS_PF - 1; p >= 0; --p) {
+      const int i = g0 + p;
+      if (i >= nb) continue;
+      const int buf = i & 1;
+      if (k == i) {
+#pragma unroll
+        for (int q = 0; q < BMX; ++q)
+          if (q < b) {  // a / d
+            const zd y = {(a[q].re * d.re + a[q].im * d.im) * rden, (a[q].im * d.re - a[q].re * d.im) * rden};
+            ys[buf][q] = y;
+            Y[(size_t)i * b + q] = y;
+          }
+      }
+      __syncthreads();
+      if (k < i) {
+        const zd h = hc[p];
+#pragma unroll
+        for (int q = 0; q < BMX; ++q)
+          if (q < b) {
+            const zd y = ys[buf][q];
+            a[q].re -= h.re * y.re - h.im * y.im;
+            a[q].im -= h.re * y.im + h.im * y.re;
+          }
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < BS_PF; ++p) hc[p] = hn[p];
   }
 }
 
@@ -904,7 +1059,7 @@ static int run_block_gmres(Task& t, double tol, int max_cycles, int fixed, bool 
       HIPCHK(scale_rhs(LQCD_F64, v0, nel, b, S.fin, nullptr, s));
       HIPCHK(bgram_parts(v0, 0, 1, v0, nrows, b, S.bpart, S.gblk, s));
       HIPCHK(reduce_parts(S.bpart, np, 1, (int)bb, 1.0, S.bW, s));
-      hipLaunchKernelGGL(k_bchol, dim3(1), dim3(1), 0, s, b, S.bact, S.bW, S.bR, S.bRi, bad, 1, S.fin);
+      hipLaunchKernelGGL(k_bchol, dim3(1), dim3(64), 0, s, b, S.bact, S.bW, S.bR, S.bRi, bad, 1, S.fin);
       HIPCHK(hipMemcpyAsync(&deficient, bad, sizeof(int), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
       if (deficient != 2) break;
@@ -932,8 +1087,8 @@ static int run_block_gmres(Task& t, double tol, int max_cycles, int fixed, bool 
       // thin QR of the new block: w = V_{j+1} R
       HIPCHK(bgram_parts(w, 0, 1, w, nrows, b, S.bpart, S.gblk, s));
       HIPCHK(reduce_parts(S.bpart, np, 1, (int)bb, 1.0, S.bW, s));
-      hipLaunchKernelGGL(k_bchol, dim3(1), dim3(1), 0, s, b, S.bact, S.bW, S.bR, S.bRi, bad, 0, S.fin);
-      hipLaunchKernelGGL(k_bhess, dim3(1), dim3(64), 0, s, j, m, b, S.bHc, S.bR, S.bH, S.bcs, S.bsn, S.bG, S.bact,
+      hipLaunchKernelGGL(k_bchol, dim3(1), dim3(64), 0, s, b, S.bact, S.bW, S.bR, S.bRi, bad, 0, S.fin);
+      hipLaunchKernelGGL(k_bhess, dim3(1), dim3(256), 0, s, j, m, b, S.bHc, S.bR, S.bH, S.bcs, S.bsn, S.bG, S.bact,
                          t.bref, tol, fixed, S.est, working);
       int fl[2];
       HIPCHK(hipMemcpyAsync(fl, bad, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -943,7 +1098,7 @@ static int run_block_gmres(Task& t, double tol, int max_cycles, int fixed, bool 
       if (j + 1 < m) HIPCHK(bgemm(w, nullptr, 0.0, 1.0, w, 0, 1, S.bRi, nrows, b, s));
     }
     // least squares and x += [V_0 .. V_{steps-1}] Y
-    hipLaunchKernelGGL(k_bsolve, dim3(1), dim3(64), 0, s, steps, m, b, S.bH, S.bG, S.bY);
+    hipLaunchKernelGGL(k_bsolve, dim3(1), dim3((steps * b + 63) / 64 * 64), 0, s, steps, m, b, S.bH, S.bG, S.bY);
     for (int k0 = 0; k0 < steps; k0 += BM_KB) {
       const int K = (steps - k0) < BM_KB ? (steps - k0) : BM_KB;
       HIPCHK(bgemm(t.x, t.x, 1.0, 1.0, V(k0), nel, K, S.bY + (size_t)k0 * bb, nrows, b, s));

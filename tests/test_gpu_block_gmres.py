@@ -29,7 +29,7 @@ def _solve(U, b, m0, layout=lq.LAYOUT2, x0=None, **kw):
 
 
 @pytest.mark.parametrize("eo", [False, True])
-@pytest.mark.parametrize("nrhs,k", [(1, 6), (3, 4), (5, 3), (16, 2)])
+@pytest.mark.parametrize("nrhs,k", [(1, 6), (3, 4), (5, 3), (16, 2), (3, 16), (7, 12)])
 def test_one_cycle_matches_oracle(gpu_lib, eo, nrhs, k):
     """restart = k, one cycle, tol = 0: x = argmin over the block Krylov space
     of the (Schur or full) system, compared with the oracle's block GMRES."""
@@ -49,6 +49,20 @@ def test_one_cycle_matches_oracle(gpu_lib, eo, nrhs, k):
                                     max_restarts=1)
     assert ost.steps == k
     assert np.all(rel_err_per_rhs(x, want) <= 1e-10)
+
+
+def test_one_cycle_longest_restart_matches_oracle(gpu_lib):
+    """16 rhs, restart 64 (the largest): the small least-squares problem has
+    1024 rows and the earlier rotations reach 1008 columns back."""
+    dims = (4, 4, 4, 4)
+    m0 = 0.1
+    U = syn.gauge_field(dims, "haar", config=42)
+    b = syn.spinor_block(dims, 16, config=42)
+    x, st, rc = _solve(U, b, m0, eo=False, restart=64, max_restarts=1, tol=0.0)
+    assert rc == lq.NOT_CONVERGED and np.all(st["iters"] == 64)
+    want, ost = obg.block_gmres(lambda v: dirac.apply_dw(U, v, m0), b, np.zeros(16), restart=64, max_restarts=1)
+    assert ost.steps == 64
+    assert np.all(rel_err_per_rhs(x, want) <= 1e-9)
 
 
 @pytest.mark.parametrize("eo", [False, True])
