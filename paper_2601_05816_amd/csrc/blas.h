@@ -40,15 +40,16 @@ hipError_t pack(int layout, bool to_internal, void* abi, void* ie, void* io, con
                 hipStream_t s, int abi_nrhs = 0, int col0 = 0);
 
 // Block kernels of block GMRES (bblas.hip), FP64 blocks [nrows][b], b <= 16,
-// on the FP64 matrix cores.  bgram_parts writes 4 * nblk partial sums of the
-// K Gram blocks V_k^H W (K <= BG_KB, each b x b, row-major) for
-// reduce_parts(parts, 4 * nblk, K, b * b, ...); nblk = bgram_blocks(nrows).
+// on the FP64 matrix cores.  bgram_parts writes nblk partial sums of the
+// K Gram blocks V_k^H W (K <= BG_KB, each b x b, row-major), which
+// bgram_reduce adds into out; nblk = bgram_blocks(nrows).
 // bgemm: out = alpha Y + beta sum_k V_k C_k, K <= BM_KB coefficient blocks.
 constexpr int BG_KB = 4;
 constexpr int BM_KB = 8;
 unsigned bgram_blocks(size_t nrows);
 hipError_t bgram_parts(const void* V, size_t vstride, int K, const void* W, size_t nrows, int b, void* parts,
                        unsigned nblk, hipStream_t s);
+hipError_t bgram_reduce(const void* parts, unsigned nblk, int K, int b, void* out, hipStream_t s);
 hipError_t bgemm(void* out, const void* Y, double alpha, double beta, const void* V, size_t vstride, int K,
                  const void* C, size_t nrows, int b, hipStream_t s);
 

@@ -687,7 +687,7 @@ struct Solver {
       bRi = (zd*)a.take(b * b * sizeof(zd));
       bW = (zd*)a.take(b * b * sizeof(zd));
       bY = (zd*)a.take(mb * b * sizeof(zd));
-      bpart = (zd*)a.take((size_t)4 * gblk * BG_KB * b * b * sizeof(zd));
+      bpart = (zd*)a.take((size_t)gblk * BG_KB * b * b * sizeof(zd));
       bact = (int*)a.take((b + 8) * sizeof(int));  // activity, breakdown flag, working count, start flags
     }
   }
@@ -1029,7 +1029,6 @@ static int run_block_gmres(Task& t, double tol, int max_cycles, int fixed, bool 
   hipStream_t s = S.s;
   const int b = S.nrhs, m = S.m;
   const size_t nel = S.nelem, nrows = nel / b, bb = (size_t)b * b;
-  const int np = 4 * (int)S.gblk;
   int* bad = S.bact + b;       // rank-deficiency flag of the last factorisation
   int* working = S.bact + b + 1;
   int* startf = S.bact + b + 2;  // 2 ints
@@ -1058,7 +1057,7 @@ static int run_block_gmres(Task& t, double tol, int max_cycles, int fixed, bool 
     for (int attempt = 0; attempt <= b; ++attempt) {
       HIPCHK(scale_rhs(LQCD_F64, v0, nel, b, S.fin, nullptr, s));
       HIPCHK(bgram_parts(v0, 0, 1, v0, nrows, b, S.bpart, S.gblk, s));
-      HIPCHK(reduce_parts(S.bpart, np, 1, (int)bb, 1.0, S.bW, s));
+      HIPCHK(bgram_reduce(S.bpart, S.gblk, 1, b, S.bW, s));
       hipLaunchKernelGGL(k_bchol, dim3(1), dim3(64), 0, s, b, S.bact, S.bW, S.bR, S.bRi, bad, 1, S.fin);
       HIPCHK(hipMemcpyAsync(&deficient, bad, sizeof(int), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
@@ -1078,7 +1077,7 @@ static int run_block_gmres(Task& t, double tol, int max_cycles, int fixed, bool 
       for (int k0 = 0; k0 <= j; k0 += BG_KB) {
         const int K = (j + 1 - k0) < BG_KB ? (j + 1 - k0) : BG_KB;
         HIPCHK(bgram_parts(V(k0), nel, K, w, nrows, b, S.bpart, S.gblk, s));
-        HIPCHK(reduce_parts(S.bpart, np, K, (int)bb, 1.0, S.bHc + (size_t)k0 * bb, s));
+        HIPCHK(bgram_reduce(S.bpart, S.gblk, K, b, S.bHc + (size_t)k0 * bb, s));
       }
       for (int k0 = 0; k0 <= j; k0 += BM_KB) {
         const int K = (j + 1 - k0) < BM_KB ? (j + 1 - k0) : BM_KB;
@@ -1086,7 +1085,7 @@ static int run_block_gmres(Task& t, double tol, int max_cycles, int fixed, bool 
       }
       // thin QR of the new block: w = V_{j+1} R
       HIPCHK(bgram_parts(w, 0, 1, w, nrows, b, S.bpart, S.gblk, s));
-      HIPCHK(reduce_parts(S.bpart, np, 1, (int)bb, 1.0, S.bW, s));
+      HIPCHK(bgram_reduce(S.bpart, S.gblk, 1, b, S.bW, s));
       hipLaunchKernelGGL(k_bchol, dim3(1), dim3(64), 0, s, b, S.bact, S.bW, S.bR, S.bRi, bad, 0, S.fin);
       hipLaunchKernelGGL(k_bhess, dim3(1), dim3(256), 0, s, j, m, b, S.bHc, S.bR, S.bH, S.bcs, S.bsn, S.bG, S.bact,
                          t.bref, tol, fixed, S.est, working);
