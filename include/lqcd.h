@@ -91,8 +91,11 @@ int lqcd_lattice_tables(const lqcd_lattice* lat, int32_t* nbr, int32_t* eo_site)
  * FP64, LQCD_LAYOUT2, nrhs >= 11; otherwise as 3), 6 = pencils whose
  * links reach the 16 rhs lanes of a column by row broadcasts, one load per
  * link element and row (LQCD_LAYOUT1 / LQCD_LAYOUT2, nrhs a multiple of 16,
- * any precision, full operator and odd-even hops; otherwise as 3),
- * 7 = variant 6 whose workgroups (256 / nrhs consecutive x columns, compact
+ * any precision, full operator and odd-even hops; otherwise as 3; the FP64
+ * full operator runs blocks of more than 16 rhs in chunks of 16, one chunk
+ * after another across the grid, so a time slice's working set is that of
+ * 16 rhs), 7 = variant 6 whose workgroups (256 / nrhs consecutive x columns,
+ * 16 for a chunked FP64 block, compact
  * columns for the odd-even hops) pass their streamed spinors through LDS so
  * that the inner columns read their +-x neighbours there (lattices whose x
  * extent does not hold whole workgroups run as 6),

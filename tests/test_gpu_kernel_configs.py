@@ -198,15 +198,18 @@ def test_row_broadcast_link_kernels_in_solves(gpu_lib):
 
 
 @pytest.mark.parametrize("prec", [lq.F64, lq.F32, lq.F16])
-@pytest.mark.parametrize("dims,nrhs", [((4, 4, 2, 16), 16), ((4, 2, 4, 8), 32), ((6, 4, 2, 4), 64)])
+@pytest.mark.parametrize("dims,nrhs", [((4, 4, 2, 16), 16), ((4, 2, 2, 16), 32), ((2, 2, 2, 16), 64),
+                                       ((6, 4, 2, 4), 64)])
 @pytest.mark.parametrize("pencil", [(0, 0, 0, 1), (1, 2, 2, 0), (2, 1, 4, 1)])
 def test_x_neighbours_through_lds(gpu_lib, prec, dims, nrhs, pencil):
     """Variant 7 (row-broadcast links and the +-x neighbours of the inner
     columns of a workgroup read from LDS, 256 / nrhs consecutive columns per
-    workgroup, end columns from memory): full apply D and D^dagger in both
-    rhs-fastest layouts on lattices whose x extent holds whole workgroups;
-    the odd-even apply (compact x rows of half the length) falls back to
-    variant 6 on these lattices."""
+    workgroup, end columns from memory; FP64 blocks of 32 and 64 rhs run in
+    chunks of 16, 16 columns per workgroup): full apply D and D^dagger in
+    both rhs-fastest layouts on lattices whose x extent holds whole
+    workgroups; the odd-even apply (compact x rows of half the length) and
+    the FP64 64-rhs apply on the last lattice (x = 4) fall back to
+    variant 6."""
     gpu_lib.set_kernel_config(7, pencil[0], pencil[1], pencil[2], pencil[3])
     U = rounded(syn.gauge_field(dims, "haar", config=16), prec)
     psi = rounded(syn.spinor_block(dims, nrhs, config=16), prec)
