@@ -23,10 +23,12 @@ struct batch_prob {
   unsigned long long unit0;  // first work unit (filled by wilson_batch)
   pencil_geo pg;             // pencil decomposition (pencil batch kernel; filled by wilson_batch)
   int nr;                    // rhs per work item of the pencil body (1 or 2)
+  int ncw;                   // > 0: links of a step through LDS (variant 2), NCW of that body
 };
 
 struct batch_desc {
   int n;
+  int pl;  // some unit stages its links in LDS (filled by wilson_batch)
   unsigned long long total_units;
   batch_prob p[LQCD_MAX_BATCH];
 };

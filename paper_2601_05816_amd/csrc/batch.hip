@@ -10,7 +10,9 @@
 // with the one-site body of dslash.hip, or one workgroup of the problem's
 // time-streaming pencil grid (pencil_kernels.h) with the tile, segment
 // count and store kind the autotuner recorded for that lattice, two rhs per
-// work item for FP32 / FP16 blocks with an even rhs count.  Pencil units
+// work item for FP32 / FP16 blocks with an even rhs count, or (FP32 / FP16,
+// 8 or more rhs) with the links of each step staged in LDS where the
+// autotuner chose that kernel (variant 2).  Pencil units
 // differ in length between lattices, so by default the pencil launch has one
 // workgroup per unit (the dispatcher balances them) with the longest units
 // first; a set grid size makes it persistent.  Pencil units of a problem
@@ -51,11 +53,29 @@ __global__ __launch_bounds__(256) void k_wilson_batch(batch_desc d) {
   }
 }
 
+// LDS slices of the links-through-LDS body: NCW 5 (16 or more rhs) and 9
+// (8 to 15 rhs); fewer rhs (NCW 17) would need 4 x 2 x 17 x 63 elements,
+// more than a pencil launch should reserve for every unit.
+constexpr int kBatchNcw[2] = {5, 9};
+
+template <int PREC>
+constexpr size_t batch_pl_bytes(int ncw) {
+  return (size_t)4 * 2 * ncw * 63 * sizeof(typename prec_traits<PREC>::store);
+}
+
 template <int PREC, int SG>
 __global__ __launch_bounds__(256) void k_wilson_batch_p(batch_desc d) {
   typedef typename prec_traits<PREC>::store S;
   typedef typename prec_traits<PREC>::real R;
+  // dynamic LDS: the link slices of the largest links-through-LDS unit (the
+  // launch requests them when a problem uses that body)
+  extern __shared__ __align__(16) unsigned char batch_lds[];
   for (unsigned long long u = blockIdx.x; u < d.total_units; u += gridDim.x) {
+    // the wavefronts of a workgroup leave a unit at different times, and the
+    // two links-through-LDS bodies place their per-wavefront slices at
+    // different offsets: no wavefront starts a unit before all have left the
+    // previous one
+    if (d.pl) __syncthreads();
     int k = 0;
     while (k + 1 < d.n && u >= d.p[k + 1].unit0) ++k;
     const batch_prob& pb = d.p[k];
@@ -64,6 +84,20 @@ __global__ __launch_bounds__(256) void k_wilson_batch_p(batch_desc d) {
     const S* in = (const S*)pb.in;
     S* out = (S*)pb.out;
     if (pb.parity < 0) {
+      if constexpr (PREC != LQCD_F64) {  // (FP64: registers of the other bodies would grow)
+        if (pb.ncw == kBatchNcw[0]) {
+          wilson_full_pl_body<PREC, LQCD_LAYOUT2, SG, kBatchNcw[0]>(
+              U, in, out, pb.pg, pb.nrhs, (R)pb.alpha, (R)pb.beta, b,
+              *reinterpret_cast<S(*)[4][2][kBatchNcw[0] * 63]>(batch_lds));
+          continue;
+        }
+        if (pb.ncw == kBatchNcw[1]) {
+          wilson_full_pl_body<PREC, LQCD_LAYOUT2, SG, kBatchNcw[1]>(
+              U, in, out, pb.pg, pb.nrhs, (R)pb.alpha, (R)pb.beta, b,
+              *reinterpret_cast<S(*)[4][2][kBatchNcw[1] * 63]>(batch_lds));
+          continue;
+        }
+      }
       if (PREC != LQCD_F64 && pb.nr == 2)
         wilson_full_pn_body<PREC, SG, (PREC == LQCD_F64 ? 1 : 2)>(U, in, out, pb.pg, pb.nrhs, (R)pb.alpha,
                                                                    (R)pb.beta, b);
@@ -107,15 +141,26 @@ hipError_t wilson_batch(batch_desc& din, int prec, bool dagger, hipStream_t s) {
   const bool pencil = g_batch_kind == 2 || (g_batch_kind == 0 && din.n > 0 && din.p[0].parity < 0);
   batch_desc d = din;  // the launch's copy: problems may be reordered below
   unsigned long long units = 0;
+  size_t pl_bytes = 0;  // LDS of the links-through-LDS units
   if (pencil) {
+    const size_t pl_max = 40 * 1024;
     for (int k = 0; k < d.n; ++k) {
       batch_prob& pb = d.p[k];
       lqcd_lattice lat;
       for (int i = 0; i < 4; ++i) lat.dims[i] = pb.g.n[i];
-      // tile, segments and store kind of the autotuner's entry for this lattice
+      // kernel, tile, segments and store kind of the autotuner's entry for this lattice
       const bool eo = pb.parity >= 0;
       const kcfg c = choose_cfg(eo ? KIND_EO : KIND_FULL, &lat, pb.nrhs, prec, LQCD_LAYOUT2);
-      pb.nr = (prec != LQCD_F64 && pb.nrhs % 2 == 0) ? 2 : 1;
+      pb.ncw = 0;
+      if (!eo && prec != LQCD_F64 && c.variant == 2 && pb.nrhs >= 8) {
+        const int ncw = pb.nrhs >= 16 ? kBatchNcw[0] : kBatchNcw[1];
+        const size_t need = prec == LQCD_F32 ? batch_pl_bytes<LQCD_F32>(ncw) : batch_pl_bytes<LQCD_F16>(ncw);
+        if (need <= pl_max) {
+          pb.ncw = ncw;
+          pl_bytes = std::max(pl_bytes, need);
+        }
+      }
+      pb.nr = (!pb.ncw && prec != LQCD_F64 && pb.nrhs % 2 == 0) ? 2 : 1;
       pb.pg = make_pencil(&lat, pb.nrhs / pb.nr, eo, c);
     }
     // longest units (most time steps per workgroup) first, so that the
@@ -133,6 +178,7 @@ hipError_t wilson_batch(batch_desc& din, int prec, bool dagger, hipStream_t s) {
     }
   }
   d.total_units = units;
+  d.pl = pl_bytes > 0 ? 1 : 0;
   if (units == 0) return hipSuccess;
   // pencils: one workgroup per unit unless a persistent grid is set (a
   // multiple of 8, so that every unit keeps the XCD its position assumes);
@@ -143,6 +189,7 @@ hipError_t wilson_batch(batch_desc& din, int prec, bool dagger, hipStream_t s) {
   if (grid > units) grid = (unsigned)units;
   size_t dyn = 0;  // residency cap of the pencil launch through its LDS request
   if (pencil && !occupancy_lds(g_batch_occ, 0, &dyn)) dyn = 0;
+  if (dyn < pl_bytes) dyn = pl_bytes;
 #define BL(K, P, SGN) hipLaunchKernelGGL((K<P, SGN>), dim3(grid), dim3(256), pencil ? dyn : 0, s, d)
 #define BL_ALL(K)                                         \
   switch (prec * 2 + (dagger ? 1 : 0)) {                  \

@@ -74,6 +74,46 @@ def test_batch_composition_matches_single_applies(gpu_lib):
         assert torch.all(d <= 1e-6 * torch.linalg.vector_norm(b.reshape(-1, b.shape[-1]), dim=0))
 
 
+@pytest.mark.parametrize("prec", [lq.F32, lq.F16])
+@pytest.mark.parametrize("cfg", [(2, 0, 0, 0, 0, 0), (2, 2, 2, 2, 1, 1)])
+@pytest.mark.parametrize("grid", [0, 8])
+def test_batch_links_through_lds(gpu_lib, prec, cfg, grid):
+    """Lattices whose kernel configuration is variant 2 (the links of each
+    step staged in LDS) run that body inside the persistent pencil launch
+    when they have 8 or more rhs (LDS slices for 5 or 9 columns per
+    wavefront), the others the plain pencil body: every lattice against the
+    oracle, and those with 8 or more rhs bit for bit equal to their own
+    variant-2 launch."""
+    import torch
+
+    from helpers import from_dev
+
+    gpu_lib.set_kernel_config(*cfg)
+    gpu_lib.set_batch_kernel(2)
+    gpu_lib.set_batch_grid(grid)
+    cases = [((4, 4, 4, 4), 8, 0.1), ((8, 4, 4, 4), 12, -0.05), ((4, 4, 2, 8), 16, 0.3), ((2, 2, 2, 2), 5, 0.0),
+             ((6, 4, 4, 2), 20, -0.2)]
+    try:
+        probs, wants = [], []
+        for k, (dims, n, m0) in enumerate(cases):
+            U = rounded(syn.gauge_field(dims, "near_identity", config=90 + k, eps=0.3), prec)
+            psi = rounded(syn.spinor_block(dims, n, config=90 + k), prec)
+            probs.append((to_dev(U, prec), to_dev(_l2(psi), prec), m0))
+            wants.append(dirac.apply_dw(U, psi, m0))
+        outs = lq.dirac_apply_batch(probs)
+        singles = [lq.dirac_apply(U, psi, m0) for U, psi, m0 in probs]
+        torch.cuda.synchronize()
+    finally:
+        gpu_lib.set_batch_grid(0)
+        gpu_lib.set_batch_kernel(0)
+        gpu_lib.set_kernel_config(0)
+    for out, single, want, (dims, n, m0) in zip(outs, singles, wants, cases):
+        if n >= 8:  # the same body as the lattice's own launch
+            assert torch.equal(out, single), (dims, n)
+        got = np.moveaxis(from_dev(out, prec), -1, 0)
+        assert np.all(rel_err_per_rhs(got, want) <= TOL[prec])
+
+
 @pytest.mark.parametrize("kind", [1, 2])
 def test_batch_composition_matches_oracle(gpu_lib, kind):
     """The eight-lattice composition (L = 8..24, T = 2L, 1..32 rhs, FP32) in
