@@ -14,7 +14,7 @@ multi-lattice batch, differentiation, small lattices) and the oracle's CPU
 throughput on a sample of the same apply (two of the 16 rhs).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-sweep] [--no-cpu] [--no-counters]
-    python bench.py --only {apply,sweep-f64,schur-f64,schur-sizes,clover-f64,gmres-fixed,block-fixed,block-hard,
+    python bench.py --only {apply,sweep-f64,schur-f64,schur-sizes,clover-f64,gmres-fixed,block-fixed,block-hard,gmres-sweep,
                             gmres-ir}
                     [--prec f64|f32|f16] [--kind full|schur] [--nrhs N] [--calibrate]
                                     (one workload, for profilers)
@@ -167,14 +167,16 @@ def measure_traffic(steps=3):
 
 def solve_times(lq, U64, b, mode, reps, warm, work, **kw):
     """Wall-clock seconds of `reps` solves after `warm` warm-up solves (all to
-    the same tolerance, same workspace); returns (times, x, stats, status)."""
+    the same tolerance, same workspace and solution buffer, both allocated
+    before the timed region); returns (times, x, stats, status)."""
     import torch
 
-    times, x, st, rc = [], None, None, None
+    times, st, rc = [], None, None
+    x = torch.empty_like(b)  # allocated outside the timed solves
     for i in range(warm + reps):
         torch.cuda.synchronize()
         t = time.time()
-        x, st, rc = lq.gmres_solve(U64, b, M0, layout=lq.LAYOUT2, work=work, mode=mode, **kw)
+        x, st, rc = lq.gmres_solve(U64, b, M0, layout=lq.LAYOUT2, work=work, mode=mode, out=x, **kw)
         torch.cuda.synchronize()
         if i >= warm:
             times.append(time.time() - t)
@@ -580,8 +582,8 @@ def autograd_section(lq, syn):
 
 def profile_only(args):
     """One workload under a profiler: GPU-drawn inputs (timing does not depend
-    on the values; gmres-ir solves on the benchmark's near-identity links,
-    whose iteration counts it reproduces), the kernel configurations of the
+    on the values; gmres-ir and gmres-sweep solve on the benchmark's
+    near-identity links, whose iteration counts they reproduce), the kernel configurations of the
     tune file, `--steps` launches after `--warmup`; prints one JSON line of
     launch times."""
     import torch
@@ -736,21 +738,34 @@ def profile_only(args):
 
         U = torch.from_numpy(syn.gauge_field(DIMS, "near_identity", config=CONFIG, eps=EPS)).to(dev)
         b = torch.randn(DIMS + (4, 3, args.nrhs), dtype=torch.complex128, device=dev, generator=g)
+        x = torch.empty_like(b)
         for mode in ("ir-f16", "ir-f32"):
             kw = dict(restart=30, eo=True, mode=mode, tol=1e-10, max_restarts=400, max_outer=60)
+            # the full width if its workspace fits the free memory, else the library's chunk width
+            p = lq.solver_params(**kw)
+            free, _ = torch.cuda.mem_get_info()
+            nbytes = min(lq.gmres_workspace_bytes(DIMS, args.nrhs, p), free - (8 << 30))
+            kw["rhs_block"] = lq.gmres_rhs_block(DIMS, args.nrhs, p, nbytes)
             work = torch.empty(lq.gmres_workspace_bytes(DIMS, args.nrhs, lq.solver_params(**kw)), dtype=torch.uint8,
                                device=dev)
             out[mode] = []
             for i in range(args.warmup + args.steps):
                 torch.cuda.synchronize()
                 t = time.time()
-                _, st, rc = lq.gmres_solve(U, b, M0, layout=lq.LAYOUT2, work=work, **kw)
+                _, st, rc = lq.gmres_solve(U, b, M0, layout=lq.LAYOUT2, work=work, out=x, **kw)
                 torch.cuda.synchronize()
                 out[mode].append(round(time.time() - t, 3))
                 log(f"{mode} to 1e-10 ({'warmup' if i < args.warmup else 'timed'}): {out[mode][-1]} s, "
-                    f"{int(st['iters'].max())} steps, status {rc}")
+                    f"{int(st['iters'].max())} steps, status {rc}, rhs_block {kw['rhs_block']}")
             del work
             torch.cuda.empty_cache()
+    elif args.only == "gmres-sweep":  # the GMRES nrhs sweep of the full run, on the benchmark's links and rhs
+        import lqcd_synth as syn
+
+        U = torch.from_numpy(syn.gauge_field(DIMS, "near_identity", config=CONFIG, eps=EPS)).to(dev)
+        psi = syn.spinor_block(DIMS, NRHS, config=CONFIG)
+        psi = torch.from_numpy(np.ascontiguousarray(np.moveaxis(psi, 0, -1))).to(dev)
+        out["points"] = gmres_nrhs_sweep(lq, U, psi)
     else:  # the paper's fixed protocol: 100 iterations = 10 restarts of 10, odd-even, FP64
         U.mul_(0.3)
         b = torch.randn(DIMS + (4, 3, NRHS), dtype=torch.complex128, device=dev, generator=g)
@@ -798,7 +813,7 @@ def main():
     ap.add_argument("--retune", action="store_true", help="ignore the tune file and autotune every apply")
     ap.add_argument("--save-tune", default="", help="write the autotuner's table here at the end")
     ap.add_argument("--only", choices=["apply", "sweep-f64", "schur-f64", "schur-sizes", "clover-f64", "gmres-fixed",
-                                       "block-fixed", "block-hard", "gmres-ir"],
+                                       "block-fixed", "block-hard", "gmres-ir", "gmres-sweep"],
                     default="",
                     help="profiling mode: run one workload only (GPU-drawn inputs except the near-identity links of "
                          "gmres-ir, tune file), print its times")

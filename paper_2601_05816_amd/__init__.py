@@ -438,12 +438,13 @@ def gmres_rhs_block(dims, nrhs, params, work_bytes):
                                          ctypes.c_size_t(int(work_bytes))))
 
 
-def gmres_solve(U, b, m0, layout=LAYOUT2, x0=None, work=None, **kw):
+def gmres_solve(U, b, m0, layout=LAYOUT2, x0=None, work=None, out=None, **kw):
     """x = D^-1 b per rhs with batched GMRES (FP64 U and b, full lattice).
 
     Keyword arguments are those of solver_params; x0 (same shape as b) is the
-    initial guess.  Returns (x, stats, status) with stats a dict of per-rhs
-    numpy arrays and status OK or NOT_CONVERGED."""
+    initial guess; out (same shape and type as b) receives x (else a new
+    tensor).  Returns (x, stats, status) with stats a dict of per-rhs numpy
+    arrays and status OK or NOT_CONVERGED."""
     import torch
 
     if U.dtype != torch.complex128 or b.dtype != torch.complex128:
@@ -453,7 +454,12 @@ def gmres_solve(U, b, m0, layout=LAYOUT2, x0=None, work=None, **kw):
     if tuple(sdims) != tuple(dims):
         raise ValueError(f"source lattice {sdims} does not match gauge lattice {dims}")
     p = solver_params(x_is_guess=x0 is not None, **kw)
-    x = x0.clone() if x0 is not None else torch.empty_like(b)
+    if out is not None:
+        if out.shape != b.shape or out.dtype != b.dtype or not out.is_contiguous():
+            raise ValueError("out must be a contiguous tensor of b's shape and type")
+        x = out.copy_(x0) if x0 is not None else out
+    else:
+        x = x0.clone() if x0 is not None else torch.empty_like(b)
     if work is None:
         work = torch.empty(gmres_workspace_bytes(dims, nrhs, p), dtype=torch.uint8, device=b.device)
     _check_device(U, b, x, work)

@@ -206,13 +206,18 @@ __global__ __launch_bounds__(256) void k_cgs_update_v(const typename vio<P>::sto
   if (none_live(live, nrhs)) return;
   extern __shared__ char lds_raw[];
   cx<double>* hs = reinterpret_cast<cx<double>*>(lds_raw);
-  if (LH) {
-    for (int i = threadIdx.x; i < K * nrhs; i += blockDim.x) hs[i] = h[i];
-    __syncthreads();
-  }
   constexpr int VW = vio<P>::VW;
   typedef typename vio<P>::acc_t A;
   const int G = nrhs / VW;
+  if (LH) {
+    // [k][v][group]: the lanes of a wavefront read G consecutive entries for
+    // one (k, v), not G entries VW apart (fewer LDS bank conflicts)
+    for (int i = threadIdx.x; i < K * nrhs; i += blockDim.x) {
+      const int k = i / nrhs, r = i - k * nrhs;
+      hs[((size_t)k * VW + r % VW) * G + r / VW] = h[i];
+    }
+    __syncthreads();
+  }
   vsched s = vgrid(G);
   A re[1][VW], im[1][VW];
 #pragma unroll
@@ -240,8 +245,8 @@ __global__ __launch_bounds__(256) void k_cgs_update_v(const typename vio<P>::sto
         for (int q = 0; q < 4; ++q)
 #pragma unroll
           for (int v = 0; v < VW; ++v) {
-            const int hi = (k + q) * nrhs + s.gr * VW + v;
-            x[v] = cmadd(x[v], -(LH ? hs[hi] : h[hi]), ve[q][v]);
+            const cx<double> c = LH ? hs[((k + q) * VW + v) * G + s.gr] : h[(k + q) * nrhs + s.gr * VW + v];
+            x[v] = cmadd(x[v], -c, ve[q][v]);
           }
       }
       for (; k < K; ++k) {
@@ -249,8 +254,8 @@ __global__ __launch_bounds__(256) void k_cgs_update_v(const typename vio<P>::sto
         vio<P>::load(V + (size_t)k * vstride + e, ve);
 #pragma unroll
         for (int v = 0; v < VW; ++v) {
-          const int hi = k * nrhs + s.gr * VW + v;
-          x[v] = cmadd(x[v], -(LH ? hs[hi] : h[hi]), ve[v]);
+          const cx<double> c = LH ? hs[(k * VW + v) * G + s.gr] : h[k * nrhs + s.gr * VW + v];
+          x[v] = cmadd(x[v], -c, ve[v]);
         }
       }
       vio<P>::save(w + e, x);

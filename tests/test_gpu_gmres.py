@@ -253,3 +253,27 @@ def test_rhs_chunked_solves(gpu_lib, layout):
     assert lq.gmres_rhs_block(dims, 6, p0, work.numel()) == 2
     xw, sw, rc = _solve(U, b, m0, layout=layout, work=work, eo=True, tol=1e-10)
     assert rc == lq.OK and np.all(_true_relres(U, b, xw, m0) <= 1e-10)
+
+
+def test_solution_buffer(gpu_lib):
+    """out= receives x (the same tensor comes back), with and without an
+    initial guess copied into it; the results equal those of a new tensor
+    and of x0= alone bit for bit; a buffer of the wrong shape is rejected."""
+    import torch
+
+    dims = (8, 4, 4, 4)
+    m0 = -0.05
+    U = torch.from_numpy(syn.gauge_field(dims, "near_identity", config=5, eps=0.3)).to("cuda")
+    b = torch.from_numpy(to_layout_np(syn.spinor_block(dims, 3, config=5), lq.LAYOUT2)).to("cuda")
+    kw = dict(restart=10, eo=True, tol=1e-10)
+    x_new, _, rc = lq.gmres_solve(U, b, m0, **kw)
+    out = torch.full_like(b, float("nan"))
+    x_out, _, rc2 = lq.gmres_solve(U, b, m0, out=out, **kw)
+    assert rc == rc2 == lq.OK and x_out is out and torch.equal(x_out, x_new)
+    x0 = 0.5 * x_new
+    x_g, _, _ = lq.gmres_solve(U, b, m0, x0=x0, **kw)
+    out2 = torch.empty_like(b)
+    x_g2, _, _ = lq.gmres_solve(U, b, m0, x0=x0, out=out2, **kw)
+    assert x_g2 is out2 and torch.equal(x_g2, x_g) and torch.equal(x0, 0.5 * x_new)
+    with pytest.raises(ValueError):
+        lq.gmres_solve(U, b, m0, out=torch.empty_like(b[..., :2]), **kw)
