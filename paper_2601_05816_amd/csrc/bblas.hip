@@ -208,11 +208,14 @@ hipError_t bgram_parts(const void* V, size_t vstride, int K, const void* W, size
     case 2:
       hipLaunchKernelGGL((k_bgram<2, false>), dim3(nblk), dim3(256), 0, s, Vz, vstride, Wz, nrows, b, rpb, P);
       break;
-    case 3:
-      hipLaunchKernelGGL((k_bgram<3, false>), dim3(nblk), dim3(256), 0, s, Vz, vstride, Wz, nrows, b, rpb, P);
-      break;
+#define LQ_BGRAM_CASE(KK)                                                                                  \
+  case KK:                                                                                                 \
+    hipLaunchKernelGGL((k_bgram<KK, false>), dim3(nblk), dim3(256), 0, s, Vz, vstride, Wz, nrows, b, rpb, P); \
+    break;
+    LQ_BGRAM_CASE(3) LQ_BGRAM_CASE(4) LQ_BGRAM_CASE(5) LQ_BGRAM_CASE(6) LQ_BGRAM_CASE(7)
+#undef LQ_BGRAM_CASE
     default:
-      hipLaunchKernelGGL((k_bgram<4, false>), dim3(nblk), dim3(256), 0, s, Vz, vstride, Wz, nrows, b, rpb, P);
+      hipLaunchKernelGGL((k_bgram<8, false>), dim3(nblk), dim3(256), 0, s, Vz, vstride, Wz, nrows, b, rpb, P);
       break;
   }
   return hipGetLastError();

@@ -44,7 +44,7 @@ hipError_t pack(int layout, bool to_internal, void* abi, void* ie, void* io, con
 // K Gram blocks V_k^H W (K <= BG_KB, each b x b, row-major), which
 // bgram_reduce adds into out; nblk = bgram_blocks(nrows).
 // bgemm: out = alpha Y + beta sum_k V_k C_k, K <= BM_KB coefficient blocks.
-constexpr int BG_KB = 4;
+constexpr int BG_KB = 8;
 constexpr int BM_KB = 8;
 unsigned bgram_blocks(size_t nrows);
 hipError_t bgram_parts(const void* V, size_t vstride, int K, const void* W, size_t nrows, int b, void* parts,
