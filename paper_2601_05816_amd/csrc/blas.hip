@@ -204,9 +204,19 @@ __global__ __launch_bounds__(256) void k_cgs_update_c(const store_t<P>* __restri
       const size_t e = e0 + (size_t)i * sb;
       if (e >= nelem) break;
       cx<double> v = ldd<P>(w + e);
-      // four basis vectors per round: their loads are issued together (the
+      // eight basis vectors per round: their loads are issued together (the
       // terms are still added in the order k = 0, 1, ..., K-1)
       int k = 0;
+      for (; k + 8 <= K; k += 8) {
+        cx<double> a[8], c[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          a[q] = ldd<P>(V + (size_t)(k + q) * vstride + e);
+          c[q] = LH ? hs[(k + q) * nrhs + rhs] : h[(size_t)(k + q) * nrhs + rhs];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v = cmadd(v, -c[q], a[q]);
+      }
       for (; k + 4 <= K; k += 4) {
         cx<double> a[4], c[4];
 #pragma unroll
