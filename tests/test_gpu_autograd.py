@@ -80,13 +80,67 @@ def test_apply_gradients_vs_oracle_and_gradcheck(gpu_lib):
     assert torch.autograd.gradcheck(lambda u, p: wilson_apply(u, p, 0.3), (Us, ps), eps=1e-6, atol=1e-7)
 
 
-def _dense_loss(U, eta, chi, m0, dagger=False):
-    D = dirac.dense(U, m0)
-    if dagger:
-        D = D.conj().T
-    n = eta.shape[0]
-    x = np.linalg.solve(D, eta.reshape(n, -1).T).T.reshape(eta.shape)
-    return float(np.real(np.vdot(chi, x)))
+class _DenseLoss:
+    """L = Re <chi, A^-1 eta> with A = D_W(U, m0) or its adjoint, from the
+    oracle's dense matrix, for central differences.  One LU of A serves all
+    evaluations: a perturbed link entry U_mu(x)[a][b] changes only the
+    columns of D at x and at its neighbours along mu, so the perturbed A is
+    A plus a low-rank term and is solved exactly with the Woodbury identity
+    (checked on a random vector that no other column changed); a perturbed
+    mass is A + dm I, factorised afresh."""
+
+    def __init__(self, U, eta, chi, m0, dagger):
+        import scipy.linalg as sla
+
+        self.sla, self.U, self.m0, self.dagger = sla, U, m0, dagger
+        self.dims = U.shape[1:5]
+        n = eta.shape[0]
+        D = dirac.dense(U, m0)
+        self.A = D.conj().T.copy() if dagger else D
+        self.lu = sla.lu_factor(self.A)
+        self.B = eta.reshape(n, -1).T
+        self.chi = chi.reshape(n, -1).T
+        self.Y = sla.lu_solve(self.lu, self.B)
+
+    def _loss(self, X):
+        return float(np.real(np.vdot(self.chi, X)))
+
+    def mass(self, dm):
+        n = self.A.shape[0]
+        return self._loss(self.sla.lu_solve(self.sla.lu_factor(self.A + dm * np.eye(n)), self.B))
+
+    def link(self, k, delta):
+        """L with U.flat[k] += delta."""
+        sla, dims, n = self.sla, self.dims, self.A.shape[0]
+        mu, t, z, y, x, _, _ = np.unravel_index(k, self.U.shape)
+        sites = set()
+        for step in (0, 1, -1):
+            c = [t, z, y, x]
+            c[mu] = (c[mu] + step) % dims[mu]
+            sites.add(int(np.ravel_multi_index(tuple(c), dims)))
+        cols = np.array(sorted(12 * st + j for st in sites for j in range(12)))
+        m = len(cols)
+        Up = self.U.copy()
+        Up.reshape(-1)[k] += delta
+        E = np.zeros((m, n), dtype=np.complex128)
+        E[np.arange(m), cols] = 1.0
+        E = E.reshape((m,) + tuple(dims) + (4, 3))
+        dC = (dirac.apply_dw(Up, E, self.m0) - dirac.apply_dw(self.U, E, self.m0)).reshape(m, n).T
+        v = np.random.default_rng(k).standard_normal(n) + 0j
+        vb = v.reshape((1,) + tuple(dims) + (4, 3))
+        dv = (dirac.apply_dw(Up, vb, self.m0) - dirac.apply_dw(self.U, vb, self.m0)).reshape(n)
+        assert np.allclose(dv, dC @ v[cols], rtol=0, atol=1e-13 * max(1.0, np.abs(dv).max()))
+        Y = self.Y
+        if self.dagger:  # A' = A + E_C dC^H
+            P = np.zeros((n, m), dtype=np.complex128)
+            P[cols, np.arange(m)] = 1.0
+            Z = sla.lu_solve(self.lu, P)
+            QH = dC.conj().T
+            X = Y - Z @ np.linalg.solve(np.eye(m) + QH @ Z, QH @ Y)
+        else:  # A' = A + dC E_C^T
+            Z = sla.lu_solve(self.lu, dC)
+            X = Y - Z @ np.linalg.solve(np.eye(m) + Z[cols], Y[cols])
+        return self._loss(X)
 
 
 @pytest.mark.parametrize("dagger", [False, True])
@@ -111,22 +165,16 @@ def test_solve_gradients_fd_4x4x4x4(gpu_lib, dagger):
     gU = Ut.grad.cpu().numpy()
     h = 1e-6
     rng = np.random.default_rng(3)
-    flat = U.reshape(-1)
-    for k in rng.choice(flat.size, size=8, replace=False):
+    L = _DenseLoss(U, eta, chi, m0, dagger)
+    for k in rng.choice(U.size, size=8, replace=False):
         for unit in (1.0, 1j):
-            up = flat.copy(); up[k] += h * unit
-            um = flat.copy(); um[k] -= h * unit
-            fd = (_dense_loss(up.reshape(U.shape), eta, chi, m0, dagger)
-                  - _dense_loss(um.reshape(U.shape), eta, chi, m0, dagger)) / (2 * h)
+            fd = (L.link(k, h * unit) - L.link(k, -h * unit)) / (2 * h)
             an = gU.reshape(-1)[k].real if unit == 1.0 else gU.reshape(-1)[k].imag
             assert abs(fd - an) < 1e-6 * max(1.0, abs(an)), (k, unit, fd, an)
-    fd = (_dense_loss(U, eta, chi, m0 + h, dagger) - _dense_loss(U, eta, chi, m0 - h, dagger)) / (2 * h)
+    fd = (L.mass(h) - L.mass(-h)) / (2 * h)
     assert abs(fd - float(mt.grad)) < 1e-6 * max(1.0, abs(fd))
     # grad_eta = lambda = A^-dagger chi
-    A = dirac.dense(U, m0)
-    if dagger:
-        A = A.conj().T
-    lam = np.linalg.solve(A.conj().T, chi.reshape(2, -1).T).T.reshape(chi.shape)
+    lam = np.linalg.solve(L.A.conj().T, chi.reshape(2, -1).T).T.reshape(chi.shape)
     assert np.all(rel_err_per_rhs(_from_l2(et.grad), lam) < 1e-10)
 
 
