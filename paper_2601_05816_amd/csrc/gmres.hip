@@ -342,23 +342,7 @@ __device__ __forceinline__ void brot(zd& x, zd& y, double c, zd s) {
   y = ny;
 }
 
-// Step j of the block Arnoldi process on the small matrices: enter column
-// block j of the block Hessenberg matrix (the Gram blocks H_ij, i <= j, and
-// the triangular factor R of the new block below them), apply the earlier
-// rotations, zero its b subdiagonals with b rotations per column, rotate the
-// right-hand side and read the per-rhs residual estimates off the last b
-// rows.  flags[0] counts the active columns that are still above tolerance.
-//
-// Layout of the work: lane q of the first wavefront owns column c0 + q and
-// carries the b + 1 rows an earlier rotation step cp touches (rows cp ..
-// cp + b) in registers, so the cp-loop is a register chain; the other
-// wavefronts stage the rotations and the incoming rows of the next
-// BH_CH steps in LDS meanwhile.  The new rotations of the 2b x b diagonal
-// block are formed in parallel: the rotation that zeroes subdiagonal entry t
-// of a column leaves the pivot with the norm r_t of the pivot and entries
-// 0..t, so cosine r_{t-1} / r_t and sine u conj(y_t) / r_t (u the pivot's
-// phase) follow from running sums of |y|^2.
-constexpr int BH_CH = 32;
+constexpr int BH_CH = 32;  // earlier rotation steps staged in LDS per chunk
 
 // n earlier rotation steps applied to one column of the incoming block:
 // x = row cp, w[t] = row cp + 1 + t (t < B) in registers; row cp is final
@@ -378,7 +362,22 @@ __device__ __forceinline__ void bhess_rows(zd& x, zd (&w)[BMX], const double* lc
   }
 }
 
-
+// Step j of the block Arnoldi process on the small matrices: enter column
+// block j of the block Hessenberg matrix (the Gram blocks H_ij, i <= j, and
+// the triangular factor R of the new block below them), apply the earlier
+// rotations, zero its b subdiagonals with b rotations per column, rotate the
+// right-hand side and read the per-rhs residual estimates off the last b
+// rows.  flags[0] counts the active columns that are still above tolerance.
+//
+// Layout of the work: lane q of the first wavefront owns column c0 + q and
+// carries the b + 1 rows an earlier rotation step cp touches (rows cp ..
+// cp + b) in registers, so the cp-loop is a register chain; the other
+// wavefronts stage the rotations and the incoming rows of the next
+// BH_CH steps in LDS meanwhile.  The new rotations of the 2b x b diagonal
+// block are formed in parallel: the rotation that zeroes subdiagonal entry t
+// of a column leaves the pivot with the norm r_t of the pivot and entries
+// 0..t, so cosine r_{t-1} / r_t and sine u conj(y_t) / r_t (u the pivot's
+// phase) follow from running sums of |y|^2.
 __global__ __launch_bounds__(256) void k_bhess(int j, int m, int b, const zd* __restrict__ Hc,
                                                const zd* __restrict__ R, zd* __restrict__ H, double* __restrict__ cs,
                                                zd* __restrict__ sn, zd* __restrict__ G, const int* __restrict__ act,
